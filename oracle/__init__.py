@@ -1,0 +1,271 @@
+"""FP64 CPU oracle for backward null-geodesic ray tracing (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares
+no code with the GPU library (``paper_2111_08744_amd``) and neither imports
+the other.
+
+The C library (``oracle/liboracle.so``, built by ``oracle/build.py``) follows
+the paper (Breton & Reverdy, Magrathea-Pathfinder):
+  * Sect. 2.2: null geodesic equations of the perturbed FLRW metric in
+    Newtonian gauge, dPhi/dlambda by the chain rule with dPhi/deta = 0, RK4
+    with N steps per AMR cell, photons started at the observer with k0 = -1
+    (backward) and the null condition, NGP/CIC/TSC weights (CIC here) with the
+    five-step AMR level-fallback procedure;
+  * Sect. 2.3: lens equation, distortion matrix by the infinitesimal beam
+    (line-of-sight integral of the transverse Hessian, force finite
+    differences) and by the finite beam (four rays, Eq. for A-hat);
+  * Sect. 2.4: HEALPix pixel centres as initial directions;
+  * Sect. 2.5: redshifts z0, z1, z5 (v = 0).
+Derivatives are exact complex-step derivatives of the same discrete map.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+REACHED, LEFT_DOMAIN, MAX_STEPS, NONFINITE = 0, 1, 2, 3
+FIELD_GRID, FIELD_LINEAR, FIELD_QUADRATIC, FIELD_POINT = 0, 1, 2, 3
+STOP_REDSHIFT, STOP_CHI = 0, 1
+
+RAY_DTYPE = np.dtype([
+    ("theta", "f8", 2), ("beta", "f8", 2), ("alpha", "f8", 2), ("sep2", "f8"),
+    ("z5", "f8"), ("z0", "f8"), ("z1", "f8"), ("phi_o", "f8"), ("phi_s", "f8"),
+    ("chi", "f8"), ("r", "f8", 3), ("k", "f8", 4), ("eta", "f8"), ("max_null", "f8"),
+    ("n_steps", "i8"), ("status", "i4"), ("hash", "u4"),
+], align=True)
+
+TAN_DTYPE = np.dtype([
+    ("r", "f8", 3), ("k", "f8", 4), ("z5", "f8"), ("phi_s", "f8"), ("alpha", "f8", 2),
+    ("sep2", "f8"), ("eta", "f8"),
+], align=True)
+
+
+class Cosmo(C.Structure):
+    _fields_ = [("omega_m", C.c_double), ("omega_l", C.c_double), ("h", C.c_double)]
+
+
+class CastParams(C.Structure):
+    _fields_ = [("obs", C.c_double * 3), ("stop_kind", C.c_int), ("stop_value", C.c_double),
+                ("steps_per_cell", C.c_int), ("adaptive", C.c_int), ("ds_analytic", C.c_double),
+                ("max_steps", C.c_int64)]
+
+
+def cosmo(omega_m=0.3, omega_l=0.7, h=0.7) -> Cosmo:
+    return Cosmo(omega_m, omega_l, h)
+
+
+STATIC = Cosmo(0.0, 0.0, 1.0)
+
+
+def params(obs, z_src=None, chi=None, steps_per_cell=10, adaptive=False, ds=0.0,
+           max_steps=1 << 40) -> CastParams:
+    p = CastParams()
+    for i in range(3):
+        p.obs[i] = float(obs[i])
+    if (z_src is None) == (chi is None):
+        raise ValueError("give exactly one of z_src, chi")
+    p.stop_kind = STOP_REDSHIFT if z_src is not None else STOP_CHI
+    p.stop_value = float(z_src if z_src is not None else chi)
+    p.steps_per_cell = int(steps_per_cell)
+    p.adaptive = int(bool(adaptive))
+    p.ds_analytic = float(ds)
+    p.max_steps = int(max_steps)
+    return p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"oracle library missing: {_LIB_PATH} (run oracle/build.py)")
+        L = C.CDLL(_LIB_PATH)
+        vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+        L.or_field_grid.restype = vp
+        L.or_field_grid.argtypes = [C.c_double, C.c_int, C.c_int, C.c_int, i64, vp, vp, vp, vp, C.c_char_p, C.c_int]
+        L.or_field_analytic.restype = vp
+        L.or_field_analytic.argtypes = [C.c_int, dp]
+        L.or_field_free.argtypes = [vp]
+        L.or_field_probe.restype = C.c_int
+        L.or_field_probe.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        for name in ("or_eta_of_a", "or_a_of_eta", "or_conformal_hubble"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.POINTER(Cosmo), C.c_double]
+        L.or_eta0.restype = C.c_double
+        L.or_eta0.argtypes = [C.POINTER(Cosmo)]
+        L.or_cosmo_check.restype = C.c_int
+        L.or_cosmo_check.argtypes = [C.POINTER(Cosmo)]
+        L.or_pix2vec_nest.argtypes = [i64, i64, dp]
+        L.or_cast.restype = C.c_int
+        L.or_cast.argtypes = [vp, C.POINTER(Cosmo), C.POINTER(CastParams), i64, vp, vp, C.c_int]
+        L.or_cast_cs.restype = C.c_int
+        L.or_cast_cs.argtypes = [vp, C.POINTER(Cosmo), C.POINTER(CastParams), i64, vp, vp, vp, vp, vp, vp, C.c_int]
+        L.or_infinitesimal.restype = C.c_int
+        L.or_infinitesimal.argtypes = [vp, C.POINTER(Cosmo), C.POINTER(CastParams), i64, vp, C.c_double, vp, vp, C.c_int]
+        L.or_integrate_steps.restype = C.c_int
+        L.or_integrate_steps.argtypes = [vp, C.POINTER(Cosmo), dp, i64, vp]
+        _lib = L
+    return _lib
+
+
+def default_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = int(env) if env and env.isdigit() else (os.cpu_count() or 1)
+    return max(1, min(n, 64))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class Field:
+    """A potential field: an octree of cells or a closed form."""
+
+    def __init__(self, handle, keep=()):
+        self._h = handle
+        self._keep = keep
+
+    @classmethod
+    def grid(cls, cells) -> "Field":
+        level = np.ascontiguousarray(cells.level, np.uint8)
+        ijk = np.ascontiguousarray(cells.ijk, np.int32)
+        phi = np.ascontiguousarray(cells.phi, np.float64)
+        grad = np.ascontiguousarray(cells.grad, np.float64)
+        err = C.create_string_buffer(256)
+        h = lib().or_field_grid(float(cells.box), int(cells.n0), int(cells.max_level),
+                                int(bool(cells.periodic)), len(level), _ptr(level), _ptr(ijk),
+                                _ptr(phi), _ptr(grad), err, 256)
+        if not h:
+            raise ValueError("oracle rejected the grid: " + err.value.decode())
+        return cls(h)
+
+    @classmethod
+    def analytic(cls, kind: int, par) -> "Field":
+        par = np.ascontiguousarray(par, np.float64)
+        h = lib().or_field_analytic(kind, par.ctypes.data_as(C.POINTER(C.c_double)))
+        if not h:
+            raise ValueError("bad field kind")
+        return cls(h)
+
+    @classmethod
+    def linear(cls, g, phi0=0.0):
+        return cls.analytic(FIELD_LINEAR, [phi0, *g])
+
+    @classmethod
+    def quadratic(cls, H, centre, phi0=0.0):
+        H = np.asarray(H, float)
+        return cls.analytic(FIELD_QUADRATIC, [phi0, *centre, H[0, 0], H[0, 1], H[0, 2], H[1, 1], H[1, 2], H[2, 2]])
+
+    @classmethod
+    def point(cls, m, centre, soft=0.0):
+        return cls.analytic(FIELD_POINT, [m, *centre, soft])
+
+    def probe(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        phi = C.c_double()
+        g = (C.c_double * 3)()
+        leaf, lvl = C.c_int(), C.c_int()
+        st = lib().or_field_probe(self._h, x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(phi), g,
+                                  C.byref(leaf), C.byref(lvl))
+        return st, phi.value, np.array(g[:]), leaf.value, lvl.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.or_field_free(self._h)
+            self._h = None
+
+
+def eta_of_a(c: Cosmo, a: float) -> float:
+    return lib().or_eta_of_a(C.byref(c), a)
+
+
+def a_of_eta(c: Cosmo, eta: float) -> float:
+    return lib().or_a_of_eta(C.byref(c), eta)
+
+
+def conformal_hubble(c: Cosmo, eta: float) -> float:
+    return lib().or_conformal_hubble(C.byref(c), eta)
+
+
+def eta0(c: Cosmo) -> float:
+    return lib().or_eta0(C.byref(c))
+
+
+def chi_of_z(c: Cosmo, z: float) -> float:
+    return eta0(c) - eta_of_a(c, 1.0 / (1.0 + z))
+
+
+def pix2vec_nest(nside: int, pix) -> np.ndarray:
+    pix = np.atleast_1d(np.asarray(pix, np.int64))
+    out = np.empty((len(pix), 3))
+    v = (C.c_double * 3)()
+    L = lib()
+    for i, p in enumerate(pix):
+        L.or_pix2vec_nest(int(nside), int(p), v)
+        out[i] = v[:]
+    return out
+
+
+def cast(field: Field, c: Cosmo, p: CastParams, dirs, threads: int | None = None) -> np.ndarray:
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    out = np.zeros(len(dirs), RAY_DTYPE)
+    rc = lib().or_cast(field._h, C.byref(c), C.byref(p), len(dirs), _ptr(dirs), _ptr(out),
+                       threads or default_threads())
+    if rc:
+        raise ValueError("or_cast rejected its arguments")
+    return out
+
+
+def cast_cs(field: Field, c: Cosmo, p: CastParams, dirs, dtheta=None, dphi=None, dgrad=None,
+            threads: int | None = None):
+    """Values and exact directional derivatives (complex step) of the outputs."""
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    n = len(dirs)
+    out = np.zeros(n, RAY_DTYPE)
+    tan = np.zeros(n, TAN_DTYPE)
+    dth = None if dtheta is None else np.ascontiguousarray(np.broadcast_to(dtheta, (n, 2)), np.float64)
+    dph = None if dphi is None else np.ascontiguousarray(dphi, np.float64)
+    dgr = None if dgrad is None else np.ascontiguousarray(dgrad, np.float64)
+    rc = lib().or_cast_cs(field._h, C.byref(c), C.byref(p), n, _ptr(dirs), _ptr(dth), _ptr(dph),
+                          _ptr(dgr), _ptr(out), _ptr(tan), threads or default_threads())
+    if rc:
+        raise ValueError("or_cast_cs rejected its arguments")
+    return out, tan
+
+
+def infinitesimal(field: Field, c: Cosmo, p: CastParams, dirs, h_deriv: float = 0.0,
+                  threads: int | None = None):
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    A = np.zeros((len(dirs), 2, 2))
+    out = np.zeros(len(dirs), RAY_DTYPE)
+    rc = lib().or_infinitesimal(field._h, C.byref(c), C.byref(p), len(dirs), _ptr(dirs), h_deriv,
+                                _ptr(A), _ptr(out), threads or default_threads())
+    if rc:
+        raise ValueError("or_infinitesimal rejected its arguments")
+    return A, out
+
+
+def integrate_steps(field: Field, c: Cosmo, y0, dl) -> tuple[int, np.ndarray]:
+    y = np.ascontiguousarray(y0, np.float64).copy()
+    dl = np.ascontiguousarray(dl, np.float64)
+    st = lib().or_integrate_steps(field._h, C.byref(c), y.ctypes.data_as(C.POINTER(C.c_double)),
+                                  len(dl), _ptr(dl))
+    return st, y
+
+
+from .lensing import (finite_beam, jacobian_cs, decompose, compose, screen_basis,  # noqa: E402
+                      angular_separation)
+
+__all__ = [
+    "Cosmo", "CastParams", "Field", "cosmo", "params", "STATIC", "cast", "cast_cs",
+    "infinitesimal", "integrate_steps", "pix2vec_nest", "eta_of_a", "a_of_eta",
+    "conformal_hubble", "eta0", "chi_of_z", "finite_beam", "jacobian_cs", "decompose",
+    "compose", "screen_basis", "angular_separation", "RAY_DTYPE", "TAN_DTYPE",
+    "REACHED", "LEFT_DOMAIN", "MAX_STEPS", "NONFINITE",
+]
