@@ -1,0 +1,215 @@
+/*
+ * mpath.h -- C ABI of the MI355X (gfx950) weak-field null-geodesic ray tracer.
+ *
+ * The method is the backward ray tracing of Breton & Reverdy,
+ * "Magrathea-Pathfinder: A 3D adaptive-mesh code for geodesic ray tracing in
+ * N-body simulations" (Sect. 2): photons leave an observer along HEALPix pixel
+ * centres (Sect. 2.4), follow the null geodesic equations of the perturbed
+ * FLRW metric in Newtonian gauge (Sect. 2.2, metric and geodesic equations),
+ * integrated by RK4 with N steps per AMR cell, with Phi and grad Phi
+ * interpolated at every RK4 sub-step by cloud-in-cell weights on an octree,
+ * falling back to coarser levels where a finer stencil is incomplete
+ * (Sect. 2.2, the five-step procedure), and stop on the source's iso-eta
+ * surface, returning the lens-equation deflection (Sect. 2.3) and the
+ * redshifts of Sect. 2.5.
+ *
+ * Conventions
+ *   c = 1; lengths and conformal time eta in Mpc/h; phi = Phi/c^2;
+ *   angles in radians; H0 = 100 h km/s/Mpc = 1/2997.92458 h/Mpc.
+ *   Backward tracing starts with k^0 = -1 at the observer (a0 = 1).
+ *
+ * Memory ownership
+ *   The library never allocates device memory.  Every call that needs device
+ *   storage first reports its size (..._workspace_bytes); the caller
+ *   allocates it (e.g. a torch tensor) and passes a raw device pointer.  All
+ *   *_desc input arrays documented as HOST are read during the call only.
+ *   Output arrays are caller-allocated DEVICE arrays.
+ *
+ * Streams and errors
+ *   Every entry point takes a hipStream_t (as void*; NULL = the null stream)
+ *   and returns an int status: MPATH_OK (0) or a negative MPATH_ERR_* code;
+ *   no C++ exception crosses the ABI.  mpath_last_error() gives a
+ *   human-readable message for the calling thread's last failure.  Kernel
+ *   work is asynchronous on the stream; per-ray conditions (a ray that leaves
+ *   a non-periodic domain, exceeds max_steps or becomes non-finite) are
+ *   reported in the status[] output, not as call errors.
+ */
+#ifndef MPATH_H
+#define MPATH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- call status ---- */
+#define MPATH_OK 0
+#define MPATH_ERR_INVALID_ARG (-1)          /* a NULL/negative/out-of-range argument  */
+#define MPATH_ERR_NOT_FULL_TREE (-2)        /* the cell list is not a full octree      */
+#define MPATH_ERR_WORKSPACE_TOO_SMALL (-3)  /* ws_bytes below the reported size        */
+#define MPATH_ERR_DEVICE (-4)               /* a HIP runtime error (text in last_error) */
+#define MPATH_ERR_UNSUPPORTED (-5)          /* a valid but not implemented option      */
+
+/* ---- per-ray status (status[] output) ---- */
+#define MPATH_RAY_REACHED 0      /* stopped on the source surface                          */
+#define MPATH_RAY_LEFT_DOMAIN 1  /* no complete stencil even at the coarse level (Sect. 2.2,
+                                    fifth step): only on non-periodic grids               */
+#define MPATH_RAY_MAX_STEPS 2    /* max_steps reached before the source                   */
+#define MPATH_RAY_NONFINITE 3    /* the state became NaN/Inf                              */
+
+/* ---- value types of the input cell data ---- */
+#define MPATH_F64 0
+#define MPATH_F32 1
+
+/* Background cosmology: flat LCDM with Omega_r = 0 (omega_m + omega_l == 1,
+ * omega_m > 0), or the static case omega_m == omega_l == 0 (a == 1, a'/a = 0,
+ * eta_0 = 0; only usable with stop_kind == MPATH_STOP_CHI).  The conformal
+ * Hubble rate a'/a (Sect. 2.2 reads a(eta), a'(eta) from precomputed tables)
+ * is tabulated by the library in double precision. */
+typedef struct {
+    double omega_m, omega_l, h;
+} mpath_cosmo;
+
+/* The octree of the gravitational potential (Sect. 2.1): a flat list of every
+ * cell, internal and leaf, of a FULL tree (each cell has 0 or 8 children;
+ * every coarse cell present).  All arrays are HOST arrays of length n_cells:
+ *   level[i]    refinement level (0 = coarse, <= max_level)
+ *   ijk[i][3]   integer coordinates at the cell's own level, in [0, n0 2^level)
+ *   phi[i]      potential at the cell centre (each cell, internal or leaf,
+ *               carries its own value: used when interpolating at its level)
+ *   grad[i][3]  gradient of the potential at the cell centre
+ * value_dtype says whether phi and grad are double or float.  Cell (l, i)
+ * covers [i h_l, (i+1) h_l) per axis with h_l = box / (n0 2^l); n0 must be a
+ * power of two (<= 1024) and max_level <= 10.  periodic != 0 replicates the
+ * box (rays may travel further than the box size); otherwise cells outside
+ * the box do not exist. */
+typedef struct {
+    double box;
+    int32_t n0;
+    int32_t max_level;
+    int32_t periodic;
+    int32_t value_dtype;
+    int64_t n_cells;
+    const uint8_t* level;
+    const int32_t* ijk;
+    const void* phi;
+    const void* grad;
+} mpath_grid_desc;
+
+typedef struct mpath_grid mpath_grid;   /* opaque host handle */
+
+/* Device workspace needed by mpath_grid_build for this tree (payload of
+ * 16 B/cell, child links, cell permutation, cosmology table). */
+int mpath_grid_workspace_bytes(const mpath_grid_desc* desc, size_t* bytes);
+
+/* Validate the tree (MPATH_ERR_NOT_FULL_TREE if a cell's parent is missing, a
+ * refined cell has 1-7 children, a coarse cell is missing or a cell repeats),
+ * order it (coarse cells in Morton order, then blocks of 8 siblings level by
+ * level), pack (phi, grad) to float32 and upload into dev_ws on the stream.
+ * Synchronises the stream before returning; the host arrays may be freed
+ * afterwards.  *out receives a handle that refers to dev_ws: dev_ws must
+ * outlive the handle. */
+int mpath_grid_build(const mpath_grid_desc* desc, const mpath_cosmo* cosmo, void* dev_ws,
+                     size_t ws_bytes, void* stream, mpath_grid** out);
+
+/* Release the handle (not dev_ws, which the caller owns). */
+int mpath_grid_free(mpath_grid* grid);
+
+typedef struct {
+    int64_t n_cells;
+    int32_t n0, max_level, periodic;
+    double box;
+    double eta0;              /* conformal time today */
+    int64_t cells_per_level[16];
+    float* payload;           /* DEVICE [n_cells][4] (phi, gx, gy, gz), library order */
+    const int64_t* perm;      /* DEVICE [n_cells]: user index of library cell i */
+} mpath_grid_info;
+
+int mpath_grid_get_info(const mpath_grid* grid, mpath_grid_info* info);
+
+/* Replace the cell values from a DEVICE array values[n_cells][4] = (phi, gx,
+ * gy, gz) float32 in the caller's original cell order (asynchronous). */
+int mpath_grid_set_values(mpath_grid* grid, const float* values, void* stream);
+
+/* ---- casting rays ---- */
+#define MPATH_STOP_REDSHIFT 0   /* stop_value[j] = z_src: eta_s = eta(a = 1/(1+z_src))         */
+#define MPATH_STOP_CHI 1        /* stop_value[j] = comoving distance: eta_s = eta_0 - value    */
+
+#define MPATH_SCHED_AUTO 0      /* library choice (persistent when many observers/uneven rays) */
+#define MPATH_SCHED_STATIC 1    /* one lane per ray, one launch                                 */
+#define MPATH_SCHED_PERSISTENT 2/* resident waves pull ray batches from a global queue          */
+
+typedef struct {
+    /* observers: HOST arrays */
+    int32_t n_obs;
+    const double* obs_pos;      /* [n_obs][3] observer positions */
+    const double* stop_value;   /* [n_obs] per stop_kind */
+    int32_t stop_kind;
+    /* sky pixels (Sect. 2.4): NESTED HEALPix at nside; observer j casts the
+       pixel range [pix_first[j], pix_first[j] + pix_count[j]); rays are
+       numbered observer by observer, in pixel order.  pix_first/pix_count
+       NULL = the full sky for every observer. */
+    int32_t nside;
+    const int64_t* pix_first;
+    const int64_t* pix_count;
+    /* integration (Sect. 2.2) */
+    int32_t order;              /* 1 = CIC; 0 (NGP) and 2 (TSC): MPATH_ERR_UNSUPPORTED */
+    int32_t steps_per_cell;     /* N >= 1: comoving step length h / N                   */
+    int32_t adaptive;           /* 1: h of the leaf cell at the step start; 0: coarse h */
+    int64_t max_steps;          /* per ray, including the landing step                   */
+    /* launch shape; 0 = library default (see mpath_autotune) */
+    int32_t schedule;
+    int32_t block_size;         /* threads per block, multiple of 64, <= 1024           */
+    int32_t waves_per_cu;       /* persistent schedule: resident waves per CU            */
+    int32_t batch;              /* persistent schedule: rays per queue pop per wave (64k)*/
+    /* adjoint support: 0 = forward only, else checkpoint every K steps */
+    int32_t checkpoint_every;
+} mpath_cast_desc;
+
+/* Per-ray outputs: caller-allocated DEVICE arrays of length n_rays
+ * (= sum pix_count).  Any pointer may be NULL (not written).
+ *   beta[2]     (polar, azimuth) of x_s - x_obs (lens equation, Sect. 2.3)
+ *   alpha[2]    deflection theta - beta as a tangent vector at theta of length
+ *               the great-circle angle, on e1 = e_phi(theta), e2 = -e_theta(theta)
+ *   z5          observed redshift (ratio of g_mu nu k^mu u^nu, v = 0, Sect. 2.5)
+ *   z0          FLRW redshift of the stop surface
+ *   phi_src     Phi at the end point
+ *   n_steps     RK4 steps taken, the landing step included
+ *   status      MPATH_RAY_*
+ *   hash        FNV-1a over the discrete decisions (leaf level of every step,
+ *               stencil level of every sub-step) for comparing with a reference
+ *   chi         |x_s - x_obs| */
+typedef struct {
+    double* beta;
+    float* alpha;
+    double* z5;
+    double* z0;
+    float* phi_src;
+    int32_t* n_steps;
+    int32_t* status;
+    uint32_t* hash;
+    double* chi;
+} mpath_observables;
+
+/* Device workspace for a cast (observer table, queue counters and, when
+ * checkpoint_every > 0, the checkpoints of every ray for mpath_adjoint). */
+int mpath_cast_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* desc, size_t* bytes);
+
+/* Cast all rays; asynchronous on the stream except for the upload of the
+ * observer table (a few bytes per observer), which completes before return. */
+int mpath_cast(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observables* out,
+               void* dev_ws, size_t ws_bytes, void* stream);
+
+/* Number of rays a desc describes. */
+int mpath_cast_count_rays(const mpath_cast_desc* desc, int64_t* n_rays);
+
+const char* mpath_status_string(int status);
+const char* mpath_last_error(void);
+const char* mpath_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

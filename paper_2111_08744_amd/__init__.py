@@ -1,0 +1,214 @@
+"""MI355X (gfx950) weak-field null-geodesic ray tracer: Python binding.
+
+Thin marshalling over the C ABI of ``include/mpath.h`` (``libmpath.so`` in
+this directory).  PyTorch provides device memory and the current HIP stream;
+every step of the ray tracing runs in the library's kernels.  The names follow
+the C entry points:
+
+    grid = Grid(cells, cosmo=(0.3, 0.7, 0.7))      # mpath_grid_build
+    out  = cast(grid, obs, z_src, nside, ...)      # mpath_cast
+    grad = adjoint(grid, ..., dL_dalpha, dL_dz)    # mpath_adjoint
+
+Method: Breton & Reverdy, Magrathea-Pathfinder, Sect. 2 (geodesic
+integration with AMR interpolation, lens equation, redshifts).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import (MPATH_RAY_LEFT_DOMAIN, MPATH_RAY_MAX_STEPS, MPATH_RAY_NONFINITE,  # noqa: F401
+                   MPATH_RAY_REACHED, MPATH_SCHED_AUTO, MPATH_SCHED_PERSISTENT,
+                   MPATH_SCHED_STATIC, MPATH_STOP_CHI, MPATH_STOP_REDSHIFT, MpathError)
+
+__all__ = ["Grid", "cast", "CastConfig", "library_path", "MpathError"]
+
+
+def library_path() -> str:
+    return _abi.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Grid:
+    """An octree of Phi and grad Phi resident on the GPU (mpath_grid_build).
+
+    cells: an object with box, n0, max_level, periodic, level[n] (uint8),
+    ijk[n,3] (int32), phi[n], grad[n,3] (float64 or float32 numpy arrays).
+    cosmo: (omega_m, omega_l, h); (0, 0, h) is a static background.
+    """
+
+    def __init__(self, cells, cosmo=(0.3, 0.7, 0.7), device="cuda"):
+        torch = _torch()
+        L = _abi.lib()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the grid lives in GPU memory")
+        level = np.ascontiguousarray(cells.level, np.uint8)
+        ijk = np.ascontiguousarray(cells.ijk, np.int32)
+        f32 = np.asarray(cells.phi).dtype == np.float32
+        vt = np.float32 if f32 else np.float64
+        phi = np.ascontiguousarray(cells.phi, vt)
+        grad = np.ascontiguousarray(cells.grad, vt)
+        self._keep = (level, ijk, phi, grad)
+        d = _abi.mpath_grid_desc()
+        d.box = float(cells.box)
+        d.n0 = int(cells.n0)
+        d.max_level = int(cells.max_level)
+        d.periodic = int(bool(cells.periodic))
+        d.value_dtype = _abi.MPATH_F32 if f32 else _abi.MPATH_F64
+        d.n_cells = len(level)
+        d.level = level.ctypes.data
+        d.ijk = ijk.ctypes.data
+        d.phi = phi.ctypes.data
+        d.grad = grad.ctypes.data
+        nbytes = C.c_size_t()
+        _abi.check(L.mpath_grid_workspace_bytes(C.byref(d), C.byref(nbytes)), "mpath_grid_workspace_bytes")
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        cz = _abi.mpath_cosmo(*map(float, cosmo))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _abi.check(L.mpath_grid_build(C.byref(d), C.byref(cz), _ptr(self.ws), nbytes.value,
+                                          _stream_ptr(self.device), C.byref(h)), "mpath_grid_build")
+        self._h = h
+        self._keep = None
+        self.cosmo = tuple(map(float, cosmo))
+        info = _abi.mpath_grid_info()
+        _abi.check(L.mpath_grid_get_info(self._h, C.byref(info)), "mpath_grid_get_info")
+        self.n_cells = info.n_cells
+        self.max_level = info.max_level
+        self.n0 = info.n0
+        self.box = info.box
+        self.eta0 = info.eta0
+        self.cells_per_level = list(info.cells_per_level[: info.max_level + 1])
+        self.payload_ptr = info.payload
+        self.perm_ptr = info.perm
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_values(self, values):
+        """values: float32 CUDA tensor [n_cells, 4] = (phi, gx, gy, gz) in the
+        caller's cell order (mpath_grid_set_values)."""
+        torch = _torch()
+        assert values.is_cuda and values.dtype == torch.float32 and values.shape == (self.n_cells, 4)
+        values = values.contiguous()
+        _abi.check(_abi.lib().mpath_grid_set_values(self._h, _ptr(values), _stream_ptr(self.device)),
+                   "mpath_grid_set_values")
+        self._values_ref = values     # keep alive until the stream is done with it
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _abi.lib().mpath_grid_free(h)
+            self._h = None
+
+
+class CastConfig:
+    """Everything mpath_cast_desc holds besides the grid (host side)."""
+
+    def __init__(self, obs, stop, nside, pix_first=None, pix_count=None, stop_kind="z",
+                 steps_per_cell=10, adaptive=False, max_steps=1 << 40, schedule=0,
+                 block_size=0, waves_per_cu=0, batch=0, checkpoint_every=0):
+        self.obs = np.ascontiguousarray(np.atleast_2d(obs), np.float64)
+        self.stop = np.ascontiguousarray(np.atleast_1d(stop), np.float64)
+        self.nside = int(nside)
+        self.pix_first = None if pix_first is None else np.ascontiguousarray(np.atleast_1d(pix_first), np.int64)
+        self.pix_count = None if pix_count is None else np.ascontiguousarray(np.atleast_1d(pix_count), np.int64)
+        self.stop_kind = {"z": MPATH_STOP_REDSHIFT, "chi": MPATH_STOP_CHI}[stop_kind] \
+            if isinstance(stop_kind, str) else int(stop_kind)
+        self.steps_per_cell = int(steps_per_cell)
+        self.adaptive = bool(adaptive)
+        self.max_steps = int(max_steps)
+        self.schedule = int(schedule)
+        self.block_size = int(block_size)
+        self.waves_per_cu = int(waves_per_cu)
+        self.batch = int(batch)
+        self.checkpoint_every = int(checkpoint_every)
+
+    def desc(self) -> _abi.mpath_cast_desc:
+        d = _abi.mpath_cast_desc()
+        d.n_obs = self.obs.shape[0]
+        d.obs_pos = self.obs.ctypes.data
+        d.stop_value = self.stop.ctypes.data
+        d.stop_kind = self.stop_kind
+        d.nside = self.nside
+        d.pix_first = self.pix_first.ctypes.data if self.pix_first is not None else None
+        d.pix_count = self.pix_count.ctypes.data if self.pix_count is not None else None
+        d.order = 1
+        d.steps_per_cell = self.steps_per_cell
+        d.adaptive = int(self.adaptive)
+        d.max_steps = self.max_steps
+        d.schedule = self.schedule
+        d.block_size = self.block_size
+        d.waves_per_cu = self.waves_per_cu
+        d.batch = self.batch
+        d.checkpoint_every = self.checkpoint_every
+        return d
+
+    def n_rays(self) -> int:
+        n = C.c_int64()
+        d = self.desc()
+        _abi.check(_abi.lib().mpath_cast_count_rays(C.byref(d), C.byref(n)), "mpath_cast_count_rays")
+        return n.value
+
+
+_OUT_FIELDS = {
+    "beta": ("float64", 2), "alpha": ("float32", 2), "z5": ("float64", 1), "z0": ("float64", 1),
+    "phi_src": ("float32", 1), "n_steps": ("int32", 1), "status": ("int32", 1), "hash": ("int32", 1),
+    "chi": ("float64", 1),
+}
+
+
+def alloc_outputs(n_rays: int, device="cuda", fields=None):
+    torch = _torch()
+    out = {}
+    for k, (dt, w) in _OUT_FIELDS.items():
+        if fields is not None and k not in fields:
+            continue
+        shape = (n_rays, w) if w > 1 else (n_rays,)
+        out[k] = torch.empty(shape, dtype=getattr(torch, dt), device=device)
+    return out
+
+
+def observables_struct(out) -> _abi.mpath_observables:
+    o = _abi.mpath_observables()
+    for k in _OUT_FIELDS:
+        setattr(o, k, out[k].data_ptr() if k in out else None)
+    return o
+
+
+def cast(grid: Grid, cfg: CastConfig, out=None, ws=None):
+    """mpath_cast: cast every ray of cfg on the current stream of the grid's
+    device; returns the dict of output tensors (see mpath_observables)."""
+    torch = _torch()
+    L = _abi.lib()
+    d = cfg.desc()
+    n = cfg.n_rays()
+    if out is None:
+        out = alloc_outputs(n, grid.device)
+    nbytes = C.c_size_t()
+    _abi.check(L.mpath_cast_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)), "mpath_cast_workspace_bytes")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=grid.device)
+    obs = observables_struct(out)
+    with torch.cuda.device(grid.device):
+        _abi.check(L.mpath_cast(grid.handle, C.byref(d), C.byref(obs), _ptr(ws), ws.numel(),
+                                _stream_ptr(grid.device)), "mpath_cast")
+    out["_ws"] = ws
+    return out

@@ -1,0 +1,115 @@
+"""ctypes declarations of the C ABI in include/mpath.h (argument marshalling only).
+
+The shared library is loaded from this package's directory; importing this
+module raises when it is missing, so nothing can silently fall back to
+another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpath.so")
+
+MPATH_OK = 0
+MPATH_ERR_INVALID_ARG = -1
+MPATH_ERR_NOT_FULL_TREE = -2
+MPATH_ERR_WORKSPACE_TOO_SMALL = -3
+MPATH_ERR_DEVICE = -4
+MPATH_ERR_UNSUPPORTED = -5
+
+MPATH_RAY_REACHED = 0
+MPATH_RAY_LEFT_DOMAIN = 1
+MPATH_RAY_MAX_STEPS = 2
+MPATH_RAY_NONFINITE = 3
+
+MPATH_F64 = 0
+MPATH_F32 = 1
+MPATH_STOP_REDSHIFT = 0
+MPATH_STOP_CHI = 1
+MPATH_SCHED_AUTO = 0
+MPATH_SCHED_STATIC = 1
+MPATH_SCHED_PERSISTENT = 2
+
+
+class mpath_cosmo(C.Structure):
+    _fields_ = [("omega_m", C.c_double), ("omega_l", C.c_double), ("h", C.c_double)]
+
+
+class mpath_grid_desc(C.Structure):
+    _fields_ = [("box", C.c_double), ("n0", C.c_int32), ("max_level", C.c_int32),
+                ("periodic", C.c_int32), ("value_dtype", C.c_int32), ("n_cells", C.c_int64),
+                ("level", C.c_void_p), ("ijk", C.c_void_p), ("phi", C.c_void_p), ("grad", C.c_void_p)]
+
+
+class mpath_grid_info(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n0", C.c_int32), ("max_level", C.c_int32),
+                ("periodic", C.c_int32), ("box", C.c_double), ("eta0", C.c_double),
+                ("cells_per_level", C.c_int64 * 16), ("payload", C.c_void_p), ("perm", C.c_void_p)]
+
+
+class mpath_cast_desc(C.Structure):
+    _fields_ = [("n_obs", C.c_int32), ("obs_pos", C.c_void_p), ("stop_value", C.c_void_p),
+                ("stop_kind", C.c_int32), ("nside", C.c_int32), ("pix_first", C.c_void_p),
+                ("pix_count", C.c_void_p), ("order", C.c_int32), ("steps_per_cell", C.c_int32),
+                ("adaptive", C.c_int32), ("max_steps", C.c_int64), ("schedule", C.c_int32),
+                ("block_size", C.c_int32), ("waves_per_cu", C.c_int32), ("batch", C.c_int32),
+                ("checkpoint_every", C.c_int32)]
+
+
+class mpath_observables(C.Structure):
+    _fields_ = [("beta", C.c_void_p), ("alpha", C.c_void_p), ("z5", C.c_void_p), ("z0", C.c_void_p),
+                ("phi_src", C.c_void_p), ("n_steps", C.c_void_p), ("status", C.c_void_p),
+                ("hash", C.c_void_p), ("chi", C.c_void_p)]
+
+
+class mpath_adjoint_desc(C.Structure):
+    _fields_ = [("dL_dalpha", C.c_void_p), ("dL_dz", C.c_void_p), ("jac", C.c_void_p),
+                ("dz_dtheta", C.c_void_p), ("dL_dphi", C.c_void_p), ("dL_dgrad", C.c_void_p),
+                ("dL_dtheta", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"the HIP library is not built: {LIB_PATH} "
+                              "(run `python -m paper_2111_08744_amd.build`)")
+        L = C.CDLL(LIB_PATH)
+        P, vp, sz = C.POINTER, C.c_void_p, C.c_size_t
+        L.mpath_grid_workspace_bytes.argtypes = [P(mpath_grid_desc), P(sz)]
+        L.mpath_grid_build.argtypes = [P(mpath_grid_desc), P(mpath_cosmo), vp, sz, vp, P(vp)]
+        L.mpath_grid_free.argtypes = [vp]
+        L.mpath_grid_get_info.argtypes = [vp, P(mpath_grid_info)]
+        L.mpath_grid_set_values.argtypes = [vp, vp, vp]
+        L.mpath_cast_workspace_bytes.argtypes = [vp, P(mpath_cast_desc), P(sz)]
+        L.mpath_cast.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp, sz, vp]
+        L.mpath_cast_count_rays.argtypes = [P(mpath_cast_desc), P(C.c_int64)]
+        if hasattr(L, "mpath_adjoint"):
+            L.mpath_adjoint.argtypes = [vp, P(mpath_cast_desc), vp, sz, P(mpath_adjoint_desc), vp]
+        L.mpath_status_string.restype = C.c_char_p
+        L.mpath_status_string.argtypes = [C.c_int]
+        L.mpath_last_error.restype = C.c_char_p
+        L.mpath_version.restype = C.c_char_p
+        for name in ("mpath_grid_workspace_bytes", "mpath_grid_build", "mpath_grid_free",
+                     "mpath_grid_get_info", "mpath_grid_set_values", "mpath_cast_workspace_bytes",
+                     "mpath_cast", "mpath_cast_count_rays"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class MpathError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().mpath_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib().mpath_status_string(code).decode()} ({code}): {msg}")
+
+
+def check(code, where):
+    if code != MPATH_OK:
+        raise MpathError(code, where)

@@ -1,0 +1,263 @@
+// cast.hip -- forward ray-casting kernels for gfx950.
+//
+// One lane integrates one photon (Sect. 2.2: photons are independent).  Two
+// schedules share the per-ray code:
+//   static      one launch with one lane per ray; rays of a wave are
+//               neighbouring NESTED pixels of one observer, so their
+//               stencil gathers hit the same cache lines near the observer;
+//   persistent  a grid sized to the resident capacity of the GPU; every lane
+//               that finishes its ray takes the next one from a global
+//               queue (one atomic per wave per refill, ballot-aggregated), so
+//               rays of uneven length (many observers, many source
+//               redshifts, AMR) do not leave lanes idle.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace mpath {
+namespace {
+
+constexpr int kWave = 64;
+
+// Everything one lane carries for its current ray.
+template <bool AMR>
+struct RayRun {
+    int64_t ray;          // -1: no ray
+    int obs;
+    RayGeom geo;
+    double eta_s;
+    float phi_o;
+    GeoState y;
+    int64_t n_steps;
+    uint32_t hash;
+    int status;           // -1 while running
+    FieldCache<AMR> F;
+
+    __device__ __forceinline__ void start(const CastArgs& a, int64_t r)
+    {
+        ray = r;
+        // observer owning the ray (observers are few; linear scan from the end)
+        int j = a.n_obs - 1;
+        while (j > 0 && a.obs[j].ray_first > r) --j;
+        obs = j;
+        const ObsDev& ob = a.obs[j];
+        geo.o[0] = ob.x[0]; geo.o[1] = ob.x[1]; geo.o[2] = ob.x[2];
+        healpix_nest_dir(a.nside, ob.pix_first + (r - ob.ray_first), geo.n);
+        eta_s = ob.eta_s;
+        F.reset();
+        n_steps = 0;
+        hash = kFnvOffset;
+        status = -1;
+        float G[3];
+        int leafl, l;
+        if (F.eval(a.grid, geo.o, phi_o, G, leafl, l)) {
+            status = MPATH_RAY_LEFT_DOMAIN;
+            phi_o = __builtin_nanf("");
+        }
+        // k0 = -1 (backward in time); |k| from the null condition
+        const double po = (double)phi_o;
+        const double kmag = sqrt((1.0 + 2.0 * po) / (1.0 - 2.0 * po));
+        y.eta = a.cosmo_eta0;
+        y.K = 1.0;
+        y.s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            y.d[i] = (float)(geo.n[i] * (kmag - 1.0));
+            y.dx[i] = 0.0f;
+        }
+    }
+
+    // Advance by at most max_iter steps; returns true when the ray is done.
+    __device__ __forceinline__ bool advance(const CastArgs& a, int max_iter)
+    {
+        if (status >= 0) return true;
+        const GridDev& g = a.grid;
+        for (int it = 0; it < max_iter; ++it) {
+            if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return true; }
+            // leaf level at the step start sets the step length (N steps per cell)
+            double x[3];
+            position(geo, y.s, y.dx, x);
+            const int Lm = AMR ? g.max_level : 0;
+            const double scale = (double)(2 << Lm);
+            int I[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) I[d] = (int)floor((x[d] / g.h0) * scale);
+            const int L = F.leaf(g, I);
+            if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
+            hash = fnv(hash, (uint32_t)L);
+            const int lstep = a.adaptive ? L : 0;
+            const double ds = g.h0 / (double)(1 << lstep) / (double)a.steps_per_cell;
+            const double dl = ds / y.K;
+            // landing on the iso-eta surface: Newton on eta_RK4(dl) = eta_s
+            // with derivative -K at the trial end, two iterations, then the step
+            const bool landing = y.eta - y.K * dl < eta_s;
+            double dlx = landing ? (y.eta - eta_s) / y.K : dl;
+            const int passes = landing ? 3 : 1;
+            GeoState yn;
+            for (int k = 0; k < passes; ++k) {
+                if (rk4_step<AMR>(g, a.cosmo, F, geo, y, dlx, yn, hash)) {
+                    status = MPATH_RAY_LEFT_DOMAIN;
+                    return true;
+                }
+                if (k + 1 < passes) dlx = dlx + (yn.eta - eta_s) / yn.K;
+            }
+            const bool fin = finite_state(yn);
+            if (landing) {
+                y = yn;
+                ++n_steps;
+                status = fin ? MPATH_RAY_REACHED : MPATH_RAY_NONFINITE;
+                return true;
+            }
+            if (!fin) { status = MPATH_RAY_NONFINITE; return true; }
+            y = yn;
+            ++n_steps;
+        }
+        return false;
+    }
+
+    // Observables (lens equation, Sect. 2.3; redshifts, Sect. 2.5).
+    __device__ __forceinline__ void finish(const CastArgs& a)
+    {
+        const ObsDev& ob = a.obs[obs];
+        double r[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[i] = y.s * geo.n[i] + (double)y.dx[i];
+        double x[3];
+        position(geo, y.s, y.dx, x);
+        float phi_s = __builtin_nanf(""), G[3];
+        int leafl, l;
+        if (F.eval(a.grid, x, phi_s, G, leafl, l)) phi_s = __builtin_nanf("");
+        const double chi = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        const OutDev& o = a.out;
+        if (o.beta) {
+            o.beta[2 * ray] = atan2(hypot(r[0], r[1]), r[2]);
+            o.beta[2 * ray + 1] = atan2(r[1], r[0]);
+        }
+        if (o.alpha) {
+            const double* n = geo.n;
+            double rh[3] = {r[0] / chi, r[1] / chi, r[2] / chi};
+            const double c = rh[0] * n[0] + rh[1] * n[1] + rh[2] * n[2];
+            double t[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) t[i] = rh[i] - c * n[i];
+            const double st2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+            double fac = 0.0;
+            if (st2 > 0.0) {
+                const double st = sqrt(st2);
+                fac = -atan2(st, c) / st;
+            }
+            const double ph = atan2(n[1], n[0]);
+            const double th = atan2(hypot(n[0], n[1]), n[2]);
+            double sp, cp, stt, ctt;
+            sincos(ph, &sp, &cp);
+            sincos(th, &stt, &ctt);
+            const double e1[3] = {-sp, cp, 0.0};
+            const double e2[3] = {-cp * ctt, -sp * ctt, stt};
+            o.alpha[2 * ray] = (float)(fac * (t[0] * e1[0] + t[1] * e1[1] + t[2] * e1[2]));
+            o.alpha[2 * ray + 1] = (float)(fac * (t[0] * e2[0] + t[1] * e2[1] + t[2] * e2[2]));
+        }
+        const bool ok = status == MPATH_RAY_REACHED;
+        if (o.z5)
+            o.z5[ray] = ok ? ob.a_s * y.K * (1.0 + (double)phi_s) / (1.0 + (double)phi_o) - 1.0
+                           : __builtin_nan("");
+        if (o.z0) o.z0[ray] = ok ? ob.z0 : __builtin_nan("");
+        if (o.phi_src) o.phi_src[ray] = phi_s;
+        if (o.n_steps) o.n_steps[ray] = (int32_t)n_steps;
+        if (o.status) o.status[ray] = status;
+        if (o.hash) o.hash[ray] = hash;
+        if (o.chi) o.chi[ray] = chi;
+    }
+};
+
+template <bool AMR>
+__global__ __launch_bounds__(256) void cast_static_kernel(CastArgs a)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    RayRun<AMR> R;
+    R.start(a, r);
+    R.advance(a, 0x7fffffff);
+    R.finish(a);
+}
+
+template <bool AMR>
+__global__ __launch_bounds__(256) void cast_persistent_kernel(CastArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    RayRun<AMR> R;
+    R.ray = -1;
+    bool exhausted = false;
+    for (;;) {
+        // refill every lane without a ray (one atomic per wave)
+        const bool need = R.ray < 0 && !exhausted;
+        const unsigned long long want = __ballot(need);
+        if (want) {
+            const int cnt = __popcll(want);
+            const int leader = __ffsll((long long)want) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)cnt);
+            base = __shfl(base, leader);
+            if (base + (unsigned long long)cnt >= (unsigned long long)a.n_rays) exhausted = true;
+            if (need) {
+                const unsigned long long mine = base + __popcll(want & ((1ull << lane) - 1ull));
+                if (mine < (unsigned long long)a.n_rays) R.start(a, (int64_t)mine);
+            }
+        }
+        if (!__ballot(R.ray >= 0)) break;          // queue drained and every lane idle
+        if (R.ray >= 0 && R.advance(a, a.batch)) {
+            R.finish(a);
+            R.ray = -1;
+        }
+    }
+}
+
+__global__ void zero_u64(unsigned long long* p) { *p = 0ull; }
+
+__global__ void permute_values_kernel(float4* payload, const int64_t* perm, const float4* values, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) payload[i] = values[perm[i]];
+}
+
+}  // namespace
+
+hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const int64_t blocks = (a.n_rays + block - 1) / block;
+    if (a.grid.max_level > 0)
+        hipLaunchKernelGGL(cast_static_kernel<true>, dim3((unsigned)blocks), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL(cast_static_kernel<false>, dim3((unsigned)blocks), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, a.queue);
+    if (a.grid.max_level > 0)
+        hipLaunchKernelGGL(cast_persistent_kernel<true>, dim3(blocks), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL(cast_persistent_kernel<false>, dim3(blocks), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+int cast_occupancy_blocks_per_cu(int block, bool amr)
+{
+    int nb = 0;
+    hipError_t e = amr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<true>, block, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<false>, block, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_permute_values(float4* payload, const int64_t* perm, const float4* values, int64_t n,
+                                 hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(permute_values_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, payload, perm,
+                       values, n);
+    return hipGetLastError();
+}
+
+}  // namespace mpath

@@ -1,0 +1,97 @@
+// internal.h -- types shared by the host part and the kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mpath.h"
+
+namespace mpath {
+
+// Per-observer table, uploaded by mpath_cast.  eta_s is the conformal time of
+// the stop surface, a_s = a(eta_s), z0 = 1/a_s - 1.
+struct ObsDev {
+    double x[3];
+    double eta_s;
+    double a_s;
+    double z0;
+    int64_t pix_first;
+    int64_t ray_first;   // index of the observer's first ray in the outputs
+    int64_t count;
+};
+
+// Octree on the device.  Cells are numbered coarse-first: coarse cell
+// (i, j, k) has id morton3(i, j, k); the children of a refined cell c are the
+// 8 consecutive ids child[c] + octant, octant = ox + 2 oy + 4 oz.
+struct GridDev {
+    const float4* payload;    // (phi, gx, gy, gz) per cell
+    const int32_t* child;     // first child id, -1 for a leaf
+    double h0;                // coarse cell size
+    int32_t n0;               // coarse cells per side (power of two)
+    int32_t max_level;
+    int32_t periodic;
+};
+
+// Conformal Hubble rate a'/a tabulated with its eta-derivative on a uniform
+// eta grid, for cubic Hermite interpolation.
+struct CosmoDev {
+    const double2* table;     // (H, dH/deta) at eta_lo + i * deta
+    double eta_lo;
+    double inv_deta;
+    double deta;
+    int32_t n;
+    int32_t is_static;
+};
+
+struct OutDev {
+    double* beta;
+    float* alpha;
+    double* z5;
+    double* z0;
+    float* phi_src;
+    int32_t* n_steps;
+    int32_t* status;
+    uint32_t* hash;
+    double* chi;
+};
+
+struct CastArgs {
+    GridDev grid;
+    CosmoDev cosmo;
+    double cosmo_eta0;           // conformal time at the observers (a = 1)
+    const ObsDev* obs;
+    int32_t n_obs;
+    int32_t nside;
+    int32_t steps_per_cell;
+    int32_t adaptive;
+    int64_t max_steps;
+    int64_t n_rays;
+    OutDev out;
+    unsigned long long* queue;   // persistent schedule: next ray to hand out
+    int32_t batch;               // rays per queue pop (multiple of the wave size)
+};
+
+// Kernel launchers (defined in cast.hip).
+hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s);
+hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipStream_t s);
+hipError_t launch_permute_values(float4* payload, const int64_t* perm, const float4* values,
+                                 int64_t n, hipStream_t s);
+int cast_occupancy_blocks_per_cu(int block, bool amr);
+
+// Morton interleave of three 10-bit coordinates (host and device).
+__host__ __device__ inline uint32_t part1by2(uint32_t x)
+{
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__host__ __device__ inline uint32_t morton3(uint32_t i, uint32_t j, uint32_t k)
+{
+    return part1by2(i) | (part1by2(j) << 1) | (part1by2(k) << 2);
+}
+
+}  // namespace mpath

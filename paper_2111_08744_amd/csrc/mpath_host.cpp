@@ -1,0 +1,550 @@
+// mpath_host.cpp -- host side of the C ABI: argument checks, octree build
+// (validation, ordering, packing), background cosmology table, observer
+// table and kernel launches.  See include/mpath.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace mpath;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(MPATH_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr double kH0 = 1.0 / 2997.92458;   // h/Mpc with c = 1
+constexpr int kTableN = 4096;
+constexpr double kZMaxTable = 20.0;          // rays may be traced up to this redshift
+
+// ---------------------------------------------------------------------------
+// Background: flat LCDM, Omega_r = 0.  With y = sqrt(a), d eta = da/(a^2 H)
+// becomes d eta = 2 dy / (H0 sqrt(Om + OL y^6)), a smooth integrand; eta(a)
+// is evaluated by composite Gauss-Legendre quadrature and a(eta) by Newton's
+// method in y.
+// ---------------------------------------------------------------------------
+struct Background {
+    double om = 0.3, ol = 0.7;
+    bool is_static = false;
+    double gl_x[20], gl_w[20];
+
+    void init(double omega_m, double omega_l)
+    {
+        om = omega_m;
+        ol = omega_l;
+        is_static = (om == 0.0 && ol == 0.0);
+        // Gauss-Legendre nodes on [-1, 1]: Newton on P_20 from the
+        // Chebyshev-like initial guesses
+        const int n = 20;
+        for (int i = 0; i < n; ++i) {
+            double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+            double dp = 1.0;
+            for (int it = 0; it < 100; ++it) {
+                double p0 = 1.0, p1 = x;
+                for (int k = 2; k <= n; ++k) {
+                    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = n * (x * p1 - p0) / (x * x - 1.0);
+                const double dx = p1 / dp;
+                x -= dx;
+                if (std::fabs(dx) < 1e-16) break;
+            }
+            gl_x[i] = x;
+            gl_w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+        }
+    }
+
+    double deta_dy(double y) const { return 2.0 / (kH0 * std::sqrt(om + ol * y * y * y * y * y * y)); }
+
+    double eta_of_y(double y) const
+    {
+        const int panels = 8;
+        const double w = y / panels;
+        double sum = 0.0;
+        for (int p = 0; p < panels; ++p) {
+            const double c = (p + 0.5) * w;
+            double s = 0.0;
+            for (int i = 0; i < 20; ++i) s += gl_w[i] * deta_dy(c + 0.5 * w * gl_x[i]);
+            sum += 0.5 * w * s;
+        }
+        return sum;
+    }
+
+    double eta_of_a(double a) const { return is_static ? 0.0 : eta_of_y(std::sqrt(a)); }
+    double eta0() const { return eta_of_a(1.0); }
+
+    double a_of_eta(double eta) const
+    {
+        if (is_static) return 1.0;
+        // matter-dominated start: eta = 2 y / (H0 sqrt(Om))
+        double y = 0.5 * kH0 * std::sqrt(om) * eta;
+        for (int it = 0; it < 60; ++it) {
+            const double dy = (eta_of_y(y) - eta) / deta_dy(y);
+            y -= dy;
+            if (std::fabs(dy) <= 1e-16 * y) break;
+        }
+        return y * y;
+    }
+
+    // a'/a = a H = H0 sqrt(Om/a + OL a^2) and its eta-derivative
+    // d(a'/a)/d eta = d(aH)/da * a (a'/a)
+    void hubble(double a, double& H, double& dH) const
+    {
+        const double s = std::sqrt(om / a + ol * a * a);
+        H = kH0 * s;
+        const double dHda = kH0 * (-om / (a * a) + 2.0 * ol * a) / (2.0 * s);
+        dH = dHda * a * H;
+    }
+};
+
+}  // namespace
+
+struct mpath_grid {
+    int64_t n_cells = 0;
+    int32_t n0 = 0, max_level = 0, periodic = 0;
+    double box = 0.0;
+    int64_t cells_per_level[16] = {0};
+    Background bg;
+    double eta0 = 0.0;
+    double table_eta_lo = 0.0, table_deta = 0.0;
+    char* ws = nullptr;
+    float4* payload = nullptr;
+    int32_t* child = nullptr;
+    int64_t* perm = nullptr;
+    double2* table = nullptr;
+    int num_cus = 0;
+};
+
+namespace {
+
+struct GridLayout {
+    size_t off_payload, off_child, off_perm, off_table, total;
+};
+
+GridLayout grid_layout(int64_t n)
+{
+    GridLayout L;
+    L.off_payload = 0;
+    L.off_child = align_up(L.off_payload + (size_t)n * 16, 256);
+    L.off_perm = align_up(L.off_child + (size_t)n * 4, 256);
+    L.off_table = align_up(L.off_perm + (size_t)n * 8, 256);
+    L.total = align_up(L.off_table + (size_t)kTableN * 16, 256);
+    return L;
+}
+
+int check_grid_desc(const mpath_grid_desc* d)
+{
+    if (!d) return fail(MPATH_ERR_INVALID_ARG, "grid desc is NULL");
+    if (!(d->box > 0.0) || !std::isfinite(d->box)) return fail(MPATH_ERR_INVALID_ARG, "box must be > 0");
+    if (d->n0 < 1 || d->n0 > 1024 || (d->n0 & (d->n0 - 1)))
+        return fail(MPATH_ERR_INVALID_ARG, "n0 must be a power of two in [1, 1024]");
+    if (d->max_level < 0 || d->max_level > 10) return fail(MPATH_ERR_INVALID_ARG, "max_level must be in [0, 10]");
+    if ((int64_t)d->n0 << d->max_level > (1 << 20))
+        return fail(MPATH_ERR_INVALID_ARG, "n0 * 2^max_level must be <= 2^20");
+    if (d->value_dtype != MPATH_F64 && d->value_dtype != MPATH_F32)
+        return fail(MPATH_ERR_INVALID_ARG, "value_dtype must be MPATH_F64 or MPATH_F32");
+    const int64_t nc = (int64_t)d->n0 * d->n0 * d->n0;
+    if (d->n_cells < nc) return fail(MPATH_ERR_NOT_FULL_TREE, "fewer cells than the coarse grid");
+    if (d->n_cells > ((int64_t)1 << 31) - 8) return fail(MPATH_ERR_INVALID_ARG, "n_cells must be < 2^31");
+    if (!d->level || !d->ijk || !d->phi || !d->grad) return fail(MPATH_ERR_INVALID_ARG, "a cell array is NULL");
+    return MPATH_OK;
+}
+
+uint64_t morton_key(uint32_t i, uint32_t j, uint32_t k)
+{
+    // 21 bits per axis
+    auto spread = [](uint64_t x) {
+        x &= 0x1fffffull;
+        x = (x | (x << 32)) & 0x1f00000000ffffull;
+        x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+        x = (x | (x << 8)) & 0x100f00f00f00f00full;
+        x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+        x = (x | (x << 2)) & 0x1249249249249249ull;
+        return x;
+    };
+    return spread(i) | (spread(j) << 1) | (spread(k) << 2);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mpath_last_error(void) { return g_last_error.c_str(); }
+
+const char* mpath_version(void) { return "mpath 0.1 (gfx950)"; }
+
+const char* mpath_status_string(int s)
+{
+    switch (s) {
+        case MPATH_OK: return "ok";
+        case MPATH_ERR_INVALID_ARG: return "invalid argument";
+        case MPATH_ERR_NOT_FULL_TREE: return "not a full octree";
+        case MPATH_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case MPATH_ERR_DEVICE: return "device error";
+        case MPATH_ERR_UNSUPPORTED: return "unsupported option";
+        default: return "unknown status";
+    }
+}
+
+int mpath_grid_workspace_bytes(const mpath_grid_desc* desc, size_t* bytes)
+{
+    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
+    const int rc = check_grid_desc(desc);
+    if (rc) return rc;
+    *bytes = grid_layout(desc->n_cells).total;
+    return MPATH_OK;
+}
+
+int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* dev_ws, size_t ws_bytes,
+                     void* stream, mpath_grid** out)
+{
+    if (!out) return fail(MPATH_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_grid_desc(d);
+    if (rc) return rc;
+    if (!cosmo) return fail(MPATH_ERR_INVALID_ARG, "cosmo is NULL");
+    const bool stat = cosmo->omega_m == 0.0 && cosmo->omega_l == 0.0;
+    if (!stat && !(cosmo->omega_m > 0.0 && cosmo->omega_l >= 0.0 &&
+                   std::fabs(cosmo->omega_m + cosmo->omega_l - 1.0) < 1e-12))
+        return fail(MPATH_ERR_UNSUPPORTED, "only flat LCDM (omega_m + omega_l = 1) or a static background");
+    const GridLayout lay = grid_layout(d->n_cells);
+    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
+    if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "grid workspace too small");
+
+    const int64_t n = d->n_cells;
+    const int L = d->max_level;
+    const uint32_t n0 = (uint32_t)d->n0;
+    // ---- bucket cells by level, keyed by Morton order at their level ----
+    std::vector<std::vector<std::pair<uint64_t, int64_t>>> lev(L + 1);
+    for (int64_t c = 0; c < n; ++c) {
+        const int l = d->level[c];
+        if (l > L) return fail(MPATH_ERR_INVALID_ARG, "cell " + std::to_string(c) + " level above max_level");
+        const int64_t m = (int64_t)n0 << l;
+        const int32_t* q = d->ijk + 3 * c;
+        if (q[0] < 0 || q[1] < 0 || q[2] < 0 || q[0] >= m || q[1] >= m || q[2] >= m)
+            return fail(MPATH_ERR_INVALID_ARG, "cell " + std::to_string(c) + " coordinates out of range");
+        lev[l].push_back({morton_key((uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]), c});
+    }
+    for (int l = 0; l <= L; ++l) std::sort(lev[l].begin(), lev[l].end());
+    // coarse level: exactly n0^3 distinct cells, so the sorted keys are 0..n0^3-1
+    const int64_t nc = (int64_t)n0 * n0 * n0;
+    if ((int64_t)lev[0].size() != nc) return fail(MPATH_ERR_NOT_FULL_TREE, "the coarse level must hold n0^3 cells");
+    for (int64_t i = 0; i < nc; ++i)
+        if (lev[0][i].first != (uint64_t)i) return fail(MPATH_ERR_NOT_FULL_TREE, "missing or repeated coarse cell");
+    // refined levels: complete sibling groups whose parent exists
+    std::vector<int32_t> child(n, -1);
+    std::vector<int64_t> perm(n);
+    int64_t base_prev = 0, base = nc;
+    for (int64_t i = 0; i < nc; ++i) perm[i] = lev[0][i].second;
+    for (int l = 1; l <= L; ++l) {
+        const auto& cur = lev[l];
+        const auto& par = lev[l - 1];
+        if (cur.size() % 8) return fail(MPATH_ERR_NOT_FULL_TREE, "a refined cell has 1-7 children (level " + std::to_string(l) + ")");
+        size_t pj = 0;
+        for (size_t g = 0; g < cur.size(); g += 8) {
+            const uint64_t pk = cur[g].first >> 3;
+            for (int o = 0; o < 8; ++o)
+                if (cur[g + o].first != (pk << 3) + (uint64_t)o)
+                    return fail(MPATH_ERR_NOT_FULL_TREE, "a refined cell has 1-7 children or a repeated child (level " + std::to_string(l) + ")");
+            while (pj < par.size() && par[pj].first < pk) ++pj;
+            if (pj == par.size() || par[pj].first != pk)
+                return fail(MPATH_ERR_NOT_FULL_TREE, "a cell's parent is missing (level " + std::to_string(l) + ")");
+            const int64_t id = base + (int64_t)g;
+            child[base_prev + (int64_t)pj] = (int32_t)id;
+            for (int o = 0; o < 8; ++o) perm[id + o] = cur[g + o].second;
+        }
+        base_prev = base;
+        base += (int64_t)cur.size();
+    }
+    // ---- pack (phi, grad) as float32 in library order ----
+    std::vector<float4> payload(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t c = perm[i];
+        if (d->value_dtype == MPATH_F64) {
+            const double* p = (const double*)d->phi;
+            const double* g = (const double*)d->grad;
+            payload[i] = make_float4((float)p[c], (float)g[3 * c], (float)g[3 * c + 1], (float)g[3 * c + 2]);
+        } else {
+            const float* p = (const float*)d->phi;
+            const float* g = (const float*)d->grad;
+            payload[i] = make_float4(p[c], g[3 * c], g[3 * c + 1], g[3 * c + 2]);
+        }
+    }
+    // ---- background table of a'/a ----
+    mpath_grid* G = new mpath_grid();
+    G->bg.init(cosmo->omega_m, cosmo->omega_l);
+    G->eta0 = G->bg.is_static ? 0.0 : G->bg.eta0();
+    std::vector<double2> table(kTableN, make_double2(0.0, 0.0));
+    if (!G->bg.is_static) {
+        const double lo = G->bg.eta_of_a(1.0 / (1.0 + kZMaxTable)) - 50.0;
+        const double hi = G->eta0 + 50.0;
+        G->table_eta_lo = lo;
+        G->table_deta = (hi - lo) / (kTableN - 1);
+        for (int i = 0; i < kTableN; ++i) {
+            const double a = G->bg.a_of_eta(lo + i * G->table_deta);
+            double H, dH;
+            G->bg.hubble(a, H, dH);
+            table[i] = make_double2(H, dH);
+        }
+    }
+    // ---- upload ----
+    G->n_cells = n;
+    G->n0 = d->n0;
+    G->max_level = L;
+    G->periodic = d->periodic ? 1 : 0;
+    G->box = d->box;
+    for (int l = 0; l <= L && l < 16; ++l) G->cells_per_level[l] = (int64_t)lev[l].size();
+    G->ws = (char*)dev_ws;
+    G->payload = (float4*)(G->ws + lay.off_payload);
+    G->child = (int32_t*)(G->ws + lay.off_child);
+    G->perm = (int64_t*)(G->ws + lay.off_perm);
+    G->table = (double2*)(G->ws + lay.off_table);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(G->payload, payload.data(), (size_t)n * 16, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(G->child, child.data(), (size_t)n * 4, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(G->perm, perm.data(), (size_t)n * 8, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(G->table, table.data(), (size_t)kTableN * 16, hipMemcpyHostToDevice, s)) ||
+        (e = hipStreamSynchronize(s))) {
+        delete G;
+        return hip_fail(e, "grid upload");
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&G->num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        G->num_cus = 0;
+    *out = G;
+    return MPATH_OK;
+}
+
+int mpath_grid_free(mpath_grid* grid)
+{
+    delete grid;
+    return MPATH_OK;
+}
+
+int mpath_grid_get_info(const mpath_grid* g, mpath_grid_info* info)
+{
+    if (!g || !info) return fail(MPATH_ERR_INVALID_ARG, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    info->n_cells = g->n_cells;
+    info->n0 = g->n0;
+    info->max_level = g->max_level;
+    info->periodic = g->periodic;
+    info->box = g->box;
+    info->eta0 = g->eta0;
+    for (int l = 0; l < 16; ++l) info->cells_per_level[l] = g->cells_per_level[l];
+    info->payload = (float*)g->payload;
+    info->perm = g->perm;
+    return MPATH_OK;
+}
+
+int mpath_grid_set_values(mpath_grid* g, const float* values, void* stream)
+{
+    if (!g || !values) return fail(MPATH_ERR_INVALID_ARG, "NULL argument");
+    const hipError_t e = launch_permute_values(g->payload, g->perm, (const float4*)values, g->n_cells,
+                                               (hipStream_t)stream);
+    return e ? hip_fail(e, "set_values launch") : MPATH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct CastLayout {
+    size_t off_obs, off_queue, total;
+};
+
+CastLayout cast_layout(int64_t n_obs)
+{
+    CastLayout L;
+    L.off_obs = 0;
+    L.off_queue = align_up((size_t)n_obs * sizeof(ObsDev), 256);
+    L.total = align_up(L.off_queue + 256, 256);
+    return L;
+}
+
+int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_rays)
+{
+    if (!g) return fail(MPATH_ERR_INVALID_ARG, "grid is NULL");
+    if (!d) return fail(MPATH_ERR_INVALID_ARG, "cast desc is NULL");
+    if (d->n_obs < 1) return fail(MPATH_ERR_INVALID_ARG, "n_obs must be >= 1");
+    if (!d->obs_pos || !d->stop_value) return fail(MPATH_ERR_INVALID_ARG, "obs_pos or stop_value is NULL");
+    if (d->nside < 1 || d->nside > 8192) return fail(MPATH_ERR_INVALID_ARG, "nside must be in [1, 8192]");
+    if ((d->pix_first == nullptr) != (d->pix_count == nullptr))
+        return fail(MPATH_ERR_INVALID_ARG, "pix_first and pix_count must both be given or both NULL");
+    if (d->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "only order = 1 (CIC) is implemented");
+    if (d->steps_per_cell < 1) return fail(MPATH_ERR_INVALID_ARG, "steps_per_cell must be >= 1");
+    if (d->max_steps < 1) return fail(MPATH_ERR_INVALID_ARG, "max_steps must be >= 1");
+    if (d->stop_kind != MPATH_STOP_REDSHIFT && d->stop_kind != MPATH_STOP_CHI)
+        return fail(MPATH_ERR_INVALID_ARG, "unknown stop_kind");
+    if (d->stop_kind == MPATH_STOP_REDSHIFT && g->bg.is_static)
+        return fail(MPATH_ERR_INVALID_ARG, "a static background has no redshift stop");
+    if (d->schedule < 0 || d->schedule > 2) return fail(MPATH_ERR_INVALID_ARG, "unknown schedule");
+    if (d->block_size && (d->block_size % 64 || d->block_size > 1024))
+        return fail(MPATH_ERR_INVALID_ARG, "block_size must be a multiple of 64, <= 1024");
+    if (d->checkpoint_every < 0) return fail(MPATH_ERR_INVALID_ARG, "checkpoint_every must be >= 0");
+    const int64_t npix = 12ll * d->nside * d->nside;
+    int64_t total = 0;
+    for (int j = 0; j < d->n_obs; ++j) {
+        const int64_t f = d->pix_first ? d->pix_first[j] : 0;
+        const int64_t c = d->pix_count ? d->pix_count[j] : npix;
+        if (f < 0 || c < 0 || f + c > npix) return fail(MPATH_ERR_INVALID_ARG, "pixel range outside the sky");
+        total += c;
+    }
+    *n_rays = total;
+    return MPATH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpath_cast_count_rays(const mpath_cast_desc* d, int64_t* n_rays)
+{
+    if (!d || !n_rays) return fail(MPATH_ERR_INVALID_ARG, "NULL argument");
+    if (d->n_obs < 1 || d->nside < 1) return fail(MPATH_ERR_INVALID_ARG, "bad n_obs or nside");
+    const int64_t npix = 12ll * d->nside * d->nside;
+    int64_t t = 0;
+    for (int j = 0; j < d->n_obs; ++j) t += d->pix_count ? d->pix_count[j] : npix;
+    *n_rays = t;
+    return MPATH_OK;
+}
+
+int mpath_cast_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, size_t* bytes)
+{
+    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
+    int64_t n_rays;
+    const int rc = check_cast_desc(g, d, &n_rays);
+    if (rc) return rc;
+    *bytes = cast_layout(d->n_obs).total;
+    return MPATH_OK;
+}
+
+int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* dev_ws,
+               size_t ws_bytes, void* stream)
+{
+    int64_t n_rays;
+    int rc = check_cast_desc(g, d, &n_rays);
+    if (rc) return rc;
+    if (!out) return fail(MPATH_ERR_INVALID_ARG, "out is NULL");
+    if (d->checkpoint_every) return fail(MPATH_ERR_UNSUPPORTED, "checkpointing is not available in this build");
+    const CastLayout lay = cast_layout(d->n_obs);
+    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
+    if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "cast workspace too small");
+
+    // ---- observer table ----
+    std::vector<ObsDev> obs(d->n_obs);
+    const double amin = 1.0 / (1.0 + kZMaxTable);
+    const int Lm = g->max_level;
+    const double h0 = g->box / g->n0;
+    int64_t first = 0;
+    for (int j = 0; j < d->n_obs; ++j) {
+        ObsDev& o = obs[j];
+        for (int i = 0; i < 3; ++i) {
+            o.x[i] = d->obs_pos[3 * j + i];
+            if (!std::isfinite(o.x[i])) return fail(MPATH_ERR_INVALID_ARG, "observer position not finite");
+        }
+        const double v = d->stop_value[j];
+        if (d->stop_kind == MPATH_STOP_REDSHIFT) {
+            if (!(v >= 0.0)) return fail(MPATH_ERR_INVALID_ARG, "z_src must be >= 0");
+            if (v > kZMaxTable) return fail(MPATH_ERR_UNSUPPORTED, "z_src above 20 is outside the background table");
+            o.a_s = 1.0 / (1.0 + v);
+            o.eta_s = g->bg.eta_of_a(o.a_s);
+        } else {
+            if (!(v >= 0.0)) return fail(MPATH_ERR_INVALID_ARG, "comoving distance must be >= 0");
+            o.eta_s = g->eta0 - v;
+            if (!g->bg.is_static && o.eta_s < g->bg.eta_of_a(amin))
+                return fail(MPATH_ERR_UNSUPPORTED, "stop surface beyond z = 20 is outside the background table");
+            o.a_s = g->bg.a_of_eta(o.eta_s);
+        }
+        o.z0 = 1.0 / o.a_s - 1.0;
+        o.pix_first = d->pix_first ? d->pix_first[j] : 0;
+        o.count = d->pix_count ? d->pix_count[j] : 12ll * d->nside * d->nside;
+        o.ray_first = first;
+        first += o.count;
+        // integer cell coordinates at level max_level + 1 must stay inside int32
+        const double reach = (std::fabs(o.x[0]) + std::fabs(o.x[1]) + std::fabs(o.x[2]) +
+                              1.01 * (g->eta0 - o.eta_s) + 4.0 * h0) / h0 * std::ldexp(1.0, Lm + 1);
+        if (reach > 1.0e9) return fail(MPATH_ERR_UNSUPPORTED, "ray path too long for 32-bit cell coordinates");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dev_ws;
+    ObsDev* dobs = (ObsDev*)(ws + lay.off_obs);
+    hipError_t e = hipMemcpyAsync(dobs, obs.data(), obs.size() * sizeof(ObsDev), hipMemcpyHostToDevice, s);
+    if (!e) e = hipStreamSynchronize(s);   // the host table is released on return
+    if (e) return hip_fail(e, "observer table upload");
+
+    CastArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.grid.payload = g->payload;
+    a.grid.child = g->child;
+    a.grid.h0 = h0;
+    a.grid.n0 = g->n0;
+    a.grid.max_level = g->max_level;
+    a.grid.periodic = g->periodic;
+    a.cosmo.table = g->table;
+    a.cosmo.eta_lo = g->table_eta_lo;
+    a.cosmo.deta = g->table_deta;
+    a.cosmo.inv_deta = g->table_deta > 0 ? 1.0 / g->table_deta : 0.0;
+    a.cosmo.n = kTableN;
+    a.cosmo.is_static = g->bg.is_static ? 1 : 0;
+    a.cosmo_eta0 = g->eta0;
+    a.obs = dobs;
+    a.n_obs = d->n_obs;
+    a.nside = d->nside;
+    a.steps_per_cell = d->steps_per_cell;
+    a.adaptive = d->adaptive ? 1 : 0;
+    a.max_steps = d->max_steps;
+    a.n_rays = n_rays;
+    a.out.beta = out->beta;
+    a.out.alpha = out->alpha;
+    a.out.z5 = out->z5;
+    a.out.z0 = out->z0;
+    a.out.phi_src = out->phi_src;
+    a.out.n_steps = out->n_steps;
+    a.out.status = out->status;
+    a.out.hash = out->hash;
+    a.out.chi = out->chi;
+    a.queue = (unsigned long long*)(ws + lay.off_queue);
+    a.batch = d->batch > 0 ? d->batch : 32;
+
+    int sched = d->schedule;
+    if (sched == MPATH_SCHED_AUTO) sched = d->n_obs > 1 ? MPATH_SCHED_PERSISTENT : MPATH_SCHED_STATIC;
+    const int block = d->block_size ? d->block_size : 256;
+    if (sched == MPATH_SCHED_STATIC) {
+        e = launch_cast_static(a, block, s);
+    } else {
+        int wpc = d->waves_per_cu;
+        if (wpc <= 0) wpc = cast_occupancy_blocks_per_cu(block, g->max_level > 0) * (block / 64);
+        if (wpc <= 0) wpc = 8;
+        const int cus = g->num_cus > 0 ? g->num_cus : 256;
+        const int blocks = std::max(1, cus * wpc / (block / 64));
+        e = launch_cast_persistent(a, block, blocks, s);
+    }
+    if (e) return hip_fail(e, "cast launch");
+    return MPATH_OK;
+}
+
+}  // extern "C"
