@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark: backward null-geodesic ray tracing through an AMR octree on one MI355X.
+
+Default workload (one "step" = one full cast of every ray):
+  AMR grid: 128^3 coarse cells + 3 refinement levels (box 500 Mpc/h, Gaussian
+  potential P(k) ~ k^-3 with rms 1e-5 plus 200 truncated NFW-like haloes,
+  refined where the density exceeds 8x the mean; 10,035,832 cells, float32
+  Phi + grad Phi on the GPU); observer at the box centre; 786,432 rays
+  (HEALPix NESTED nside 256, full sky) to z = 1; 4 RK4 steps per leaf cell.
+
+Prints one JSON line: ray-steps/s (value), rays/s, the roofline of the cast
+kernel and the FP64 CPU oracle's rate on a bounded sample of the same rays.
+
+    python bench.py [--steps K] [--warmup W] [--workload amr|uniform|batched]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic arithmetic of one ray-step of the method (RK4 with CIC
+# interpolation of Phi and grad Phi at four sub-steps and the geodesic
+# right-hand side), counted as floating-point operations with a fused
+# multiply-add = 2: ~560 FP32 + ~20 FP64.
+FLOPS_PER_RAY_STEP = 580.0
+# Peak for this kernel: vector FMA on 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
+# Packed FP32 is disabled, so FP32 and FP64 issue at the same rate.
+PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import synth
+    w = synth.WORKLOADS[name]
+    cells = synth.make_cells(w.grid)
+    return w, cells
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2111_08744_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(wl_name):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/), if they
+    were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{wl_name}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, cells, sample_stride, threads):
+    """The FP64 oracle on every sample_stride-th ray of the same workload."""
+    import oracle as O
+    t0 = time.time()
+    field = O.Field.grid(cells)
+    c = O.cosmo(0.3, 0.7, 0.7)
+    obs = w.obs[0]
+    pix = np.arange(w.pix_first[0], w.pix_first[0] + w.pix_count[0], sample_stride)
+    dirs = O.pix2vec_nest(w.nside, pix)
+    p = O.params(obs, z_src=float(w.z_src[0]), steps_per_cell=w.steps_per_cell, adaptive=w.adaptive)
+    setup = time.time() - t0
+    t0 = time.time()
+    rec = O.cast(field, c, p, dirs, threads=threads)
+    dt = time.time() - t0
+    steps = int(rec["n_steps"].sum())
+    return {"value": steps / dt, "unit": "ray-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(pix)} of {int(w.pix_count[0])} rays (every {sample_stride}th NESTED pixel), "
+                      f"full paths, {steps} ray-steps in {dt:.1f} s (grid setup {setup:.1f} s untimed)",
+            "rays_per_s": len(pix) / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="amr")
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=128)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(rays would be sharded by sky pixel with the grid replicated; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2111_08744_amd as M
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w, cells = workload(args.workload)
+    t_gen = time.time() - t0
+    log(f"[bench] workload {w.name}: grid {w.grid} with {cells.n_cells} cells, {w.n_rays} rays, "
+        f"generated in {t_gen:.1f} s")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    grid = M.Grid(cells, (0.3, 0.7, 0.7), device=dev)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    log(f"[bench] grid build {t_build:.2f} s, cells per level {grid.cells_per_level}")
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, steps_per_cell=w.steps_per_cell,
+                       adaptive=w.adaptive, schedule=args.schedule, block_size=args.block,
+                       waves_per_cu=args.waves_per_cu, batch=args.batch)
+    n_rays = cfg.n_rays()
+    out = M.alloc_outputs(n_rays, dev)
+    ws = None
+    for i in range(args.warmup):
+        r = M.cast(grid, cfg, out, ws)
+        ws = r["_ws"]
+    torch.cuda.synchronize()
+    n_steps = out["n_steps"].to(torch.int64)
+    ray_steps = int(n_steps.sum().item())
+    status = torch.bincount(out["status"].to(torch.int64), minlength=4).tolist()
+    log(f"[bench] {ray_steps} ray-steps per cast; statuses {status}; steps/ray "
+        f"min {int(n_steps.min())} mean {ray_steps / n_rays:.1f} max {int(n_steps.max())}")
+
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record(stream)
+        r = M.cast(grid, cfg, out, ws)
+        ws = r["_ws"]
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_per_step = wall * 1e3 / args.steps
+    value = ray_steps * args.steps / wall
+    kern_s = float(np.mean(launch_ms)) / 1e3
+    achieved = FLOPS_PER_RAY_STEP * ray_steps / kern_s / 1e12
+    log(f"[bench] {args.steps} casts in {wall:.3f} s: {value / 1e9:.2f} G ray-steps/s, "
+        f"launch mean {np.mean(launch_ms):.2f} ms (min {np.min(launch_ms):.2f}, max {np.max(launch_ms):.2f})")
+
+    traffic = traffic_from_profiles(w.name)
+    res = {
+        "metric": "ray-steps/sec + rays/sec to z_src at 1 GPU; adjoint/forward cost ratio",
+        "value": value,
+        "unit": "ray-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": {"amr": "AMR 128^3 coarse + 3 levels, 786432 rays (nside 256) to z = 1, "
+                                "4 steps per leaf cell",
+                         "uniform": "uniform 64^3, 3072 rays (nside 16) to z = 0.5, 10 steps per cell",
+                         "batched": "64 cones x 16384 rays on the 64^3 grid, z_src in [0.1, 2]"}.get(w.name, w.name),
+            "cells": int(cells.n_cells), "rays": n_rays, "ray_steps_per_cast": ray_steps,
+            "steps_per_cell": w.steps_per_cell, "adaptive": bool(w.adaptive),
+        },
+        "rays_per_s": n_rays * args.steps / wall,
+        "adjoint_forward_ratio": None,
+        "grid_build_s": t_build,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS,
+                     "traffic": traffic, "kernel": "cast_kernel",
+                     "launch_ms_mean": float(np.mean(launch_ms))},
+    }
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        env = os.environ.get("OMP_NUM_THREADS")
+        if env and env.isdigit():
+            threads = min(threads, int(env))
+        log(f"[bench] CPU baseline: oracle on every {args.cpu_stride}th ray with {threads} threads")
+        res["cpu_baseline"] = cpu_baseline(w, cells, args.cpu_stride, threads)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -217,7 +217,7 @@ class HaloSet:
     rho/rhobar = D0 / (y (1+y)^2) inside R."""
 
     def __init__(self, box, seed, n_halo, phi_range=(1e-6, 3e-5), rs_range=(0.2, 1.5),
-                 trunc=8.0, dens_norm=1.0, centres=None):
+                 trunc=25.0, dens_norm=1.0, centres=None):
         rng = _rng(seed)
         self.box = float(box)
         self.pos = (rng.uniform(0, box, size=(n_halo, 3)) if centres is None
@@ -231,16 +231,32 @@ class HaloSet:
         # (Poisson: Phi ~ rho rs^2); dens_norm tunes the refined volume
         self.d0 = dens_norm * self.p0 / self.rs ** 2 * 1e5
 
-    def _iter_near(self, x, lo_cell):
-        """Yield (halo index, indices of x within the halo truncation radius)."""
+    def _iter_near(self, x, lo_cell=None):
+        """Yield (halo index, indices of x within the halo truncation radius,
+        minimum-image separations, distances).  Points are bucketed on a
+        periodic grid of cells no smaller than the largest radius, so each
+        halo only inspects the 27 buckets around it."""
         box = self.box
+        nb = max(1, int(box // max(self.R.max(), 1e-9)))
+        bsz = box / nb
+        bidx = np.floor(np.mod(x, box) / bsz).astype(np.int64) % nb
+        key = (bidx[:, 0] * nb + bidx[:, 1]) * nb + bidx[:, 2]
+        order = np.argsort(key, kind="stable")
+        skey = key[order]
+        starts = np.searchsorted(skey, np.arange(nb ** 3 + 1))
+        offs = np.array([(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
         for h in range(len(self.pos)):
-            d = x - self.pos[h]
+            hb = np.floor(np.mod(self.pos[h], box) / bsz).astype(np.int64) % nb
+            nbk = np.unique(((hb[None, :] + offs) % nb) @ np.array([nb * nb, nb, 1]))
+            cand = np.concatenate([order[starts[b]:starts[b + 1]] for b in nbk])
+            if cand.size == 0:
+                continue
+            d = x[cand] - self.pos[h]
             d -= box * np.round(d / box)
             r2 = np.einsum("ij,ij->i", d, d)
-            sel = np.nonzero(r2 < self.R[h] ** 2)[0]
-            if sel.size:
-                yield h, sel, d[sel], np.sqrt(r2[sel])
+            m = r2 < self.R[h] ** 2
+            if m.any():
+                yield h, cand[m], d[m], np.sqrt(r2[m])
 
     def potential(self, x):
         phi = np.zeros(len(x))
@@ -257,11 +273,23 @@ class HaloSet:
             grad[sel] += (dphidr / np.maximum(r, 1e-12))[:, None] * d
         return phi, grad
 
-    def density(self, x):
+    def density(self, x, half=0.0):
+        """Halo density at the point of the cube of half-width `half` around
+        each x that is closest to the halo centre (so a cell is refined when
+        any part of it is dense enough)."""
         rho = np.zeros(len(x))
-        for h, sel, d, r in self._iter_near(x, None):
-            y = np.maximum(r / self.rs[h], 1e-3)
-            rho[sel] += self.d0[h] / (y * (1.0 + y) ** 2)
+        Rext = self.R + np.sqrt(3.0) * half
+        saved = self.R
+        self.R = Rext
+        try:
+            for h, sel, d, r in self._iter_near(x):
+                dd = np.maximum(np.abs(d) - half, 0.0)
+                rr = np.sqrt(np.einsum("ij,ij->i", dd, dd))
+                inside = rr < saved[h]
+                y = np.maximum(rr / self.rs[h], 1e-3)
+                rho[sel] += np.where(inside, self.d0[h] / (y * (1.0 + y) ** 2), 0.0)
+        finally:
+            self.R = saved
         return rho
 
 
@@ -290,7 +318,8 @@ def amr_halo_cells(n0: int, box: float, max_level: int, seed: int, n_halo: int =
             gb = g.reshape(-1)
         else:
             gb = _cic_sample_periodic(g, x, box)
-        rho = np.exp(-gb - 0.5) + halos.density(x)   # wells (Phi < 0) are overdense
+        half = 0.5 * box / (n0 * 2 ** lev)
+        rho = np.exp(-gb - 0.5) + halos.density(x, half)   # wells (Phi < 0) are overdense
         refine = rho > threshold
         if not refine.any():
             break
@@ -361,7 +390,7 @@ def make_cells(grid: str) -> Cells:
 
 # density normalisation of the 128^3 AMR grid's haloes, chosen so the tree holds
 # about 1e7 cells (the count is recorded by the tests)
-AMR128_DENS_NORM = 1.0
+AMR128_DENS_NORM = 10000.0
 
 
 def _full_sky(nside):
