@@ -104,7 +104,10 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=128)
+    ap.add_argument("--cpu-stride", type=int, default=48)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the casts, copy MIB mebibytes once with a plain device copy "
+                         "(reference for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -139,11 +142,6 @@ def main():
         r = M.cast(grid, cfg, out, ws)
         ws = r["_ws"]
     torch.cuda.synchronize()
-    n_steps = out["n_steps"].to(torch.int64)
-    ray_steps = int(n_steps.sum().item())
-    status = torch.bincount(out["status"].to(torch.int64), minlength=4).tolist()
-    log(f"[bench] {ray_steps} ray-steps per cast; statuses {status}; steps/ray "
-        f"min {int(n_steps.min())} mean {ray_steps / n_rays:.1f} max {int(n_steps.max())}")
 
     stream = torch.cuda.current_stream(dev)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -157,12 +155,27 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_ms = [a.elapsed_time(b) for a, b in evs]
+    # every cast integrates the same rays: count the work from the last one
+    n_steps = out["n_steps"].to(torch.int64)
+    ray_steps = int(n_steps.sum().item())
+    status = torch.bincount(out["status"].to(torch.int64), minlength=4).tolist()
+    log(f"[bench] {ray_steps} ray-steps per cast; statuses {status}; steps/ray "
+        f"min {int(n_steps.min())} mean {ray_steps / n_rays:.1f} max {int(n_steps.max())}")
     ms_per_step = wall * 1e3 / args.steps
     value = ray_steps * args.steps / wall
     kern_s = float(np.mean(launch_ms)) / 1e3
     achieved = FLOPS_PER_RAY_STEP * ray_steps / kern_s / 1e12
     log(f"[bench] {args.steps} casts in {wall:.3f} s: {value / 1e9:.2f} G ray-steps/s, "
         f"launch mean {np.mean(launch_ms):.2f} ms (min {np.min(launch_ms):.2f}, max {np.max(launch_ms):.2f})")
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {nbytes} bytes copied")
 
     traffic = traffic_from_profiles(w.name)
     res = {

@@ -161,7 +161,7 @@ typedef struct {
     int64_t max_steps;          /* per ray, including the landing step                   */
     /* launch shape; 0 = library default (see mpath_autotune) */
     int32_t schedule;
-    int32_t block_size;         /* threads per block, multiple of 64, <= 1024           */
+    int32_t block_size;         /* threads per block: 0 or 256                          */
     int32_t waves_per_cu;       /* persistent schedule: resident waves per CU            */
     int32_t batch;              /* persistent schedule: rays per queue pop per wave (64k)*/
     /* adjoint support: 0 = forward only, else checkpoint every K steps */

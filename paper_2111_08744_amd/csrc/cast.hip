@@ -18,6 +18,10 @@ namespace mpath {
 namespace {
 
 constexpr int kWave = 64;
+// Occupancy target of the integration kernels: 3 waves per SIMD keeps the
+// live state in registers (measured: 2 waves without the bound, 4 waves
+// spill to scratch and run 2x slower).
+constexpr int kMinWavesPerSimd = 3;
 
 // Everything one lane carries for its current ray.
 template <bool AMR>
@@ -41,8 +45,11 @@ struct RayRun {
         while (j > 0 && a.obs[j].ray_first > r) --j;
         obs = j;
         const ObsDev& ob = a.obs[j];
-        geo.o[0] = ob.x[0]; geo.o[1] = ob.x[1]; geo.o[2] = ob.x[2];
-        healpix_nest_dir(a.nside, ob.pix_first + (r - ob.ray_first), geo.n);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) geo.uo[i] = ob.x[i] / a.grid.h0;
+        geo.n[0] = a.dirs[3 * r];
+        geo.n[1] = a.dirs[3 * r + 1];
+        geo.n[2] = a.dirs[3 * r + 2];
         eta_s = ob.eta_s;
         F.reset();
         n_steps = 0;
@@ -50,7 +57,7 @@ struct RayRun {
         status = -1;
         float G[3];
         int leafl, l;
-        if (F.eval(a.grid, geo.o, phi_o, G, leafl, l)) {
+        if (F.eval(a.grid, geo.uo, phi_o, G, leafl, l)) {
             status = MPATH_RAY_LEFT_DOMAIN;
             phi_o = __builtin_nanf("");
         }
@@ -59,7 +66,6 @@ struct RayRun {
         const double kmag = sqrt((1.0 + 2.0 * po) / (1.0 - 2.0 * po));
         y.eta = a.cosmo_eta0;
         y.K = 1.0;
-        y.s = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             y.d[i] = (float)(geo.n[i] * (kmag - 1.0));
@@ -75,13 +81,13 @@ struct RayRun {
         for (int it = 0; it < max_iter; ++it) {
             if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return true; }
             // leaf level at the step start sets the step length (N steps per cell)
-            double x[3];
-            position(geo, y.s, y.dx, x);
+            double u[3];
+            grid_coords(g, geo, y.eta, y.dx, u);
             const int Lm = AMR ? g.max_level : 0;
             const double scale = (double)(2 << Lm);
             int I[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) I[d] = (int)floor((x[d] / g.h0) * scale);
+            for (int d = 0; d < 3; ++d) I[d] = (int)floor(u[d] * scale);
             const int L = F.leaf(g, I);
             if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
             hash = fnv(hash, (uint32_t)L);
@@ -115,47 +121,18 @@ struct RayRun {
         return false;
     }
 
-    // Observables (lens equation, Sect. 2.3; redshifts, Sect. 2.5).
+    // Redshift observables (Sect. 2.5) and the end state; the angular
+    // observables follow in observables_kernel, which keeps the FP64
+    // transcendental functions out of the integration kernel's registers.
     __device__ __forceinline__ void finish(const CastArgs& a)
     {
         const ObsDev& ob = a.obs[obs];
-        double r[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) r[i] = y.s * geo.n[i] + (double)y.dx[i];
-        double x[3];
-        position(geo, y.s, y.dx, x);
+        double u[3];
+        grid_coords(a.grid, geo, y.eta, y.dx, u);
         float phi_s = __builtin_nanf(""), G[3];
         int leafl, l;
-        if (F.eval(a.grid, x, phi_s, G, leafl, l)) phi_s = __builtin_nanf("");
-        const double chi = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        if (F.eval(a.grid, u, phi_s, G, leafl, l)) phi_s = __builtin_nanf("");
         const OutDev& o = a.out;
-        if (o.beta) {
-            o.beta[2 * ray] = atan2(hypot(r[0], r[1]), r[2]);
-            o.beta[2 * ray + 1] = atan2(r[1], r[0]);
-        }
-        if (o.alpha) {
-            const double* n = geo.n;
-            double rh[3] = {r[0] / chi, r[1] / chi, r[2] / chi};
-            const double c = rh[0] * n[0] + rh[1] * n[1] + rh[2] * n[2];
-            double t[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) t[i] = rh[i] - c * n[i];
-            const double st2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-            double fac = 0.0;
-            if (st2 > 0.0) {
-                const double st = sqrt(st2);
-                fac = -atan2(st, c) / st;
-            }
-            const double ph = atan2(n[1], n[0]);
-            const double th = atan2(hypot(n[0], n[1]), n[2]);
-            double sp, cp, stt, ctt;
-            sincos(ph, &sp, &cp);
-            sincos(th, &stt, &ctt);
-            const double e1[3] = {-sp, cp, 0.0};
-            const double e2[3] = {-cp * ctt, -sp * ctt, stt};
-            o.alpha[2 * ray] = (float)(fac * (t[0] * e1[0] + t[1] * e1[1] + t[2] * e1[2]));
-            o.alpha[2 * ray + 1] = (float)(fac * (t[0] * e2[0] + t[1] * e2[1] + t[2] * e2[2]));
-        }
         const bool ok = status == MPATH_RAY_REACHED;
         if (o.z5)
             o.z5[ray] = ok ? ob.a_s * y.K * (1.0 + (double)phi_s) / (1.0 + (double)phi_o) - 1.0
@@ -165,26 +142,95 @@ struct RayRun {
         if (o.n_steps) o.n_steps[ray] = (int32_t)n_steps;
         if (o.status) o.status[ray] = status;
         if (o.hash) o.hash[ray] = hash;
-        if (o.chi) o.chi[ray] = chi;
+        RayEnd e;
+        e.eta = y.eta;
+        e.dx[0] = y.dx[0]; e.dx[1] = y.dx[1]; e.dx[2] = y.dx[2];
+        e.obs = obs;
+        a.ends[ray] = e;
     }
 };
 
-template <bool AMR>
-__global__ __launch_bounds__(256) void cast_static_kernel(CastArgs a)
+// Initial directions: HEALPix NESTED pixel centres (Sect. 2.4), computed once
+// per cast so that the integration kernel does not carry the FP64 sincos.
+__global__ __launch_bounds__(256) void ray_dirs_kernel(CastArgs a)
 {
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ray >= a.n_rays) return;
+    int j = a.n_obs - 1;
+    while (j > 0 && a.obs[j].ray_first > ray) --j;
+    const ObsDev& ob = a.obs[j];
+    double n[3];
+    healpix_nest_dir(a.nside, ob.pix_first + (ray - ob.ray_first), n);
+    a.dirs[3 * ray] = n[0];
+    a.dirs[3 * ray + 1] = n[1];
+    a.dirs[3 * ray + 2] = n[2];
+}
+
+// Lens equation (Sect. 2.3): beta from the end point r = x_s - x_obs, and the
+// deflection alpha = theta - beta as the tangent vector at theta pointing
+// away from beta with the great-circle angle as length, on e1 = e_phi,
+// e2 = -e_theta.
+__global__ __launch_bounds__(256) void observables_kernel(CastArgs a)
+{
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ray >= a.n_rays) return;
+    const RayEnd e = a.ends[ray];
+    const double n[3] = {a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]};
+    const double s = a.cosmo_eta0 - e.eta;
+    double r[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r[i] = s * n[i] + (double)e.dx[i];
+    const double chi = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const OutDev& o = a.out;
+    if (o.chi) o.chi[ray] = chi;
+    if (o.beta) {
+        o.beta[2 * ray] = atan2(hypot(r[0], r[1]), r[2]);
+        o.beta[2 * ray + 1] = atan2(r[1], r[0]);
+    }
+    if (o.alpha) {
+        const double rh[3] = {r[0] / chi, r[1] / chi, r[2] / chi};
+        const double c = rh[0] * n[0] + rh[1] * n[1] + rh[2] * n[2];
+        double t[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) t[i] = rh[i] - c * n[i];
+        const double st2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+        double fac = 0.0;
+        if (st2 > 0.0) {
+            const double st = sqrt(st2);
+            fac = -atan2(st, c) / st;
+        }
+        const double ph = atan2(n[1], n[0]);
+        const double th = atan2(hypot(n[0], n[1]), n[2]);
+        double sp, cp, stt, ctt;
+        sincos(ph, &sp, &cp);
+        sincos(th, &stt, &ctt);
+        const double e1[3] = {-sp, cp, 0.0};
+        const double e2[3] = {-cp * ctt, -sp * ctt, stt};
+        o.alpha[2 * ray] = (float)(fac * (t[0] * e1[0] + t[1] * e1[1] + t[2] * e1[2]));
+        o.alpha[2 * ray + 1] = (float)(fac * (t[0] * e2[0] + t[1] * e2[1] + t[2] * e2[2]));
+    }
+}
+
+template <bool AMR>
+__global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_static_kernel(CastArgs a)
+{
+    extern __shared__ float coef_lds[];
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.n_rays) return;
     RayRun<AMR> R;
+    R.F.bind(coef_lds + threadIdx.x);
     R.start(a, r);
     R.advance(a, 0x7fffffff);
     R.finish(a);
 }
 
 template <bool AMR>
-__global__ __launch_bounds__(256) void cast_persistent_kernel(CastArgs a)
+__global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_persistent_kernel(CastArgs a)
 {
+    extern __shared__ float coef_lds[];
     const int lane = threadIdx.x & (kWave - 1);
     RayRun<AMR> R;
+    R.F.bind(coef_lds + threadIdx.x);
     R.ray = -1;
     bool exhausted = false;
     for (;;) {
@@ -225,10 +271,25 @@ hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s)
 {
     if (a.n_rays == 0) return hipSuccess;
     const int64_t blocks = (a.n_rays + block - 1) / block;
+    const size_t lds = (size_t)32 * block * sizeof(float);
     if (a.grid.max_level > 0)
-        hipLaunchKernelGGL(cast_static_kernel<true>, dim3((unsigned)blocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL(cast_static_kernel<true>, dim3((unsigned)blocks), dim3(block), lds, s, a);
     else
-        hipLaunchKernelGGL(cast_static_kernel<false>, dim3((unsigned)blocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL(cast_static_kernel<false>, dim3((unsigned)blocks), dim3(block), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ray_dirs(const CastArgs& a, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    hipLaunchKernelGGL(ray_dirs_kernel, dim3((unsigned)((a.n_rays + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(const CastArgs& a, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    hipLaunchKernelGGL(observables_kernel, dim3((unsigned)((a.n_rays + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -236,18 +297,20 @@ hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipS
 {
     if (a.n_rays == 0) return hipSuccess;
     hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, a.queue);
+    const size_t lds = (size_t)32 * block * sizeof(float);
     if (a.grid.max_level > 0)
-        hipLaunchKernelGGL(cast_persistent_kernel<true>, dim3(blocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL(cast_persistent_kernel<true>, dim3(blocks), dim3(block), lds, s, a);
     else
-        hipLaunchKernelGGL(cast_persistent_kernel<false>, dim3(blocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL(cast_persistent_kernel<false>, dim3(blocks), dim3(block), lds, s, a);
     return hipGetLastError();
 }
 
 int cast_occupancy_blocks_per_cu(int block, bool amr)
 {
     int nb = 0;
-    hipError_t e = amr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<true>, block, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<false>, block, 0);
+    const size_t lds = (size_t)32 * block * sizeof(float);
+    hipError_t e = amr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<true>, block, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<false>, block, lds);
     return e == hipSuccess ? nb : 0;
 }
 

@@ -9,6 +9,7 @@
 namespace mpath {
 
 constexpr uint32_t kFnvOffset = 2166136261u;
+constexpr int kBlock = 256;       // threads per block of the integration kernels
 constexpr uint32_t kFnvPrime = 16777619u;
 
 __device__ __forceinline__ uint32_t fnv(uint32_t h, uint32_t v) { return (h ^ v) * kFnvPrime; }
@@ -65,23 +66,43 @@ __device__ inline void healpix_nest_dir(int64_t nside, int64_t pix, double v[3])
     v[2] = z;
 }
 
-// Conformal Hubble rate a'/a at eta: cubic Hermite on the uniform table.
-__device__ __forceinline__ double conformal_hubble(const CosmoDev& c, double eta)
-{
-    if (c.is_static) return 0.0;
-    const double u = (eta - c.eta_lo) * c.inv_deta;
-    int i = (int)floor(u);
-    i = i < 0 ? 0 : (i > c.n - 2 ? c.n - 2 : i);
-    const double t = u - (double)i;
-    const double2 p0 = c.table[i];
-    const double2 p1 = c.table[i + 1];
-    const double t2 = t * t, t3 = t2 * t;
-    const double h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
-    const double h10 = t3 - 2.0 * t2 + t;
-    const double h01 = 3.0 * t2 - 2.0 * t3;
-    const double h11 = t3 - t2;
-    return h00 * p0.x + h01 * p1.x + c.deta * (h10 * p0.y + h11 * p1.y);
-}
+// Conformal Hubble rate a'/a near a conformal time eta_n: the cubic Hermite
+// interpolant of the uniform table on the interval holding eta_n, re-expanded
+// about eta_n, so that the sub-steps of one RK4 step (|eta - eta_n| <= one
+// step, less than the table spacing) evaluate it with three FMAs.  Outside
+// its interval the cubic deviates from the Hermite interpolant of the
+// neighbouring interval by O(h^4 H'''') ~ 1e-18.
+struct HubbleCubic {
+    double b0, b1, b2, b3;   // H(eta_n + tau h) = b0 + tau (b1 + tau (b2 + tau b3))
+    double eta_n;
+
+    __device__ __forceinline__ void init(const CosmoDev& c, double eta)
+    {
+        eta_n = eta;
+        if (c.is_static) { b0 = b1 = b2 = b3 = 0.0; return; }
+        const double u = (eta - c.eta_lo) * c.inv_deta;
+        int i = (int)floor(u);
+        i = i < 0 ? 0 : (i > c.n - 2 ? c.n - 2 : i);
+        const double t = u - (double)i;
+        const double2 p0 = c.table[i];
+        const double2 p1 = c.table[i + 1];
+        // Hermite cubic in t: a0 + a1 t + a2 t^2 + a3 t^3
+        const double a0 = p0.x, a1 = c.deta * p0.y;
+        const double a2 = 3.0 * (p1.x - p0.x) - c.deta * (2.0 * p0.y + p1.y);
+        const double a3 = 2.0 * (p0.x - p1.x) + c.deta * (p0.y + p1.y);
+        // Taylor coefficients about t
+        b0 = a0 + t * (a1 + t * (a2 + t * a3));
+        b1 = a1 + t * (2.0 * a2 + 3.0 * t * a3);
+        b2 = a2 + 3.0 * t * a3;
+        b3 = a3;
+    }
+
+    __device__ __forceinline__ double operator()(const CosmoDev& c, double eta) const
+    {
+        const double tau = (eta - eta_n) * c.inv_deta;
+        return b0 + tau * (b1 + tau * (b2 + tau * b3));
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Octree lookups.  Integer cell coordinates are kept unwrapped (a periodic
@@ -107,23 +128,69 @@ __device__ __forceinline__ int lookup_cell(const GridDev& g, int l, int J0, int 
     return id;
 }
 
+// Level of a cell id (ids are level-major).  Unrolled comparisons keep the
+// level table in scalar registers (a dynamically indexed array would be
+// copied to vector registers).
+__device__ __forceinline__ int level_of(const GridDev& g, int id)
+{
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxLevels; ++k) l += (k <= g.max_level && id >= g.level_start[k]) ? 1 : 0;
+    return l;
+}
+
+// Trilinear coefficients of the 8 corner payloads v[o] (o = ox + 2 oy + 4 oz):
+// f(t) = c0 + c1 tx + c2 ty + c3 tz + c4 tx ty + c5 tx tz + c6 ty tz + c7 tx ty tz,
+// which equals sum_o prod_d W_CIC(t_d - o_d) v[o] for t in [0, 1]^3.
+__device__ __forceinline__ void trilinear_coefficients(const float4 v[8], float4 c[8])
+{
+#define MPATH_TRI(f)                                                       \
+    {                                                                      \
+        const float c1 = v[1].f - v[0].f, c2 = v[2].f - v[0].f;            \
+        const float c4 = v[3].f - v[2].f - c1;                             \
+        c[0].f = v[0].f;                                                   \
+        c[1].f = c1;                                                       \
+        c[2].f = c2;                                                       \
+        c[3].f = v[4].f - v[0].f;                                          \
+        c[4].f = c4;                                                       \
+        c[5].f = v[5].f - v[4].f - c1;                                     \
+        c[6].f = v[6].f - v[4].f - c2;                                     \
+        c[7].f = v[7].f - v[6].f - v[5].f + v[4].f - c4;                   \
+    }
+    MPATH_TRI(x) MPATH_TRI(y) MPATH_TRI(z) MPATH_TRI(w)
+#undef MPATH_TRI
+}
+
+__device__ __forceinline__ float trilinear_eval(float c0, float c1, float c2, float c3, float c4, float c5,
+                                                float c6, float c7, float tx, float ty, float tz)
+{
+    return c0 + tx * (c1 + ty * (c4 + tz * c7) + tz * c5) + ty * (c2 + tz * c6) + tz * c3;
+}
+
 // Field value interpolated at one point, with the lane's cache of the leaf
-// cell and of the last resolved 8-cell stencil (with its payload).
+// cell and of the last resolved 8-cell stencil (as trilinear coefficients).
 //
 // Reuse is exact: the leaf level of x only changes when x leaves the cached
 // leaf cell, and for x inside a leaf cell of level L the CIC base at every
 // level l <= L is a function of floor(x / h_{L+1}) alone (the half of the
 // leaf cell x lies in per axis), so the resolved stencil is a function of
-// (L, floor(x / h_{L+1})).
+// (leaf cell, floor(x / h_{L+1})); the build precomputes it per half-cell.
 template <bool AMR>
 struct FieldCache {
     int leafL;          // level of the cached leaf cell (-1: none)
+    int leafId;         // its id
     int leafI[3];       // its unwrapped coordinates at level leafL
     int keyL;           // leaf level the stencil was resolved for (-1: none)
     int key[3];         // unwrapped coordinates at level keyL + 1
     int lvl;            // level of the resolved stencil
-    int b[3];           // its unwrapped base (lowest corner) at level lvl
-    float4 v[8];        // payload of the 8 cells, octant o = ox + 2 oy + 4 oz
+    float* c;           // trilinear coefficients in LDS: coefficient k of
+                        // component f (phi, gx, gy, gz) at c[(8 f + k) * kBlock]
+    static constexpr int cstride = kBlock;
+
+    // lds: this lane's first slot; lanes of a block are kBlock words apart
+    // per coefficient, so the 64 lanes of a wave touch 64 consecutive words
+    // for every (f, k) (no bank conflicts) at compile-time offsets
+    __device__ __forceinline__ void bind(float* lds) { c = lds; }
 
     __device__ __forceinline__ void reset()
     {
@@ -131,8 +198,8 @@ struct FieldCache {
         keyL = -1;
     }
 
-    // Leaf level at the point with unwrapped finest+1 coordinates I (level
-    // max_level + 1); -1 outside a non-periodic box.
+    // Leaf level at the point with unwrapped coordinates I at level
+    // max_level + 1; -1 outside a non-periodic box.
     __device__ __forceinline__ int leaf(const GridDev& g, const int I[3])
     {
         if (!AMR) {
@@ -165,6 +232,7 @@ struct FieldCache {
             ++L;
         }
         leafL = L;
+        leafId = id;
         const int sh = Lm + 1 - L;
         leafI[0] = I[0] >> sh; leafI[1] = I[1] >> sh; leafI[2] = I[2] >> sh;
         return L;
@@ -178,98 +246,112 @@ struct FieldCache {
         const int sh = Lm - L;                   // I is at level Lm + 1
         const int k0 = I[0] >> sh, k1 = I[1] >> sh, k2 = I[2] >> sh;
         if (keyL == L && k0 == key[0] && k1 == key[1] && k2 == key[2]) return true;
-        for (int l = L; l >= 0; --l) {
-            const int s = Lm - l;
-            const int b0 = ((I[0] >> s) - 1) >> 1;
-            const int b1 = ((I[1] >> s) - 1) >> 1;
-            const int b2 = ((I[2] >> s) - 1) >> 1;
-            int ids[8];
-            bool ok = true;
-#pragma unroll
-            for (int o = 0; o < 8; ++o) {
-                ids[o] = lookup_cell(g, l, b0 + (o & 1), b1 + ((o >> 1) & 1), b2 + (o >> 2));
-                ok = ok && ids[o] >= 0;
+        int base, l;
+        if (AMR) {
+            base = g.leafinfo[8 * leafId + ((k0 & 1) | ((k1 & 1) << 1) | ((k2 & 1) << 2))];
+            if (base < 0) return false;
+            l = level_of(g, base);
+        } else {
+            l = 0;
+            int b0 = (k0 - 1) >> 1, b1 = (k1 - 1) >> 1, b2 = (k2 - 1) >> 1;
+            const int M = g.n0;
+            if (g.periodic) {
+                b0 &= M - 1; b1 &= M - 1; b2 &= M - 1;
+            } else if ((unsigned)b0 >= (unsigned)(M - 1) || (unsigned)b1 >= (unsigned)(M - 1) ||
+                       (unsigned)b2 >= (unsigned)(M - 1)) {
+                return false;                     // b + 1 must exist too
             }
-            if (!ok) continue;
-#pragma unroll
-            for (int o = 0; o < 8; ++o) v[o] = g.payload[ids[o]];
-            lvl = l;
-            b[0] = b0; b[1] = b1; b[2] = b2;
-            keyL = L;
-            key[0] = k0; key[1] = k1; key[2] = k2;
-            return true;
+            base = (int)morton3((uint32_t)b0, (uint32_t)b1, (uint32_t)b2);
         }
-        return false;
+        const float4* rec = g.dual + 8 * (int64_t)base;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const float4 q = rec[o];
+            c[(0 + o) * cstride] = q.x;
+            c[(8 + o) * cstride] = q.y;
+            c[(16 + o) * cstride] = q.z;
+            c[(24 + o) * cstride] = q.w;
+        }
+        lvl = l;
+        keyL = L;
+        key[0] = k0; key[1] = k1; key[2] = k2;
+        return true;
     }
 
-    // Phi and grad Phi at x (CIC, Eq. W_CIC, with the level fallback).
-    // Returns 0, or 1 when no complete stencil exists.  *leaf_level and
-    // *stencil_level receive the levels of the deepest cell containing x and
-    // of the stencil used.
-    __device__ __forceinline__ int eval(const GridDev& g, const double x[3], float& phi, float G[3],
+    // Phi and grad Phi at the point with coarse-grid coordinates u (CIC,
+    // Eq. W_CIC, with the level fallback).  Returns 0, or 1 when no complete
+    // stencil exists.  leaf_level and stencil_level receive the levels of the
+    // deepest cell containing the point and of the stencil used.
+    __device__ __forceinline__ int eval(const GridDev& g, const double u[3], float& phi, float G[3],
                                         int& leaf_level, int& stencil_level)
     {
         const int Lm = AMR ? g.max_level : 0;
         const double scale = (double)(2 << Lm);      // 2^(Lm+1)
-        double u[3];
         int I[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            u[d] = x[d] / g.h0;                      // coarse-grid coordinates
-            I[d] = (int)floor(u[d] * scale);
-        }
+        for (int d = 0; d < 3; ++d) I[d] = (int)floor(u[d] * scale);
         const int L = leaf(g, I);
         leaf_level = L;
         if (L < 0) return 1;
         if (!stencil(g, L, I)) return 1;
         stencil_level = lvl;
+        // offsets from the stencil base (lowest corner) at level lvl
+        const int s = Lm - lvl;
         const double sl = (double)(1 << lvl);
-        const float tx = (float)(u[0] * sl - 0.5 - (double)b[0]);
-        const float ty = (float)(u[1] * sl - 0.5 - (double)b[1]);
-        const float tz = (float)(u[2] * sl - 0.5 - (double)b[2]);
-        // trilinear interpolation of the 8 payloads (weights (1-t) or t per axis)
-        const float4 c00 = lerp4(v[0], v[1], tx), c10 = lerp4(v[2], v[3], tx);
-        const float4 c01 = lerp4(v[4], v[5], tx), c11 = lerp4(v[6], v[7], tx);
-        const float4 c0 = lerp4(c00, c10, ty), c1 = lerp4(c01, c11, ty);
-        const float4 r = lerp4(c0, c1, tz);
-        phi = r.x;
-        G[0] = r.y; G[1] = r.z; G[2] = r.w;
+        const float tx = (float)(u[0] * sl - 0.5 - (double)(((I[0] >> s) - 1) >> 1));
+        const float ty = (float)(u[1] * sl - 0.5 - (double)(((I[1] >> s) - 1) >> 1));
+        const float tz = (float)(u[2] * sl - 0.5 - (double)(((I[2] >> s) - 1) >> 1));
+        // f = c0 + tx (c1 + ty (c4 + tz c7) + tz c5) + ty (c2 + tz c6) + tz c3
+        float f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float* k = c + 8 * q * cstride;
+            const float k0 = k[0], k1 = k[cstride], k2 = k[2 * cstride], k3 = k[3 * cstride];
+            const float k4 = k[4 * cstride], k5 = k[5 * cstride], k6 = k[6 * cstride], k7 = k[7 * cstride];
+            f[q] = trilinear_eval(k0, k1, k2, k3, k4, k5, k6, k7, tx, ty, tz);
+        }
+        phi = f[0];
+        G[0] = f[1];
+        G[1] = f[2];
+        G[2] = f[3];
         return 0;
-    }
-
-    static __device__ __forceinline__ float4 lerp4(const float4 a, const float4 b, float t)
-    {
-        const float s = 1.0f - t;
-        return make_float4(s * a.x + t * b.x, s * a.y + t * b.y, s * a.z + t * b.z, s * a.w + t * b.w);
     }
 };
 
 // ---------------------------------------------------------------------------
-// Geodesic state in the split representation.  With K = -k0 > 0 and
-// k = K (n + d), x = x_obs + s n + dx, the null geodesic equations of
+// Geodesic state in the split representation.  With K = -k0 > 0,
+// k = K (n + d) and x = x_obs + s n + dx, the null geodesic equations of
 // Sect. 2.2 (dPhi/dlambda = grad Phi . k, dPhi/deta = 0) become
 //   d eta/dl = -K,  ds/dl = K,  d dx/dl = K d,
 //   dK/dl = 2 H K^2 - 2 K^2 (m.G),                          m = n + d, G = grad Phi
 //   d(K d)/dl - n dK/dl = K^2 [4 (m.G) m - 2 G + 2 (H - m.G) d]   (=: P)
-// RK4 is applied to (eta, K, s, dx, K d): d at a stage or at the step end is
+// RK4 is applied to (eta, K, dx, K d): d at a stage or at the step end is
 // (K_n d_n + c dl P)/K.  This is the same RK4 as on (eta, x, k0, k), since
 // the map between the two is linear given K, and it keeps only small
-// quantities (d ~ deflection, dx ~ transverse displacement) in FP32.
+// quantities (d ~ deflection, dx ~ transverse displacement) in FP32.  The
+// path coordinate s has the same increments as -eta, so s = eta_0 - eta
+// exactly and is not carried.
 // ---------------------------------------------------------------------------
 struct GeoState {
-    double eta, K, s;
+    double eta, K;
     float d[3], dx[3];
 };
 
 struct RayGeom {
-    double o[3];        // observer
+    double uo[3];       // observer in coarse-grid coordinates (x_obs / h0)
     double n[3];        // initial direction (unit)
 };
 
-__device__ __forceinline__ void position(const RayGeom& r, double s, const float dx[3], double x[3])
+// Coarse-grid coordinates u = x / h0 of x = x_obs + s n + dx, s = eta0 - eta.
+// The observer term is the exact quotient; the displacement is scaled by
+// 1/h0 (at the observer both agree exactly with x / h0, elsewhere to one
+// rounding).
+__device__ __forceinline__ void grid_coords(const GridDev& g, const RayGeom& r, double eta, const float dx[3],
+                                            double u[3])
 {
+    const double s = g.eta0 - eta;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) x[i] = r.o[i] + (s * r.n[i] + (double)dx[i]);
+    for (int i = 0; i < 3; ++i) u[i] = r.uo[i] + (s * r.n[i] + (double)dx[i]) * g.inv_h0;
 }
 
 // One RK4 step of affine length dl from y into out.  The four stencil levels
@@ -280,11 +362,14 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
                                         uint32_t& hash)
 {
     const float nf[3] = {(float)r.n[0], (float)r.n[1], (float)r.n[2]};
-    double acc_eta = 0.0, acc_K = 0.0, acc_s = 0.0;
+    double acc_eta = 0.0, acc_K = 0.0;
     float acc_dx[3] = {0.f, 0.f, 0.f}, acc_P[3] = {0.f, 0.f, 0.f};
-    double f_eta = 0.0, f_K = 0.0, f_s = 0.0;
+    double f_K = 0.0, Kprev = y.K;
     float f_dx[3] = {0.f, 0.f, 0.f}, f_P[3] = {0.f, 0.f, 0.f};
+    const float yKf = (float)y.K;
     uint32_t h = hash;
+    HubbleCubic Hc;
+    Hc.init(cz, y.eta);
 #pragma unroll 1
     for (int st = 0; st < 4; ++st) {
         GeoState yi;
@@ -292,30 +377,29 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
             yi = y;
         } else {
             const double c = (st == 3 ? 1.0 : 0.5) * dl;
-            yi.eta = y.eta + c * f_eta;
+            yi.eta = y.eta - c * Kprev;            // f_eta = -K of the previous stage
             yi.K = y.K + c * f_K;
-            yi.s = y.s + c * f_s;
             const float cf = (float)c;
-            const float ratio = (float)(y.K / yi.K);
-            const float cK = (float)(c / yi.K);
+            const float inv = 1.0f / (float)yi.K;
+            const float ratio = yKf * inv;
+            const float cK = cf * inv;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 yi.dx[i] = y.dx[i] + cf * f_dx[i];
                 yi.d[i] = ratio * y.d[i] + cK * f_P[i];
             }
         }
-        double x[3];
-        position(r, yi.s, yi.dx, x);
+        double u[3];
+        grid_coords(g, r, yi.eta, yi.dx, u);
         float phi, G[3];
         int leafl, l;
-        if (F.eval(g, x, phi, G, leafl, l)) return 1;
+        if (F.eval(g, u, phi, G, leafl, l)) return 1;
         h = fnv(h, (uint32_t)l);
-        const double H = conformal_hubble(cz, yi.eta);
+        const double H = Hc(cz, yi.eta);
         const float m[3] = {nf[0] + yi.d[0], nf[1] + yi.d[1], nf[2] + yi.d[2]};
         const float mG = m[0] * G[0] + m[1] * G[1] + m[2] * G[2];
-        f_eta = -yi.K;
+        Kprev = yi.K;
         f_K = yi.K * yi.K * (2.0 * H - 2.0 * (double)mG);
-        f_s = yi.K;
         const float Kf = (float)yi.K;
         const float K2 = Kf * Kf;
         const float hm = 2.0f * ((float)H - mG);
@@ -326,9 +410,8 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
         }
         const double w = (st == 0 || st == 3) ? 1.0 : 2.0;
         const float wf = (float)w;
-        acc_eta += w * f_eta;
+        acc_eta -= w * yi.K;
         acc_K += w * f_K;
-        acc_s += w * f_s;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             acc_dx[i] += wf * f_dx[i];
@@ -338,10 +421,10 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
     const double h6 = dl / 6.0;
     out.eta = y.eta + h6 * acc_eta;
     out.K = y.K + h6 * acc_K;
-    out.s = y.s + h6 * acc_s;
     const float h6f = (float)h6;
-    const float ratio = (float)(y.K / out.K);
-    const float cK = (float)(h6 / out.K);
+    const float inv = 1.0f / (float)out.K;
+    const float ratio = yKf * inv;
+    const float cK = h6f * inv;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         out.dx[i] = y.dx[i] + h6f * acc_dx[i];
@@ -353,7 +436,7 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
 
 __device__ __forceinline__ bool finite_state(const GeoState& y)
 {
-    bool ok = isfinite(y.eta) && isfinite(y.K) && isfinite(y.s);
+    bool ok = isfinite(y.eta) && isfinite(y.K);
 #pragma unroll
     for (int i = 0; i < 3; ++i) ok = ok && isfinite(y.d[i]) && isfinite(y.dx[i]);
     return ok;

@@ -20,16 +20,35 @@ struct ObsDev {
     int64_t count;
 };
 
-// Octree on the device.  Cells are numbered coarse-first: coarse cell
+// Octree on the device.  Cells are numbered level by level: coarse cell
 // (i, j, k) has id morton3(i, j, k); the children of a refined cell c are the
-// 8 consecutive ids child[c] + octant, octant = ox + 2 oy + 4 oz.
+// 8 consecutive ids child[c] + octant, octant = ox + 2 oy + 4 oz, and blocks
+// of one level follow the order of their parents, so the ids of level l are
+// the contiguous range [level_start[l], level_start[l + 1]).
+//
+// Two derived tables make a stencil one 128-byte read:
+//   dual[c]      the trilinear coefficients c0..c7 (see device.h) of the
+//                payloads of the 8 cells (l, ijk(c) + {0,1}^3) of c's level
+//                (zeros where such a cell does not exist);
+//   leafinfo[c]  for a leaf c of level L and each half-cell q of it (the
+//                8 sub-octants, q = qx + 2 qy + 4 qz), the id of the lowest
+//                corner cell of the CIC stencil that the AMR fallback
+//                procedure selects for points in that half-cell, or -1 when
+//                no level has a complete stencil there.
+constexpr int kMaxLevels = 11;
+
 struct GridDev {
     const float4* payload;    // (phi, gx, gy, gz) per cell
     const int32_t* child;     // first child id, -1 for a leaf
+    const float4* dual;       // [n][8]
+    const int32_t* leafinfo;  // [n][8]
     double h0;                // coarse cell size
+    double inv_h0;
+    double eta0;              // conformal time at the observers (a = 1)
     int32_t n0;               // coarse cells per side (power of two)
     int32_t max_level;
     int32_t periodic;
+    int32_t level_start[kMaxLevels + 1];
 };
 
 // Conformal Hubble rate a'/a tabulated with its eta-derivative on a uniform
@@ -41,6 +60,13 @@ struct CosmoDev {
     double deta;
     int32_t n;
     int32_t is_static;
+};
+
+// End state of a ray kept between the integration and the observables kernel.
+struct RayEnd {
+    double eta;
+    float dx[3];
+    int32_t obs;
 };
 
 struct OutDev {
@@ -68,14 +94,22 @@ struct CastArgs {
     int64_t n_rays;
     OutDev out;
     unsigned long long* queue;   // persistent schedule: next ray to hand out
-    int32_t batch;               // rays per queue pop (multiple of the wave size)
+    int32_t batch;               // steps between queue refills
+    RayEnd* ends;                // [n_rays] end states for the observables kernel
+    double* dirs;                // [n_rays][3] initial directions (HEALPix pixel centres)
 };
 
 // Kernel launchers (defined in cast.hip).
 hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s);
 hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipStream_t s);
+hipError_t launch_observables(const CastArgs& a, hipStream_t s);
+hipError_t launch_ray_dirs(const CastArgs& a, hipStream_t s);
 hipError_t launch_permute_values(float4* payload, const int64_t* perm, const float4* values,
                                  int64_t n, hipStream_t s);
+// Derived tables (defined in grid.hip); cellpos[c] = (i, j, k, level).
+hipError_t launch_build_dual(const GridDev& g, const int4* cellpos, float4* dual, int64_t n, hipStream_t s);
+hipError_t launch_build_leafinfo(const GridDev& g, const int4* cellpos, int32_t* leafinfo, int64_t n,
+                                 hipStream_t s);
 int cast_occupancy_blocks_per_cu(int block, bool amr);
 
 // Morton interleave of three 10-bit coordinates (host and device).

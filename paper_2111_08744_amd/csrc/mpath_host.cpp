@@ -132,25 +132,51 @@ struct mpath_grid {
     float4* payload = nullptr;
     int32_t* child = nullptr;
     int64_t* perm = nullptr;
+    int4* cellpos = nullptr;
+    float4* dual = nullptr;
+    int32_t* leafinfo = nullptr;
     double2* table = nullptr;
+    int32_t level_start[kMaxLevels + 1] = {0};
     int num_cus = 0;
 };
 
 namespace {
 
 struct GridLayout {
-    size_t off_payload, off_child, off_perm, off_table, total;
+    size_t off_payload, off_child, off_perm, off_cellpos, off_dual, off_leafinfo, off_table, total;
 };
 
+// Device workspace of a grid: 204 bytes per cell plus the background table.
 GridLayout grid_layout(int64_t n)
 {
     GridLayout L;
     L.off_payload = 0;
     L.off_child = align_up(L.off_payload + (size_t)n * 16, 256);
     L.off_perm = align_up(L.off_child + (size_t)n * 4, 256);
-    L.off_table = align_up(L.off_perm + (size_t)n * 8, 256);
+    L.off_cellpos = align_up(L.off_perm + (size_t)n * 8, 256);
+    L.off_dual = align_up(L.off_cellpos + (size_t)n * 16, 256);
+    L.off_leafinfo = align_up(L.off_dual + (size_t)n * 128, 256);
+    L.off_table = align_up(L.off_leafinfo + (size_t)n * 32, 256);
     L.total = align_up(L.off_table + (size_t)kTableN * 16, 256);
     return L;
+}
+
+GridDev make_griddev(const mpath_grid* g)
+{
+    GridDev d;
+    std::memset(&d, 0, sizeof d);
+    d.payload = g->payload;
+    d.child = g->child;
+    d.dual = g->dual;
+    d.leafinfo = g->leafinfo;
+    d.h0 = g->box / g->n0;
+    d.inv_h0 = g->n0 / g->box;
+    d.eta0 = g->eta0;
+    d.n0 = g->n0;
+    d.max_level = g->max_level;
+    d.periodic = g->periodic;
+    for (int l = 0; l <= kMaxLevels; ++l) d.level_start[l] = g->level_start[l];
+    return d;
 }
 
 int check_grid_desc(const mpath_grid_desc* d)
@@ -159,7 +185,8 @@ int check_grid_desc(const mpath_grid_desc* d)
     if (!(d->box > 0.0) || !std::isfinite(d->box)) return fail(MPATH_ERR_INVALID_ARG, "box must be > 0");
     if (d->n0 < 1 || d->n0 > 1024 || (d->n0 & (d->n0 - 1)))
         return fail(MPATH_ERR_INVALID_ARG, "n0 must be a power of two in [1, 1024]");
-    if (d->max_level < 0 || d->max_level > 10) return fail(MPATH_ERR_INVALID_ARG, "max_level must be in [0, 10]");
+    if (d->max_level < 0 || d->max_level >= kMaxLevels)
+        return fail(MPATH_ERR_INVALID_ARG, "max_level must be in [0, 10]");
     if ((int64_t)d->n0 << d->max_level > (1 << 20))
         return fail(MPATH_ERR_INVALID_ARG, "n0 * 2^max_level must be <= 2^20");
     if (d->value_dtype != MPATH_F64 && d->value_dtype != MPATH_F32)
@@ -277,10 +304,12 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
         base_prev = base;
         base += (int64_t)cur.size();
     }
-    // ---- pack (phi, grad) as float32 in library order ----
+    // ---- pack (phi, grad) as float32 and the cell coordinates in library order ----
     std::vector<float4> payload(n);
+    std::vector<int4> cellpos(n);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t c = perm[i];
+        cellpos[i] = make_int4(d->ijk[3 * c], d->ijk[3 * c + 1], d->ijk[3 * c + 2], (int)d->level[c]);
         if (d->value_dtype == MPATH_F64) {
             const double* p = (const double*)d->phi;
             const double* g = (const double*)d->grad;
@@ -314,18 +343,32 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     G->max_level = L;
     G->periodic = d->periodic ? 1 : 0;
     G->box = d->box;
-    for (int l = 0; l <= L && l < 16; ++l) G->cells_per_level[l] = (int64_t)lev[l].size();
+    int64_t start = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        G->level_start[l] = (int32_t)start;
+        if (l <= L) {
+            G->cells_per_level[l] = (int64_t)lev[l].size();
+            start += (int64_t)lev[l].size();
+        }
+    }
     G->ws = (char*)dev_ws;
     G->payload = (float4*)(G->ws + lay.off_payload);
     G->child = (int32_t*)(G->ws + lay.off_child);
     G->perm = (int64_t*)(G->ws + lay.off_perm);
+    G->cellpos = (int4*)(G->ws + lay.off_cellpos);
+    G->dual = (float4*)(G->ws + lay.off_dual);
+    G->leafinfo = (int32_t*)(G->ws + lay.off_leafinfo);
     G->table = (double2*)(G->ws + lay.off_table);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
+    const GridDev gd = make_griddev(G);
     if ((e = hipMemcpyAsync(G->payload, payload.data(), (size_t)n * 16, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(G->child, child.data(), (size_t)n * 4, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(G->perm, perm.data(), (size_t)n * 8, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(G->cellpos, cellpos.data(), (size_t)n * 16, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(G->table, table.data(), (size_t)kTableN * 16, hipMemcpyHostToDevice, s)) ||
+        (e = launch_build_dual(gd, G->cellpos, G->dual, n, s)) ||
+        (e = launch_build_leafinfo(gd, G->cellpos, G->leafinfo, n, s)) ||
         (e = hipStreamSynchronize(s))) {
         delete G;
         return hip_fail(e, "grid upload");
@@ -363,8 +406,9 @@ int mpath_grid_get_info(const mpath_grid* g, mpath_grid_info* info)
 int mpath_grid_set_values(mpath_grid* g, const float* values, void* stream)
 {
     if (!g || !values) return fail(MPATH_ERR_INVALID_ARG, "NULL argument");
-    const hipError_t e = launch_permute_values(g->payload, g->perm, (const float4*)values, g->n_cells,
-                                               (hipStream_t)stream);
+    hipError_t e = launch_permute_values(g->payload, g->perm, (const float4*)values, g->n_cells,
+                                         (hipStream_t)stream);
+    if (!e) e = launch_build_dual(make_griddev(g), g->cellpos, g->dual, g->n_cells, (hipStream_t)stream);
     return e ? hip_fail(e, "set_values launch") : MPATH_OK;
 }
 
@@ -373,15 +417,19 @@ int mpath_grid_set_values(mpath_grid* g, const float* values, void* stream)
 namespace {
 
 struct CastLayout {
-    size_t off_obs, off_queue, total;
+    size_t off_obs, off_queue, off_ends, off_dirs, total;
 };
 
-CastLayout cast_layout(int64_t n_obs)
+// Cast workspace: observer table, queue counter, per-ray end states and
+// initial directions.
+CastLayout cast_layout(int64_t n_obs, int64_t n_rays)
 {
     CastLayout L;
     L.off_obs = 0;
     L.off_queue = align_up((size_t)n_obs * sizeof(ObsDev), 256);
-    L.total = align_up(L.off_queue + 256, 256);
+    L.off_ends = align_up(L.off_queue + 256, 256);
+    L.off_dirs = align_up(L.off_ends + (size_t)n_rays * sizeof(RayEnd), 256);
+    L.total = align_up(L.off_dirs + (size_t)n_rays * 24, 256);
     return L;
 }
 
@@ -402,8 +450,8 @@ int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_ra
     if (d->stop_kind == MPATH_STOP_REDSHIFT && g->bg.is_static)
         return fail(MPATH_ERR_INVALID_ARG, "a static background has no redshift stop");
     if (d->schedule < 0 || d->schedule > 2) return fail(MPATH_ERR_INVALID_ARG, "unknown schedule");
-    if (d->block_size && (d->block_size % 64 || d->block_size > 1024))
-        return fail(MPATH_ERR_INVALID_ARG, "block_size must be a multiple of 64, <= 1024");
+    if (d->block_size && d->block_size != 256)
+        return fail(MPATH_ERR_UNSUPPORTED, "the integration kernels run 256 threads per block (block_size 0 or 256)");
     if (d->checkpoint_every < 0) return fail(MPATH_ERR_INVALID_ARG, "checkpoint_every must be >= 0");
     const int64_t npix = 12ll * d->nside * d->nside;
     int64_t total = 0;
@@ -438,7 +486,7 @@ int mpath_cast_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, si
     int64_t n_rays;
     const int rc = check_cast_desc(g, d, &n_rays);
     if (rc) return rc;
-    *bytes = cast_layout(d->n_obs).total;
+    *bytes = cast_layout(d->n_obs, n_rays).total;
     return MPATH_OK;
 }
 
@@ -450,7 +498,7 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
     if (rc) return rc;
     if (!out) return fail(MPATH_ERR_INVALID_ARG, "out is NULL");
     if (d->checkpoint_every) return fail(MPATH_ERR_UNSUPPORTED, "checkpointing is not available in this build");
-    const CastLayout lay = cast_layout(d->n_obs);
+    const CastLayout lay = cast_layout(d->n_obs, n_rays);
     if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
     if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "cast workspace too small");
 
@@ -498,12 +546,7 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
 
     CastArgs a;
     std::memset(&a, 0, sizeof a);
-    a.grid.payload = g->payload;
-    a.grid.child = g->child;
-    a.grid.h0 = h0;
-    a.grid.n0 = g->n0;
-    a.grid.max_level = g->max_level;
-    a.grid.periodic = g->periodic;
+    a.grid = make_griddev(g);
     a.cosmo.table = g->table;
     a.cosmo.eta_lo = g->table_eta_lo;
     a.cosmo.deta = g->table_deta;
@@ -528,11 +571,15 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
     a.out.hash = out->hash;
     a.out.chi = out->chi;
     a.queue = (unsigned long long*)(ws + lay.off_queue);
+    a.ends = (RayEnd*)(ws + lay.off_ends);
+    a.dirs = (double*)(ws + lay.off_dirs);
     a.batch = d->batch > 0 ? d->batch : 32;
 
     int sched = d->schedule;
     if (sched == MPATH_SCHED_AUTO) sched = d->n_obs > 1 ? MPATH_SCHED_PERSISTENT : MPATH_SCHED_STATIC;
     const int block = d->block_size ? d->block_size : 256;
+    e = launch_ray_dirs(a, s);
+    if (e) return hip_fail(e, "ray directions launch");
     if (sched == MPATH_SCHED_STATIC) {
         e = launch_cast_static(a, block, s);
     } else {
@@ -543,6 +590,7 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
         const int blocks = std::max(1, cus * wpc / (block / 64));
         e = launch_cast_persistent(a, block, blocks, s);
     }
+    if (!e) e = launch_observables(a, s);
     if (e) return hip_fail(e, "cast launch");
     return MPATH_OK;
 }
