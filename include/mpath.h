@@ -164,7 +164,13 @@ typedef struct {
     int32_t block_size;         /* threads per block: 0 or 256                          */
     int32_t waves_per_cu;       /* persistent schedule: resident waves per CU            */
     int32_t batch;              /* persistent schedule: rays per queue pop per wave (64k)*/
-    /* adjoint support: 0 = forward only, else checkpoint every K steps */
+    /* adjoint support: 0 = forward only; K > 0 = store every ray's state
+       before steps 0, K, 2K, ... for mpath_adjoint.  A checkpointed cast runs
+       the static schedule (schedule, waves_per_cu and batch are ignored) and
+       sizes its checkpoints for at most
+       min(max_steps, 1.02 (eta_0 - eta_s) / ds_min + 16) steps per ray
+       (ds_min the smallest comoving step length), rounded up to a multiple
+       of K; a ray that would need more ends with MPATH_RAY_MAX_STEPS. */
     int32_t checkpoint_every;
 } mpath_cast_desc;
 
@@ -193,14 +199,64 @@ typedef struct {
     double* chi;
 } mpath_observables;
 
-/* Device workspace for a cast (observer table, queue counters and, when
- * checkpoint_every > 0, the checkpoints of every ray for mpath_adjoint). */
+/* Device workspace for a cast (observer table, queue counter, end states,
+ * directions and, when checkpoint_every > 0, the checkpoints of every ray
+ * for mpath_adjoint: 40 bytes per ray and checkpoint). */
 int mpath_cast_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* desc, size_t* bytes);
 
 /* Cast all rays; asynchronous on the stream except for the upload of the
  * observer table (a few bytes per observer), which completes before return. */
 int mpath_cast(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observables* out,
                void* dev_ws, size_t ws_bytes, void* stream);
+
+/* ---- reverse mode ----
+ * The derivative of the discrete map that mpath_cast computes (RK4 on the
+ * geodesic equations of Sect. 2.2 with CIC interpolation and the AMR level
+ * fallback, step length h_leaf / N, landing on the iso-eta surface), by one
+ * reverse sweep per ray over the checkpointed forward path: each segment of
+ * K steps is recomputed from its checkpoint, then traversed backwards.  The
+ * discrete decisions (leaf levels, stencils, landing) are those of the
+ * forward cast and carry no derivative.
+ *
+ * Per-ray outputs (DEVICE, length n_rays; NaN for rays whose status is not
+ * MPATH_RAY_REACHED):
+ *   jac[2][2]     distortion matrix A_ab = d beta_a / d theta_b of the lens
+ *                 equation (Sect. 2.3), beta_a measured on e1 = e_phi,
+ *                 e2 = -e_theta at the end point's direction, theta_b on the
+ *                 same basis at the initial direction (row-major: a, then b)
+ *   dz_dtheta[2]  d z5 / d theta_b
+ * Cell outputs (DEVICE, caller order, overwritten) for the scalar loss L
+ * whose per-ray cotangents are dL_dalpha[n_rays][2] (of alpha) and
+ * dL_dz[n_rays] (of z5), either may be NULL (= 0):
+ *   dL_dvalues[n_cells][4]  dL / d (phi, gx, gy, gz) of every cell
+ *   dL_dphi_total[n_cells]  uniform periodic grids whose gradient is the
+ *                           central difference (phi[i+1] - phi[i-1]) / 2h:
+ *                           dL/dphi + (difference operator)^T dL/dgrad
+ * Any output pointer may be NULL; the cell cotangents are float32 sums
+ * accumulated with atomics, so their last bits depend on the order of the
+ * additions. */
+typedef struct {
+    const float* dL_dalpha;
+    const double* dL_dz;
+    float* jac;
+    float* dz_dtheta;
+    float* dL_dvalues;
+    float* dL_dphi_total;
+} mpath_adjoint_desc;
+
+/* Device workspace of mpath_adjoint for this desc (which needs
+ * checkpoint_every > 0): K states per ray (40 B each) and 16 B per cell. */
+int mpath_adjoint_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* desc, size_t* bytes);
+
+/* Reverse sweep after a checkpointed mpath_cast with the same grid (whose
+ * values must not have changed since), the same desc and its workspace
+ * cast_ws; fwd gives that cast's n_steps and status arrays (the other
+ * fields are not read).  Asynchronous on the stream; cast_ws and the forward
+ * outputs must stay untouched until it has run.  MPATH_ERR_UNSUPPORTED when
+ * dL_dphi_total is requested on an AMR or non-periodic grid. */
+int mpath_adjoint(const mpath_grid* grid, const mpath_cast_desc* desc, const mpath_observables* fwd,
+                  const void* cast_ws, size_t cast_ws_bytes, const mpath_adjoint_desc* adj, void* dev_ws,
+                  size_t ws_bytes, void* stream);
 
 /* Number of rays a desc describes. */
 int mpath_cast_count_rays(const mpath_cast_desc* desc, int64_t* n_rays);

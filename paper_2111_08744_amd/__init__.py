@@ -6,8 +6,9 @@ every step of the ray tracing runs in the library's kernels.  The names follow
 the C entry points:
 
     grid = Grid(cells, cosmo=(0.3, 0.7, 0.7))      # mpath_grid_build
-    out  = cast(grid, obs, z_src, nside, ...)      # mpath_cast
-    grad = adjoint(grid, ..., dL_dalpha, dL_dz)    # mpath_adjoint
+    out  = cast(grid, CastConfig(obs, z_src, nside, ...))            # mpath_cast
+    res  = adjoint(grid, cfg, out, dL_dalpha=..., jacobian=True)     # mpath_adjoint
+    alpha, z5 = cast_differentiable(values, grid, cfg)  # torch.autograd.Function
 
 Method: Breton & Reverdy, Magrathea-Pathfinder, Sect. 2 (geodesic
 integration with AMR interpolation, lens equation, redshifts).
@@ -23,7 +24,7 @@ from ._abi import (MPATH_RAY_LEFT_DOMAIN, MPATH_RAY_MAX_STEPS, MPATH_RAY_NONFINI
                    MPATH_RAY_REACHED, MPATH_SCHED_AUTO, MPATH_SCHED_PERSISTENT,
                    MPATH_SCHED_STATIC, MPATH_STOP_CHI, MPATH_STOP_REDSHIFT, MpathError)
 
-__all__ = ["Grid", "cast", "CastConfig", "library_path", "MpathError"]
+__all__ = ["Grid", "cast", "CastConfig", "adjoint", "cast_differentiable", "library_path", "MpathError"]
 
 
 def library_path() -> str:
@@ -212,3 +213,100 @@ def cast(grid: Grid, cfg: CastConfig, out=None, ws=None):
                                 _stream_ptr(grid.device)), "mpath_cast")
     out["_ws"] = ws
     return out
+
+
+def adjoint(grid: Grid, cfg: CastConfig, fwd, dL_dalpha=None, dL_dz=None, jacobian=False, cells=False,
+            phi_total=False, ws=None):
+    """mpath_adjoint: reverse sweep over the checkpointed cast ``fwd`` (the
+    dict returned by ``cast`` with cfg.checkpoint_every > 0, on the same grid
+    values).
+
+    jacobian: return ``jac`` [n_rays, 2, 2] (A_ab = d beta_a / d theta_b) and
+    ``dz_dtheta`` [n_rays, 2].  cells: return ``dL_dvalues`` [n_cells, 4],
+    the derivative of the loss with per-ray cotangents dL_dalpha [n_rays, 2]
+    (float32) and dL_dz [n_rays] (float64) with respect to the cell values
+    (phi, gx, gy, gz) in the caller's order.  phi_total (uniform periodic
+    grids): also ``dL_dphi_total`` [n_cells] for a gradient defined as the
+    central difference of phi."""
+    torch = _torch()
+    L = _abi.lib()
+    d = cfg.desc()
+    if cfg.checkpoint_every <= 0:
+        raise ValueError("the adjoint needs a cast with checkpoint_every > 0")
+    n = cfg.n_rays()
+    dev = grid.device
+    res = {}
+    ad = _abi.mpath_adjoint_desc()
+    keep = []
+    if dL_dalpha is not None:
+        dL_dalpha = dL_dalpha.to(device=dev, dtype=torch.float32).contiguous()
+        assert dL_dalpha.shape == (n, 2)
+        keep.append(dL_dalpha)
+        ad.dL_dalpha = dL_dalpha.data_ptr()
+    if dL_dz is not None:
+        dL_dz = dL_dz.to(device=dev, dtype=torch.float64).contiguous()
+        assert dL_dz.shape == (n,)
+        keep.append(dL_dz)
+        ad.dL_dz = dL_dz.data_ptr()
+    if jacobian:
+        res["jac"] = torch.empty((n, 2, 2), dtype=torch.float32, device=dev)
+        res["dz_dtheta"] = torch.empty((n, 2), dtype=torch.float32, device=dev)
+        ad.jac = res["jac"].data_ptr()
+        ad.dz_dtheta = res["dz_dtheta"].data_ptr()
+    if cells:
+        res["dL_dvalues"] = torch.empty((grid.n_cells, 4), dtype=torch.float32, device=dev)
+        ad.dL_dvalues = res["dL_dvalues"].data_ptr()
+    if phi_total:
+        res["dL_dphi_total"] = torch.empty((grid.n_cells,), dtype=torch.float32, device=dev)
+        ad.dL_dphi_total = res["dL_dphi_total"].data_ptr()
+    nbytes = C.c_size_t()
+    _abi.check(L.mpath_adjoint_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)),
+               "mpath_adjoint_workspace_bytes")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+    obs = observables_struct(fwd)
+    cast_ws = fwd["_ws"]
+    with torch.cuda.device(dev):
+        _abi.check(L.mpath_adjoint(grid.handle, C.byref(d), C.byref(obs), _ptr(cast_ws), cast_ws.numel(),
+                                   C.byref(ad), _ptr(ws), ws.numel(), _stream_ptr(dev)), "mpath_adjoint")
+    res["_ws"] = ws
+    res["_keep"] = keep
+    return res
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class CastFunction(torch.autograd.Function):
+        """(alpha [n_rays, 2], z5 [n_rays]) as functions of the cell values
+        [n_cells, 4] = (phi, gx, gy, gz) in the caller's order; backward runs
+        mpath_adjoint.  The grid keeps these values until the backward."""
+
+        @staticmethod
+        def forward(ctx, values, grid, cfg):
+            if cfg.checkpoint_every <= 0:
+                raise ValueError("cast_differentiable needs cfg.checkpoint_every > 0")
+            grid.set_values(values.detach().to(torch.float32))
+            out = cast(grid, cfg)
+            ctx.grid, ctx.cfg, ctx.out = grid, cfg, out
+            return out["alpha"].clone(), out["z5"].clone()
+
+        @staticmethod
+        def backward(ctx, g_alpha, g_z5):
+            res = adjoint(ctx.grid, ctx.cfg, ctx.out, dL_dalpha=g_alpha, dL_dz=g_z5, cells=True)
+            return res["dL_dvalues"], None, None
+
+    return CastFunction
+
+
+_CAST_FN = None
+
+
+def cast_differentiable(values, grid: Grid, cfg: CastConfig):
+    """torch.autograd entry: sets the grid's cell values (float32 [n_cells,
+    4], caller order), casts with checkpoints and returns (alpha, z5); their
+    gradients flow back to ``values`` through mpath_adjoint."""
+    global _CAST_FN
+    if _CAST_FN is None:
+        _CAST_FN = _autograd_function()
+    return _CAST_FN.apply(values, grid, cfg)

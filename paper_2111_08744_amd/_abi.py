@@ -66,8 +66,7 @@ class mpath_observables(C.Structure):
 
 class mpath_adjoint_desc(C.Structure):
     _fields_ = [("dL_dalpha", C.c_void_p), ("dL_dz", C.c_void_p), ("jac", C.c_void_p),
-                ("dz_dtheta", C.c_void_p), ("dL_dphi", C.c_void_p), ("dL_dgrad", C.c_void_p),
-                ("dL_dtheta", C.c_void_p)]
+                ("dz_dtheta", C.c_void_p), ("dL_dvalues", C.c_void_p), ("dL_dphi_total", C.c_void_p)]
 
 
 _lib = None
@@ -89,15 +88,17 @@ def lib():
         L.mpath_cast_workspace_bytes.argtypes = [vp, P(mpath_cast_desc), P(sz)]
         L.mpath_cast.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp, sz, vp]
         L.mpath_cast_count_rays.argtypes = [P(mpath_cast_desc), P(C.c_int64)]
-        if hasattr(L, "mpath_adjoint"):
-            L.mpath_adjoint.argtypes = [vp, P(mpath_cast_desc), vp, sz, P(mpath_adjoint_desc), vp]
+        L.mpath_adjoint_workspace_bytes.argtypes = [vp, P(mpath_cast_desc), P(sz)]
+        L.mpath_adjoint.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp, sz,
+                                    P(mpath_adjoint_desc), vp, sz, vp]
         L.mpath_status_string.restype = C.c_char_p
         L.mpath_status_string.argtypes = [C.c_int]
         L.mpath_last_error.restype = C.c_char_p
         L.mpath_version.restype = C.c_char_p
         for name in ("mpath_grid_workspace_bytes", "mpath_grid_build", "mpath_grid_free",
                      "mpath_grid_get_info", "mpath_grid_set_values", "mpath_cast_workspace_bytes",
-                     "mpath_cast", "mpath_cast_count_rays"):
+                     "mpath_cast", "mpath_cast_count_rays", "mpath_adjoint_workspace_bytes",
+                     "mpath_adjoint"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

@@ -74,12 +74,16 @@ struct RayRun {
     }
 
     // Advance by at most max_iter steps; returns true when the ray is done.
+    // With CKPT the state before every K-th step is stored for the adjoint.
+    template <bool CKPT = false>
     __device__ __forceinline__ bool advance(const CastArgs& a, int max_iter)
     {
         if (status >= 0) return true;
         const GridDev& g = a.grid;
         for (int it = 0; it < max_iter; ++it) {
             if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return true; }
+            if (CKPT && n_steps % a.ckpt_every == 0)
+                a.ckpt[(n_steps / a.ckpt_every) * a.n_rays + ray] = y;
             // leaf level at the step start sets the step length (N steps per cell)
             double u[3];
             grid_coords(g, geo, y.eta, y.dx, u);
@@ -224,6 +228,20 @@ __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_static_kernel(C
     R.finish(a);
 }
 
+// Static schedule storing checkpoints for the adjoint.
+template <bool AMR>
+__global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_ckpt_kernel(CastArgs a)
+{
+    extern __shared__ float coef_lds[];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    RayRun<AMR> R;
+    R.F.bind(coef_lds + threadIdx.x);
+    R.start(a, r);
+    R.template advance<true>(a, 0x7fffffff);
+    R.finish(a);
+}
+
 template <bool AMR>
 __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_persistent_kernel(CastArgs a)
 {
@@ -276,6 +294,18 @@ hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s)
         hipLaunchKernelGGL(cast_static_kernel<true>, dim3((unsigned)blocks), dim3(block), lds, s, a);
     else
         hipLaunchKernelGGL(cast_static_kernel<false>, dim3((unsigned)blocks), dim3(block), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_checkpointed(const CastArgs& a, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
+    const size_t lds = (size_t)32 * kBlock * sizeof(float);
+    if (a.grid.max_level > 0)
+        hipLaunchKernelGGL(cast_ckpt_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    else
+        hipLaunchKernelGGL(cast_ckpt_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 

@@ -102,6 +102,13 @@ struct HubbleCubic {
         const double tau = (eta - eta_n) * c.inv_deta;
         return b0 + tau * (b1 + tau * (b2 + tau * b3));
     }
+
+    // d(a'/a)/d eta of the same cubic
+    __device__ __forceinline__ double deriv(const CosmoDev& c, double eta) const
+    {
+        const double tau = (eta - eta_n) * c.inv_deta;
+        return (b1 + tau * (2.0 * b2 + 3.0 * tau * b3)) * c.inv_deta;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -183,6 +190,7 @@ struct FieldCache {
     int keyL;           // leaf level the stencil was resolved for (-1: none)
     int key[3];         // unwrapped coordinates at level keyL + 1
     int lvl;            // level of the resolved stencil
+    int base;           // id of its lowest corner cell
     float* c;           // trilinear coefficients in LDS: coefficient k of
                         // component f (phi, gx, gy, gz) at c[(8 f + k) * kBlock]
     static constexpr int cstride = kBlock;
@@ -263,6 +271,7 @@ struct FieldCache {
             }
             base = (int)morton3((uint32_t)b0, (uint32_t)b1, (uint32_t)b2);
         }
+        this->base = base;
         const float4* rec = g.dual + 8 * (int64_t)base;
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
@@ -332,11 +341,6 @@ struct FieldCache {
 // path coordinate s has the same increments as -eta, so s = eta_0 - eta
 // exactly and is not carried.
 // ---------------------------------------------------------------------------
-struct GeoState {
-    double eta, K;
-    float d[3], dx[3];
-};
-
 struct RayGeom {
     double uo[3];       // observer in coarse-grid coordinates (x_obs / h0)
     double n[3];        // initial direction (unit)
@@ -354,12 +358,19 @@ __device__ __forceinline__ void grid_coords(const GridDev& g, const RayGeom& r, 
     for (int i = 0; i < 3; ++i) u[i] = r.uo[i] + (s * r.n[i] + (double)dx[i]) * g.inv_h0;
 }
 
+// No-op stage recorder of the forward kernels.
+struct NoRecord {
+    __device__ __forceinline__ void stage(int, const GeoState&, int, int) {}
+};
+
 // One RK4 step of affine length dl from y into out.  The four stencil levels
-// are appended to *hash only when all four stages succeed (return 0).
-template <bool AMR>
+// are appended to *hash only when all four stages succeed (return 0).  The
+// recorder receives every stage's state and stencil (base id, level); the
+// reverse sweep uses it to replay the forward stages exactly.
+template <bool AMR, class Rec = NoRecord>
 __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FieldCache<AMR>& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
-                                        uint32_t& hash)
+                                        uint32_t& hash, Rec* rec = nullptr)
 {
     const float nf[3] = {(float)r.n[0], (float)r.n[1], (float)r.n[2]};
     double acc_eta = 0.0, acc_K = 0.0;
@@ -395,6 +406,7 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
         int leafl, l;
         if (F.eval(g, u, phi, G, leafl, l)) return 1;
         h = fnv(h, (uint32_t)l);
+        if (rec) rec->stage(st, yi, F.base, F.lvl);
         const double H = Hc(cz, yi.eta);
         const float m[3] = {nf[0] + yi.d[0], nf[1] + yi.d[1], nf[2] + yi.d[2]};
         const float mG = m[0] * G[0] + m[1] * G[1] + m[2] * G[2];

@@ -55,7 +55,25 @@ __global__ void build_leafinfo_kernel(GridDev g, const int4* __restrict__ cellpo
     }
 }
 
+__global__ void build_dual_ids_kernel(GridDev g, const int4* __restrict__ cellpos, int32_t* __restrict__ ids,
+                                      int64_t n)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int4 p = cellpos[c];
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+        ids[8 * c + o] = lookup_cell(g, p.w, p.x + (o & 1), p.y + ((o >> 1) & 1), p.z + (o >> 2));
+}
+
 }  // namespace
+
+hipError_t launch_build_dual_ids(const GridDev& g, const int4* cellpos, int32_t* ids, int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(build_dual_ids_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, cellpos, ids, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_build_dual(const GridDev& g, const int4* cellpos, float4* dual, int64_t n, hipStream_t s)
 {

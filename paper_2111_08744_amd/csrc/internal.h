@@ -42,6 +42,7 @@ struct GridDev {
     const int32_t* child;     // first child id, -1 for a leaf
     const float4* dual;       // [n][8]
     const int32_t* leafinfo;  // [n][8]
+    const int32_t* dual_ids;  // [n][8] ids of the 8 cells of dual[c] (-1: missing)
     double h0;                // coarse cell size
     double inv_h0;
     double eta0;              // conformal time at the observers (a = 1)
@@ -60,6 +61,12 @@ struct CosmoDev {
     double deta;
     int32_t n;
     int32_t is_static;
+};
+
+// Geodesic state in the split representation (see device.h).
+struct GeoState {
+    double eta, K;
+    float d[3], dx[3];
 };
 
 // End state of a ray kept between the integration and the observables kernel.
@@ -97,6 +104,22 @@ struct CastArgs {
     int32_t batch;               // steps between queue refills
     RayEnd* ends;                // [n_rays] end states for the observables kernel
     double* dirs;                // [n_rays][3] initial directions (HEALPix pixel centres)
+    GeoState* ckpt;              // [slots][n_rays] state before steps 0, K, 2K, ... (adjoint)
+    int32_t ckpt_every;          // K (0: no checkpoints)
+    int32_t ckpt_slots;
+};
+
+// Reverse-mode (adjoint) arguments.
+struct AdjointArgs {
+    CastArgs c;                  // the cast that stored the checkpoints
+    GeoState* tape;              // [ckpt_every][n_rays] step states of one segment
+    const int32_t* n_steps;      // forward outputs
+    const int32_t* status;
+    const float* dL_dalpha;      // [n_rays][2] or NULL
+    const double* dL_dz;         // [n_rays] or NULL
+    float* jac;                  // [n_rays][2][2] or NULL
+    float* dz_dtheta;            // [n_rays][2] or NULL
+    float* grad;                 // [n_cells][4] accumulated cotangent of (phi, grad) (library order) or NULL
 };
 
 // Kernel launchers (defined in cast.hip).
@@ -110,6 +133,15 @@ hipError_t launch_permute_values(float4* payload, const int64_t* perm, const flo
 hipError_t launch_build_dual(const GridDev& g, const int4* cellpos, float4* dual, int64_t n, hipStream_t s);
 hipError_t launch_build_leafinfo(const GridDev& g, const int4* cellpos, int32_t* leafinfo, int64_t n,
                                  hipStream_t s);
+hipError_t launch_build_dual_ids(const GridDev& g, const int4* cellpos, int32_t* ids, int64_t n, hipStream_t s);
+// Adjoint (defined in adjoint.hip).
+hipError_t launch_cast_checkpointed(const CastArgs& a, hipStream_t s);
+hipError_t launch_adjoint(const AdjointArgs& a, int columns, hipStream_t s);
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+hipError_t launch_scatter_grad(const float4* grad_lib, const int64_t* perm, float4* out_user, int64_t n,
+                               hipStream_t s);
+hipError_t launch_central_transpose(const float4* g_lib, const int4* cellpos, const int64_t* perm, float* out,
+                                    int n0, double h0, int64_t n, hipStream_t s);
 int cast_occupancy_blocks_per_cu(int block, bool amr);
 
 // Morton interleave of three 10-bit coordinates (host and device).

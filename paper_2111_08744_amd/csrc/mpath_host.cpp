@@ -135,6 +135,7 @@ struct mpath_grid {
     int4* cellpos = nullptr;
     float4* dual = nullptr;
     int32_t* leafinfo = nullptr;
+    int32_t* dual_ids = nullptr;
     double2* table = nullptr;
     int32_t level_start[kMaxLevels + 1] = {0};
     int num_cus = 0;
@@ -143,10 +144,10 @@ struct mpath_grid {
 namespace {
 
 struct GridLayout {
-    size_t off_payload, off_child, off_perm, off_cellpos, off_dual, off_leafinfo, off_table, total;
+    size_t off_payload, off_child, off_perm, off_cellpos, off_dual, off_leafinfo, off_dual_ids, off_table, total;
 };
 
-// Device workspace of a grid: 204 bytes per cell plus the background table.
+// Device workspace of a grid: 236 bytes per cell plus the background table.
 GridLayout grid_layout(int64_t n)
 {
     GridLayout L;
@@ -156,7 +157,8 @@ GridLayout grid_layout(int64_t n)
     L.off_cellpos = align_up(L.off_perm + (size_t)n * 8, 256);
     L.off_dual = align_up(L.off_cellpos + (size_t)n * 16, 256);
     L.off_leafinfo = align_up(L.off_dual + (size_t)n * 128, 256);
-    L.off_table = align_up(L.off_leafinfo + (size_t)n * 32, 256);
+    L.off_dual_ids = align_up(L.off_leafinfo + (size_t)n * 32, 256);
+    L.off_table = align_up(L.off_dual_ids + (size_t)n * 32, 256);
     L.total = align_up(L.off_table + (size_t)kTableN * 16, 256);
     return L;
 }
@@ -169,6 +171,7 @@ GridDev make_griddev(const mpath_grid* g)
     d.child = g->child;
     d.dual = g->dual;
     d.leafinfo = g->leafinfo;
+    d.dual_ids = g->dual_ids;
     d.h0 = g->box / g->n0;
     d.inv_h0 = g->n0 / g->box;
     d.eta0 = g->eta0;
@@ -358,6 +361,7 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     G->cellpos = (int4*)(G->ws + lay.off_cellpos);
     G->dual = (float4*)(G->ws + lay.off_dual);
     G->leafinfo = (int32_t*)(G->ws + lay.off_leafinfo);
+    G->dual_ids = (int32_t*)(G->ws + lay.off_dual_ids);
     G->table = (double2*)(G->ws + lay.off_table);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
@@ -369,6 +373,7 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
         (e = hipMemcpyAsync(G->table, table.data(), (size_t)kTableN * 16, hipMemcpyHostToDevice, s)) ||
         (e = launch_build_dual(gd, G->cellpos, G->dual, n, s)) ||
         (e = launch_build_leafinfo(gd, G->cellpos, G->leafinfo, n, s)) ||
+        (e = launch_build_dual_ids(gd, G->cellpos, G->dual_ids, n, s)) ||
         (e = hipStreamSynchronize(s))) {
         delete G;
         return hip_fail(e, "grid upload");
@@ -417,19 +422,22 @@ int mpath_grid_set_values(mpath_grid* g, const float* values, void* stream)
 namespace {
 
 struct CastLayout {
-    size_t off_obs, off_queue, off_ends, off_dirs, total;
+    size_t off_obs, off_queue, off_ends, off_dirs, off_ckpt, total;
+    int64_t ckpt_slots;
 };
 
-// Cast workspace: observer table, queue counter, per-ray end states and
-// initial directions.
-CastLayout cast_layout(int64_t n_obs, int64_t n_rays)
+// Cast workspace: observer table, queue counter, per-ray end states, initial
+// directions and, for a checkpointed cast, ckpt_slots states per ray.
+CastLayout cast_layout(int64_t n_obs, int64_t n_rays, int64_t ckpt_slots)
 {
     CastLayout L;
     L.off_obs = 0;
     L.off_queue = align_up((size_t)n_obs * sizeof(ObsDev), 256);
     L.off_ends = align_up(L.off_queue + 256, 256);
     L.off_dirs = align_up(L.off_ends + (size_t)n_rays * sizeof(RayEnd), 256);
-    L.total = align_up(L.off_dirs + (size_t)n_rays * 24, 256);
+    L.off_ckpt = align_up(L.off_dirs + (size_t)n_rays * 24, 256);
+    L.ckpt_slots = ckpt_slots;
+    L.total = align_up(L.off_ckpt + (size_t)ckpt_slots * (size_t)n_rays * sizeof(GeoState), 256);
     return L;
 }
 
@@ -465,45 +473,11 @@ int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_ra
     return MPATH_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int mpath_cast_count_rays(const mpath_cast_desc* d, int64_t* n_rays)
+// Observer table: stop surface per observer (conformal time eta_s, a_s, z0)
+// and the first ray of each observer.
+int make_obs_table(const mpath_grid* g, const mpath_cast_desc* d, std::vector<ObsDev>& obs)
 {
-    if (!d || !n_rays) return fail(MPATH_ERR_INVALID_ARG, "NULL argument");
-    if (d->n_obs < 1 || d->nside < 1) return fail(MPATH_ERR_INVALID_ARG, "bad n_obs or nside");
-    const int64_t npix = 12ll * d->nside * d->nside;
-    int64_t t = 0;
-    for (int j = 0; j < d->n_obs; ++j) t += d->pix_count ? d->pix_count[j] : npix;
-    *n_rays = t;
-    return MPATH_OK;
-}
-
-int mpath_cast_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, size_t* bytes)
-{
-    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
-    int64_t n_rays;
-    const int rc = check_cast_desc(g, d, &n_rays);
-    if (rc) return rc;
-    *bytes = cast_layout(d->n_obs, n_rays).total;
-    return MPATH_OK;
-}
-
-int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* dev_ws,
-               size_t ws_bytes, void* stream)
-{
-    int64_t n_rays;
-    int rc = check_cast_desc(g, d, &n_rays);
-    if (rc) return rc;
-    if (!out) return fail(MPATH_ERR_INVALID_ARG, "out is NULL");
-    if (d->checkpoint_every) return fail(MPATH_ERR_UNSUPPORTED, "checkpointing is not available in this build");
-    const CastLayout lay = cast_layout(d->n_obs, n_rays);
-    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
-    if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "cast workspace too small");
-
-    // ---- observer table ----
-    std::vector<ObsDev> obs(d->n_obs);
+    obs.assign(d->n_obs, ObsDev{});
     const double amin = 1.0 / (1.0 + kZMaxTable);
     const int Lm = g->max_level;
     const double h0 = g->box / g->n0;
@@ -537,13 +511,27 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
                               1.01 * (g->eta0 - o.eta_s) + 4.0 * h0) / h0 * std::ldexp(1.0, Lm + 1);
         if (reach > 1.0e9) return fail(MPATH_ERR_UNSUPPORTED, "ray path too long for 32-bit cell coordinates");
     }
-    hipStream_t s = (hipStream_t)stream;
-    char* ws = (char*)dev_ws;
-    ObsDev* dobs = (ObsDev*)(ws + lay.off_obs);
-    hipError_t e = hipMemcpyAsync(dobs, obs.data(), obs.size() * sizeof(ObsDev), hipMemcpyHostToDevice, s);
-    if (!e) e = hipStreamSynchronize(s);   // the host table is released on return
-    if (e) return hip_fail(e, "observer table upload");
+    return MPATH_OK;
+}
 
+// Checkpoint slots per ray: every step advances eta by at least the comoving
+// step length ds >= ds_min (|k0| grows along a backward path), so a ray
+// takes at most (eta_0 - eta_s) / ds_min + 1 steps; 2 % and 16 steps of
+// margin, capped by max_steps.
+int64_t checkpoint_slots(const mpath_grid* g, const mpath_cast_desc* d, const std::vector<ObsDev>& obs)
+{
+    if (d->checkpoint_every <= 0) return 0;
+    double chi = 0.0;
+    for (const ObsDev& o : obs) chi = std::max(chi, g->eta0 - o.eta_s);
+    const double ds_min = g->box / g->n0 / std::ldexp(1.0, d->adaptive ? g->max_level : 0) / d->steps_per_cell;
+    const double est = std::floor(1.02 * chi / ds_min) + 16.0;
+    const int64_t steps = (int64_t)std::min((double)d->max_steps, est);
+    return (steps + d->checkpoint_every - 1) / d->checkpoint_every;
+}
+
+CastArgs make_cast_args(const mpath_grid* g, const mpath_cast_desc* d, const CastLayout& lay, char* ws,
+                        int64_t n_rays)
+{
     CastArgs a;
     std::memset(&a, 0, sizeof a);
     a.grid = make_griddev(g);
@@ -554,13 +542,101 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
     a.cosmo.n = kTableN;
     a.cosmo.is_static = g->bg.is_static ? 1 : 0;
     a.cosmo_eta0 = g->eta0;
-    a.obs = dobs;
+    a.obs = (const ObsDev*)(ws + lay.off_obs);
     a.n_obs = d->n_obs;
     a.nside = d->nside;
     a.steps_per_cell = d->steps_per_cell;
     a.adaptive = d->adaptive ? 1 : 0;
     a.max_steps = d->max_steps;
     a.n_rays = n_rays;
+    a.queue = (unsigned long long*)(ws + lay.off_queue);
+    a.ends = (RayEnd*)(ws + lay.off_ends);
+    a.dirs = (double*)(ws + lay.off_dirs);
+    a.batch = d->batch > 0 ? d->batch : 32;
+    if (d->checkpoint_every > 0) {
+        a.ckpt = (GeoState*)(ws + lay.off_ckpt);
+        a.ckpt_every = d->checkpoint_every;
+        a.ckpt_slots = (int32_t)lay.ckpt_slots;
+        a.max_steps = std::min<int64_t>(d->max_steps, lay.ckpt_slots * (int64_t)d->checkpoint_every);
+    }
+    return a;
+}
+
+int cast_plan(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_rays, std::vector<ObsDev>& obs,
+              CastLayout* lay)
+{
+    int rc = check_cast_desc(g, d, n_rays);
+    if (rc) return rc;
+    rc = make_obs_table(g, d, obs);
+    if (rc) return rc;
+    const int64_t slots = checkpoint_slots(g, d, obs);
+    if (slots > (int64_t)1 << 30) return fail(MPATH_ERR_INVALID_ARG, "too many checkpoints: lower max_steps");
+    *lay = cast_layout(d->n_obs, *n_rays, slots);
+    return MPATH_OK;
+}
+
+// Adjoint workspace: one segment of step states per ray and the cell
+// cotangents in library order.
+struct AdjointLayout {
+    size_t off_tape, off_grad, total;
+};
+
+AdjointLayout adjoint_layout(const mpath_grid* g, const mpath_cast_desc* d, int64_t n_rays)
+{
+    AdjointLayout L;
+    L.off_tape = 0;
+    L.off_grad = align_up((size_t)d->checkpoint_every * (size_t)n_rays * sizeof(GeoState), 256);
+    L.total = align_up(L.off_grad + (size_t)g->n_cells * 16, 256);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpath_cast_count_rays(const mpath_cast_desc* d, int64_t* n_rays)
+{
+    if (!d || !n_rays) return fail(MPATH_ERR_INVALID_ARG, "NULL argument");
+    if (d->n_obs < 1 || d->nside < 1) return fail(MPATH_ERR_INVALID_ARG, "bad n_obs or nside");
+    const int64_t npix = 12ll * d->nside * d->nside;
+    int64_t t = 0;
+    for (int j = 0; j < d->n_obs; ++j) t += d->pix_count ? d->pix_count[j] : npix;
+    *n_rays = t;
+    return MPATH_OK;
+}
+
+int mpath_cast_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, size_t* bytes)
+{
+    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
+    int64_t n_rays;
+    std::vector<ObsDev> obs;
+    CastLayout lay;
+    const int rc = cast_plan(g, d, &n_rays, obs, &lay);
+    if (rc) return rc;
+    *bytes = lay.total;
+    return MPATH_OK;
+}
+
+int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* dev_ws,
+               size_t ws_bytes, void* stream)
+{
+    int64_t n_rays;
+    std::vector<ObsDev> obs;
+    CastLayout lay;
+    int rc = cast_plan(g, d, &n_rays, obs, &lay);
+    if (rc) return rc;
+    if (!out) return fail(MPATH_ERR_INVALID_ARG, "out is NULL");
+    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
+    if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "cast workspace too small");
+
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dev_ws;
+    hipError_t e = hipMemcpyAsync(ws + lay.off_obs, obs.data(), obs.size() * sizeof(ObsDev),
+                                  hipMemcpyHostToDevice, s);
+    if (!e) e = hipStreamSynchronize(s);   // the host table is released on return
+    if (e) return hip_fail(e, "observer table upload");
+
+    CastArgs a = make_cast_args(g, d, lay, ws, n_rays);
     a.out.beta = out->beta;
     a.out.alpha = out->alpha;
     a.out.z5 = out->z5;
@@ -570,28 +646,90 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
     a.out.status = out->status;
     a.out.hash = out->hash;
     a.out.chi = out->chi;
-    a.queue = (unsigned long long*)(ws + lay.off_queue);
-    a.ends = (RayEnd*)(ws + lay.off_ends);
-    a.dirs = (double*)(ws + lay.off_dirs);
-    a.batch = d->batch > 0 ? d->batch : 32;
 
-    int sched = d->schedule;
-    if (sched == MPATH_SCHED_AUTO) sched = d->n_obs > 1 ? MPATH_SCHED_PERSISTENT : MPATH_SCHED_STATIC;
-    const int block = d->block_size ? d->block_size : 256;
     e = launch_ray_dirs(a, s);
     if (e) return hip_fail(e, "ray directions launch");
-    if (sched == MPATH_SCHED_STATIC) {
-        e = launch_cast_static(a, block, s);
+    if (d->checkpoint_every > 0) {
+        e = launch_cast_checkpointed(a, s);
     } else {
-        int wpc = d->waves_per_cu;
-        if (wpc <= 0) wpc = cast_occupancy_blocks_per_cu(block, g->max_level > 0) * (block / 64);
-        if (wpc <= 0) wpc = 8;
-        const int cus = g->num_cus > 0 ? g->num_cus : 256;
-        const int blocks = std::max(1, cus * wpc / (block / 64));
-        e = launch_cast_persistent(a, block, blocks, s);
+        int sched = d->schedule;
+        if (sched == MPATH_SCHED_AUTO) sched = d->n_obs > 1 ? MPATH_SCHED_PERSISTENT : MPATH_SCHED_STATIC;
+        const int block = d->block_size ? d->block_size : 256;
+        if (sched == MPATH_SCHED_STATIC) {
+            e = launch_cast_static(a, block, s);
+        } else {
+            int wpc = d->waves_per_cu;
+            if (wpc <= 0) wpc = cast_occupancy_blocks_per_cu(block, g->max_level > 0) * (block / 64);
+            if (wpc <= 0) wpc = 8;
+            const int cus = g->num_cus > 0 ? g->num_cus : 256;
+            const int blocks = std::max(1, cus * wpc / (block / 64));
+            e = launch_cast_persistent(a, block, blocks, s);
+        }
     }
     if (!e) e = launch_observables(a, s);
     if (e) return hip_fail(e, "cast launch");
+    return MPATH_OK;
+}
+
+int mpath_adjoint_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, size_t* bytes)
+{
+    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
+    int64_t n_rays;
+    std::vector<ObsDev> obs;
+    CastLayout lay;
+    const int rc = cast_plan(g, d, &n_rays, obs, &lay);
+    if (rc) return rc;
+    if (d->checkpoint_every <= 0) return fail(MPATH_ERR_INVALID_ARG, "the adjoint needs checkpoint_every > 0");
+    *bytes = adjoint_layout(g, d, n_rays).total;
+    return MPATH_OK;
+}
+
+int mpath_adjoint(const mpath_grid* g, const mpath_cast_desc* d, const mpath_observables* fwd,
+                  const void* cast_ws, size_t cast_ws_bytes, const mpath_adjoint_desc* ad, void* dev_ws,
+                  size_t ws_bytes, void* stream)
+{
+    int64_t n_rays;
+    std::vector<ObsDev> obs;
+    CastLayout lay;
+    int rc = cast_plan(g, d, &n_rays, obs, &lay);
+    if (rc) return rc;
+    if (d->checkpoint_every <= 0) return fail(MPATH_ERR_INVALID_ARG, "the adjoint needs checkpoint_every > 0");
+    if (!fwd || !fwd->n_steps || !fwd->status)
+        return fail(MPATH_ERR_INVALID_ARG, "the forward n_steps and status arrays are required");
+    if (!ad) return fail(MPATH_ERR_INVALID_ARG, "adjoint desc is NULL");
+    if (!cast_ws || !dev_ws) return fail(MPATH_ERR_INVALID_ARG, "a workspace is NULL");
+    if (cast_ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "cast workspace too small");
+    const AdjointLayout al = adjoint_layout(g, d, n_rays);
+    if (ws_bytes < al.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "adjoint workspace too small");
+    if (ad->dL_dphi_total && !(g->max_level == 0 && g->periodic))
+        return fail(MPATH_ERR_UNSUPPORTED, "dL_dphi_total needs a uniform periodic grid");
+    const bool jac = ad->jac || ad->dz_dtheta;
+    const bool loss = ad->dL_dvalues || ad->dL_dphi_total;
+    if (!jac && !loss) return MPATH_OK;
+
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dev_ws;
+    AdjointArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.c = make_cast_args(g, d, lay, (char*)cast_ws, n_rays);
+    A.tape = (GeoState*)(ws + al.off_tape);
+    A.n_steps = fwd->n_steps;
+    A.status = fwd->status;
+    A.dL_dalpha = ad->dL_dalpha;
+    A.dL_dz = ad->dL_dz;
+    A.jac = ad->jac;
+    A.dz_dtheta = ad->dz_dtheta;
+    float* grad = (float*)(ws + al.off_grad);
+    A.grad = loss ? grad : nullptr;
+    hipError_t e = hipSuccess;
+    if (loss) e = launch_fill_zero(grad, g->n_cells * 4, s);
+    if (!e) e = launch_adjoint(A, jac && loss ? 4 : (jac ? 3 : 1), s);
+    if (!e && ad->dL_dvalues)
+        e = launch_scatter_grad((const float4*)grad, g->perm, (float4*)ad->dL_dvalues, g->n_cells, s);
+    if (!e && ad->dL_dphi_total)
+        e = launch_central_transpose((const float4*)grad, g->cellpos, g->perm, ad->dL_dphi_total, g->n0,
+                                     g->box / g->n0, g->n_cells, s);
+    if (e) return hip_fail(e, "adjoint launch");
     return MPATH_OK;
 }
 

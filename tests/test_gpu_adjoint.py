@@ -1,0 +1,276 @@
+"""GPU adjoint (reverse sweep over checkpoints) against the FP64 oracle's
+complex-step derivatives of the same discrete map, through the C ABI.
+
+Checked quantities:
+  * the distortion matrix A_ab = d beta_a / d theta_b and d z5 / d theta_b
+    (Sect. 2.3, 2.5) per ray, against the oracle's exact derivative of the
+    same RK4 / CIC / landing map (two complex-step passes);
+  * the loss gradient with respect to the cell values (phi, grad phi), by
+    directional derivatives: <dL/dvalues, delta> against the oracle's
+    complex-step derivative along delta, for random delta and for single
+    cells;
+  * the derivative through a gradient defined as the central difference of
+    phi, on a uniform periodic grid;
+  * invariance of the results under the checkpoint interval, and the
+    forward outputs of a checkpointed cast.
+
+Tolerances.  The GPU state is FP32 (direction offset d and displacement dx)
+with FP64 conformal time and |k0|; its path differs from the oracle's by
+~1e-6 of a cell.  Derivatives inherit that relative error wherever the
+interpolant is smooth; where a stage of one side falls across a cell-centre
+plane (a kink of the CIC interpolant of the gradient) from the other, that
+one stage's Jacobian differs by the jump of the second derivative, which
+moves A by about (A - I) / (number of stages) ~ 1e-6 on such rare rays.
+The outputs A and dz/dtheta are float32 (rounding 6e-8 on A ~ 1).  Bars:
+5e-6 on the largest |A_gpu - A_oracle| of any ray and 2e-7 on the median,
+1e-5 relative on dz/dtheta (1e-6 median) and on the directional loss
+derivatives (float32 cell cotangents summed by atomics).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from parity import oracle_dirs
+
+pytestmark = pytest.mark.gpu
+
+COSMO = (0.3, 0.7, 0.7)
+OBS = [250.0, 250.0, 250.0]
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2111_08744_amd as M
+    return M
+
+
+@pytest.fixture(scope="module")
+def gauss64():
+    return synth.make_cells("gauss64")
+
+
+def _cfg(M, z, nside, K, first=0, count=None, **kw):
+    count = 12 * nside * nside if count is None else count
+    return M.CastConfig(OBS, z, nside, [first], [count], steps_per_cell=10, checkpoint_every=K, **kw)
+
+
+def _fwd(M, grid, cfg):
+    import torch
+    out = M.cast(grid, cfg)
+    torch.cuda.synchronize()
+    return out
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _oracle_params(z, **kw):
+    return O.params(OBS, z_src=z, steps_per_cell=10, adaptive=False, **kw)
+
+
+def test_checkpointed_forward_equals_static(M, gauss64):
+    grid = M.Grid(gauss64, COSMO)
+    a = _fwd(M, grid, M.CastConfig(OBS, 0.3, 4, steps_per_cell=10, schedule=1))
+    b = _fwd(M, grid, _cfg(M, 0.3, 4, 32))
+    for k in ("beta", "alpha", "z5", "phi_src", "n_steps", "status", "hash"):
+        assert np.array_equal(_np(a[k]), _np(b[k]), equal_nan=True), k
+
+
+def test_jacobian_vs_oracle_complex_step(M, gauss64):
+    """A and dz/dtheta of every ray of nside 4 (192 rays) to z = 0.3."""
+    import torch
+    grid = M.Grid(gauss64, COSMO)
+    cfg = _cfg(M, 0.3, 4, 32)
+    out = _fwd(M, grid, cfg)
+    res = M.adjoint(grid, cfg, out, jacobian=True)
+    torch.cuda.synchronize()
+    jac, dz = _np(res["jac"]).astype(np.float64), _np(res["dz_dtheta"]).astype(np.float64)
+    field = O.Field.grid(gauss64)
+    c = O.cosmo(*COSMO)
+    p = _oracle_params(0.3)
+    dirs = oracle_dirs(4, [0], [192])
+    A, dzo, rec = O.jacobian_cs(lambda d, t: O.cast_cs(field, c, p, d, dtheta=t), dirs)
+    same = _np(out["hash"]).view(np.uint32) == rec["hash"]
+    _print("rays with the oracle's decisions:", same.sum(), "of", len(same))
+    assert same.mean() > 0.95
+    dA = np.abs(jac - A)[same].reshape(-1, 4).max(1)
+    lens = np.abs(A - np.eye(2)).reshape(-1, 4).max(1)
+    _print("|A - I| median", np.median(lens), "max", lens.max())
+    _print("|A_gpu - A_oracle| median", np.median(dA), "p99", np.quantile(dA, 0.99), "max", dA.max())
+    rz = np.abs(dz - dzo)[same].max(1) / np.abs(dzo).max()
+    _print("dz/dtheta rel. diff median", np.median(rz), "max", rz.max(), "scale", np.abs(dzo).max())
+    assert lens.max() > 1e-4                    # lensing is measurable here
+    assert dA.max() < 5e-6 and np.median(dA) < 2e-7
+    assert rz.max() < 1e-5 and np.median(rz) < 1e-6
+
+
+def test_jacobian_independent_of_checkpoint_interval(M, gauss64):
+    import torch
+    grid = M.Grid(gauss64, COSMO)
+    ref = None
+    for K in (32, 1, 7, 100000):
+        cfg = _cfg(M, 0.2, 2, K)
+        out = _fwd(M, grid, cfg)
+        res = M.adjoint(grid, cfg, out, jacobian=True)
+        torch.cuda.synchronize()
+        j = (_np(res["jac"]), _np(res["dz_dtheta"]))
+        if ref is None:
+            ref = j
+        else:
+            assert np.array_equal(j[0], ref[0]) and np.array_equal(j[1], ref[1]), K
+
+
+def _loss_setup(M, cells, z, nside, K=32):
+    import torch
+    grid = M.Grid(cells, COSMO)
+    cfg = _cfg(M, z, nside, K)
+    out = _fwd(M, grid, cfg)
+    alpha = out["alpha"].to(torch.float64)
+    rng = np.random.default_rng(7)
+    wz = rng.normal(size=alpha.shape[0])
+    return grid, cfg, out, alpha, wz
+
+
+def test_loss_gradient_directional(M, gauss64):
+    """L = sum |alpha|^2 + sum w z5: <dL/dvalues, delta> against the oracle's
+    complex-step derivative along random delta."""
+    import torch
+    grid, cfg, out, alpha, wz = _loss_setup(M, gauss64, 0.3, 4)
+    res = M.adjoint(grid, cfg, out, dL_dalpha=2.0 * alpha, dL_dz=torch.tensor(wz, device="cuda"),
+                    jacobian=True, cells=True)
+    res1 = M.adjoint(grid, cfg, out, dL_dalpha=2.0 * alpha, dL_dz=torch.tensor(wz, device="cuda"), cells=True)
+    torch.cuda.synchronize()
+    g = _np(res["dL_dvalues"]).astype(np.float64)
+    g1 = _np(res1["dL_dvalues"]).astype(np.float64)
+    # the loss-only sweep and the combined one give the same cell gradient
+    assert np.allclose(g, g1, rtol=1e-5, atol=1e-6 * np.abs(g).max())
+    field = O.Field.grid(gauss64)
+    c = O.cosmo(*COSMO)
+    p = _oracle_params(0.3)
+    dirs = oracle_dirs(4, [0], [192])
+    a = _np(alpha)
+    rng = np.random.default_rng(11)
+    for trial in range(3):
+        delta = rng.normal(size=(gauss64.n_cells, 4))
+        delta[:, 0] *= 1e-5
+        delta[:, 1:] *= 1e-5 / 7.8
+        rec, tan = O.cast_cs(field, c, p, dirs, dphi=delta[:, 0], dgrad=delta[:, 1:])
+        want = np.sum(2.0 * a * tan["alpha"]) + np.sum(wz * tan["z5"])
+        got = np.sum(g * delta)
+        _print(f"trial {trial}: adjoint {got:.9e} oracle {want:.9e} rel {abs(got - want) / abs(want):.2e}")
+        assert abs(got - want) <= 1e-5 * abs(want)
+
+
+def test_loss_gradient_single_cells(M, gauss64):
+    """Per-cell derivatives on the cells with the largest gradients."""
+    import torch
+    grid, cfg, out, alpha, wz = _loss_setup(M, gauss64, 0.2, 2)
+    res = M.adjoint(grid, cfg, out, dL_dalpha=2.0 * alpha, dL_dz=torch.tensor(wz, device="cuda"), cells=True)
+    torch.cuda.synchronize()
+    g = _np(res["dL_dvalues"]).astype(np.float64)
+    field = O.Field.grid(gauss64)
+    c = O.cosmo(*COSMO)
+    p = _oracle_params(0.2)
+    dirs = oracle_dirs(2, [0], [48])
+    a = _np(alpha)
+    top = np.argsort(-np.abs(g).max(1))[:4]
+    for cell in top:
+        for q in range(4):
+            delta = np.zeros((gauss64.n_cells, 4))
+            delta[cell, q] = 1.0
+            _, tan = O.cast_cs(field, c, p, dirs, dphi=delta[:, 0], dgrad=delta[:, 1:])
+            want = np.sum(2.0 * a * tan["alpha"]) + np.sum(wz * tan["z5"])
+            got = g[cell, q]
+            _print(f"cell {cell} comp {q}: adjoint {got:.6e} oracle {want:.6e}")
+            assert abs(got - want) <= 1e-5 * np.abs(g[cell]).max() + 1e-12
+
+
+def test_phi_total_central_difference(M, gauss64):
+    """dL/dphi with grad phi = central difference of phi (periodic)."""
+    import torch
+    grid, cfg, out, alpha, wz = _loss_setup(M, gauss64, 0.3, 4)
+    res = M.adjoint(grid, cfg, out, dL_dalpha=2.0 * alpha, dL_dz=torch.tensor(wz, device="cuda"), cells=True,
+                    phi_total=True)
+    torch.cuda.synchronize()
+    gt = _np(res["dL_dphi_total"]).astype(np.float64)
+    field = O.Field.grid(gauss64)
+    c = O.cosmo(*COSMO)
+    p = _oracle_params(0.3)
+    dirs = oracle_dirs(4, [0], [192])
+    a = _np(alpha)
+    rng = np.random.default_rng(5)
+    n = gauss64.n0
+    d3 = rng.normal(size=(n, n, n)) * 1e-5
+    dg3 = synth.central_gradient(d3, gauss64.box)
+    ijk = gauss64.ijk
+    dphi = d3[ijk[:, 0], ijk[:, 1], ijk[:, 2]]
+    dgrad = dg3[ijk[:, 0], ijk[:, 1], ijk[:, 2]]
+    _, tan = O.cast_cs(field, c, p, dirs, dphi=dphi, dgrad=dgrad)
+    want = np.sum(2.0 * a * tan["alpha"]) + np.sum(wz * tan["z5"])
+    got = np.sum(gt * dphi)
+    _print(f"phi total: adjoint {got:.9e} oracle {want:.9e}")
+    assert abs(got - want) <= 1e-5 * abs(want)
+
+
+def test_autograd_function(M, gauss64):
+    import torch
+    grid = M.Grid(gauss64, COSMO)
+    cfg = _cfg(M, 0.2, 2, 32)
+    vals = torch.tensor(np.concatenate([gauss64.phi[:, None], gauss64.grad], 1), dtype=torch.float32,
+                        device="cuda", requires_grad=True)
+    alpha, z5 = M.cast_differentiable(vals, grid, cfg)
+    loss = (alpha.double() ** 2).sum() + 3.0 * z5.sum()
+    loss.backward()
+    out = _fwd(M, grid, cfg)
+    res = M.adjoint(grid, cfg, out, dL_dalpha=2.0 * out["alpha"],
+                    dL_dz=torch.full((cfg.n_rays(),), 3.0, dtype=torch.float64, device="cuda"), cells=True)
+    torch.cuda.synchronize()
+    g_ref = _np(res["dL_dvalues"])
+    g = _np(vals.grad)
+    assert np.allclose(g, g_ref, rtol=1e-5, atol=1e-6 * np.abs(g_ref).max())
+
+
+def test_amr_jacobian_vs_oracle(M):
+    """Adaptive steps on a small random AMR tree (level fallback, landing)."""
+    import torch
+    cells = synth.random_amr_cells(16, 125.0, 3, seed=5)
+    grid = M.Grid(cells, COSMO)
+    obs = [40.0, 70.0, 90.0]
+    cfg = M.CastConfig(obs, 0.1, 2, steps_per_cell=4, adaptive=True, checkpoint_every=32)
+    out = M.cast(grid, cfg)
+    res = M.adjoint(grid, cfg, out, jacobian=True)
+    torch.cuda.synchronize()
+    field = O.Field.grid(cells)
+    c = O.cosmo(*COSMO)
+    p = O.params(obs, z_src=0.1, steps_per_cell=4, adaptive=True)
+    dirs = oracle_dirs(2, [0], [48])
+    A, dzo, rec = O.jacobian_cs(lambda d, t: O.cast_cs(field, c, p, d, dtheta=t), dirs)
+    same = _np(out["hash"]).view(np.uint32) == rec["hash"]
+    jac = _np(res["jac"]).astype(np.float64)
+    dA = np.abs(jac - A)[same].reshape(-1, 4).max(1)
+    _print("AMR: same decisions", same.sum(), "of", len(same), "|dA| max", dA.max())
+    assert same.mean() > 0.9
+    assert dA.max() < 5e-6 and np.median(dA) < 2e-7
+
+
+def test_adjoint_argument_errors(M, gauss64):
+    grid = M.Grid(gauss64, COSMO)
+    cfg = M.CastConfig(OBS, 0.1, 1, steps_per_cell=10)
+    out = _fwd(M, grid, cfg)
+    with pytest.raises(ValueError):
+        M.adjoint(grid, cfg, out, jacobian=True)
+    cells = synth.random_amr_cells(16, 125.0, 2, seed=5)
+    g2 = M.Grid(cells, COSMO)
+    cfg2 = M.CastConfig([40.0, 70.0, 90.0], 0.05, 1, steps_per_cell=4, adaptive=True, checkpoint_every=16)
+    out2 = _fwd(M, g2, cfg2)
+    with pytest.raises(M.MpathError):
+        M.adjoint(g2, cfg2, out2, cells=True, phi_total=True)
