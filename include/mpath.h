@@ -232,6 +232,11 @@ int mpath_cast(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observ
  *   dL_dphi_total[n_cells]  uniform periodic grids whose gradient is the
  *                           central difference (phi[i+1] - phi[i-1]) / 2h:
  *                           dL/dphi + (difference operator)^T dL/dgrad
+ * Per-ray check (DEVICE int32 [n_rays]): ray_status[r] = 0 when the
+ * derivative was computed, 1 when the ray did not reach the source (no
+ * derivative), 2 when the recomputation did not retrace the forward path bit
+ * for bit (only possible if the cell values changed after the cast; the
+ * ray's outputs are then NaN and its cell terms incomplete).
  * Any output pointer may be NULL; the cell cotangents are float32 sums
  * accumulated with atomics, so their last bits depend on the order of the
  * additions. */
@@ -242,10 +247,12 @@ typedef struct {
     float* dz_dtheta;
     float* dL_dvalues;
     float* dL_dphi_total;
+    int32_t* ray_status;
 } mpath_adjoint_desc;
 
 /* Device workspace of mpath_adjoint for this desc (which needs
- * checkpoint_every > 0): K states per ray (40 B each) and 16 B per cell. */
+ * checkpoint_every > 0): K states per ray (40 B each) and 16 B per cell
+ * (rounded up to a multiple of 8 cells). */
 int mpath_adjoint_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* desc, size_t* bytes);
 
 /* Reverse sweep after a checkpointed mpath_cast with the same grid (whose

@@ -227,7 +227,8 @@ def adjoint(grid: Grid, cfg: CastConfig, fwd, dL_dalpha=None, dL_dz=None, jacobi
     (float32) and dL_dz [n_rays] (float64) with respect to the cell values
     (phi, gx, gy, gz) in the caller's order.  phi_total (uniform periodic
     grids): also ``dL_dphi_total`` [n_cells] for a gradient defined as the
-    central difference of phi."""
+    central difference of phi.  ``ray_status`` [n_rays]: 0 derivative
+    computed, 1 ray not reached (no derivative), 2 replay mismatch."""
     torch = _torch()
     L = _abi.lib()
     d = cfg.desc()
@@ -259,6 +260,8 @@ def adjoint(grid: Grid, cfg: CastConfig, fwd, dL_dalpha=None, dL_dz=None, jacobi
     if phi_total:
         res["dL_dphi_total"] = torch.empty((grid.n_cells,), dtype=torch.float32, device=dev)
         ad.dL_dphi_total = res["dL_dphi_total"].data_ptr()
+    res["ray_status"] = torch.empty((n,), dtype=torch.int32, device=dev)
+    ad.ray_status = res["ray_status"].data_ptr()
     nbytes = C.c_size_t()
     _abi.check(L.mpath_adjoint_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)),
                "mpath_adjoint_workspace_bytes")

@@ -66,7 +66,8 @@ class mpath_observables(C.Structure):
 
 class mpath_adjoint_desc(C.Structure):
     _fields_ = [("dL_dalpha", C.c_void_p), ("dL_dz", C.c_void_p), ("jac", C.c_void_p),
-                ("dz_dtheta", C.c_void_p), ("dL_dvalues", C.c_void_p), ("dL_dphi_total", C.c_void_p)]
+                ("dz_dtheta", C.c_void_p), ("dL_dvalues", C.c_void_p), ("dL_dphi_total", C.c_void_p),
+                ("ray_status", C.c_void_p)]
 
 
 _lib = None

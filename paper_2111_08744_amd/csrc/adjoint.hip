@@ -3,18 +3,21 @@
 // The forward cast (with checkpoints) stores every ray's state before steps
 // 0, K, 2K, ...  The adjoint kernel then runs, per ray, one reverse sweep:
 // segment by segment from the source back to the observer it recomputes the
-// K steps of the segment from its checkpoint (the same code as the forward,
-// so every leaf level, stencil and landing decision is replayed exactly) into
-// a per-ray tape, and for every step in reverse order re-records the four
-// RK4 stages and applies the transposed Jacobian of the step.
+// steps of the segment from its checkpoint (the same code as the forward, so
+// every leaf level, stencil and landing decision is replayed exactly) into a
+// per-ray tape, and for every step in reverse order re-records the four RK4
+// stages and applies the transposed Jacobian of the step.
 //
 // The derivative is that of the discrete map: classical RK4 on the null
 // geodesic equations of Sect. 2.2 with CIC interpolation (piecewise
 // trilinear, so grad Phi has a piecewise-constant spatial derivative), step
 // length h_leaf / N with affine step ds / |k0| (differentiated through k0),
 // and the landing step on the source iso-eta surface (implicit step length).
-// It is computed in double precision on the physical variables
-// (eta, x, k0, k), whose RK4 map equals the split one of the forward kernels.
+// It is taken on the physical variables (eta, x, k0, k), whose RK4 map equals
+// the split one of the forward kernels.  Precision follows the forward: the
+// cotangent of the state is accumulated in double precision, while the
+// per-stage products (stage Jacobians applied to small cotangent increments)
+// run in single precision, like the stage arithmetic of the forward.
 //
 // Cotangent columns (one reverse sweep carries all of them):
 //   beta_1, beta_2   e~_a(beta) . x / |x_s - x_obs|: their values at the
@@ -32,58 +35,113 @@
 namespace mpath {
 namespace {
 
-constexpr int kMinWavesAdj = 1;
-
-// Physical state (eta, x, k0, k) or a cotangent of it.
-struct Phys {
-    double eta, x[3], k0, k[3];
+// Physical state (eta, x, k0, k) or a cotangent of it, in precision T.
+template <class T>
+struct PhysT {
+    T eta, x[3], k0, k[3];
 };
+using Phys = PhysT<double>;
+using Phys32 = PhysT<float>;
 
-__device__ __forceinline__ void phys_zero(Phys& a)
+template <class T>
+__device__ __forceinline__ void phys_zero(PhysT<T>& a)
 {
-    a.eta = 0.0; a.k0 = 0.0;
+    a.eta = T(0); a.k0 = T(0);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { a.x[i] = 0.0; a.k[i] = 0.0; }
+    for (int i = 0; i < 3; ++i) { a.x[i] = T(0); a.k[i] = T(0); }
 }
 
-__device__ __forceinline__ void phys_axpy(Phys& a, double s, const Phys& b)
+template <class T, class U>
+__device__ __forceinline__ void phys_axpy(PhysT<T>& a, T s, const PhysT<U>& b)
 {
-    a.eta += s * b.eta; a.k0 += s * b.k0;
+    a.eta += s * (T)b.eta; a.k0 += s * (T)b.k0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { a.x[i] += s * b.x[i]; a.k[i] += s * b.k[i]; }
+    for (int i = 0; i < 3; ++i) { a.x[i] += s * (T)b.x[i]; a.k[i] += s * (T)b.k[i]; }
 }
 
-__device__ __forceinline__ double phys_dot(const Phys& a, const Phys& b)
+template <class T>
+__device__ __forceinline__ T phys_dot(const PhysT<T>& a, const PhysT<T>& b)
 {
-    double s = a.eta * b.eta + a.k0 * b.k0;
+    T s = a.eta * b.eta + a.k0 * b.k0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) s += a.x[i] * b.x[i] + a.k[i] * b.k[i];
     return s;
 }
 
-// The four stages of one RK4 step as the forward computed them.
-struct StageRecord {
-    GeoState y[4];
-    int base[4];
-    int lvl[4];
-    __device__ __forceinline__ void stage(int i, const GeoState& yi, int b, int l)
-    {
-        y[i] = yi;
-        base[i] = b;
-        lvl[i] = l;
-    }
+__device__ __forceinline__ Phys32 to32(const Phys& a)
+{
+    Phys32 r;
+    r.eta = (float)a.eta; r.k0 = (float)a.k0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { r.x[i] = (float)a.x[i]; r.k[i] = (float)a.k[i]; }
+    return r;
+}
+
+// What the forward computed at one RK4 stage: the state, the interpolated
+// gradient and the stencil (lowest-corner id, level, offsets of the point).
+struct StageData {
+    GeoState y;
+    float G[3], t[3];
+    int base, lvl;
 };
 
-// Everything the transposed stage Jacobian needs at one stage.
-struct Jet {
-    Phys Y;             // stage state
-    Phys F;             // right-hand side at Y
-    double G[3];        // interpolated grad Phi
-    double JG[3][3];    // dG_j / dx_l of the trilinear interpolant
-    double phi, gphi[3];// interpolated Phi and the gradient of its interpolant
-    double H, dH;       // a'/a and its eta-derivative
-    float w[8];         // CIC weights of the 8 stencil cells
-    int base;
+// The four stages of one RK4 step, kept in this lane's LDS slots (the
+// forward's stage loop is not unrolled, so the stage index is a run-time
+// value, and the replay must run that same loop to reproduce the forward's
+// rounding bit for bit).  Word w of stage i is at p[(i * kWords + w) kBlock].
+struct StageRecord {
+    static constexpr int kWords = 18;
+    float* p;
+
+    __device__ __forceinline__ void put(float* q, int w, float v) const { q[w * kBlock] = v; }
+    __device__ __forceinline__ void put64(float* q, int w, double v) const
+    {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        q[w * kBlock] = __uint_as_float((unsigned)b);
+        q[(w + 1) * kBlock] = __uint_as_float((unsigned)(b >> 32));
+    }
+    __device__ __forceinline__ double get64(const float* q, int w) const
+    {
+        const unsigned long long lo = __float_as_uint(q[w * kBlock]);
+        const unsigned long long hi = __float_as_uint(q[(w + 1) * kBlock]);
+        return __longlong_as_double((long long)(lo | (hi << 32)));
+    }
+
+    template <class FC>
+    __device__ __forceinline__ void stage(int i, const GeoState& yi, const FC& F, const float* G)
+    {
+        float* q = p + i * kWords * kBlock;
+        put64(q, 0, yi.eta);
+        put64(q, 2, yi.K);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            put(q, 4 + k, yi.d[k]);
+            put(q, 7 + k, yi.dx[k]);
+            put(q, 10 + k, G[k]);
+            put(q, 13 + k, F.t[k]);
+        }
+        put(q, 16, __int_as_float(F.base));
+        put(q, 17, __int_as_float(F.lvl));
+    }
+
+    template <int I>
+    __device__ __forceinline__ StageData get() const
+    {
+        const float* q = p + I * kWords * kBlock;
+        StageData d;
+        d.y.eta = get64(q, 0);
+        d.y.K = get64(q, 2);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            d.y.d[k] = q[(4 + k) * kBlock];
+            d.y.dx[k] = q[(7 + k) * kBlock];
+            d.G[k] = q[(10 + k) * kBlock];
+            d.t[k] = q[(13 + k) * kBlock];
+        }
+        d.base = __float_as_int(q[16 * kBlock]);
+        d.lvl = __float_as_int(q[17 * kBlock]);
+        return d;
+    }
 };
 
 struct RayCtx {
@@ -91,142 +149,300 @@ struct RayCtx {
     double xobs[3];
 };
 
-__device__ __forceinline__ void make_jet(const AdjointArgs& A, const RayCtx& R, const GeoState& ys, int base,
-                                         int lvl, const HubbleCubic& Hc, Jet& J)
+// Trilinear coefficients (component-major: c[8 q + k]) of a stencil: from the
+// lane's LDS cache when it holds that stencil, else from the dual table.
+template <bool AMR>
+__device__ __forceinline__ void stencil_coefs(const GridDev& g, const FieldCache<AMR>& F, int base, float c[32])
 {
-    const GridDev& g = A.c.grid;
-    const double s = g.eta0 - ys.eta;
-    double u[3];
-    J.Y.eta = ys.eta;
-    J.Y.k0 = -ys.K;
+    if (F.keyL >= 0 && F.base == base) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double disp = s * R.geo.n[i] + (double)ys.dx[i];
-        J.Y.x[i] = R.xobs[i] + disp;
-        u[i] = R.geo.uo[i] + disp * g.inv_h0;
-        J.Y.k[i] = ys.K * (R.geo.n[i] + (double)ys.d[i]);
+        for (int i = 0; i < 32; ++i) c[i] = F.c[i * FieldCache<AMR>::cstride];
+    } else {
+        const float4* rec = g.dual + 8 * (int64_t)base;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const float4 q = rec[o];
+            c[o] = q.x; c[8 + o] = q.y; c[16 + o] = q.z; c[24 + o] = q.w;
+        }
     }
+}
+
+// Offsets of a stage position from its stencil's lowest corner, at the
+// stencil level (as the forward interpolation computes them).
+__device__ __forceinline__ void stage_offsets(const GridDev& g, const RayCtx& R, const GeoState& ys, int lvl,
+                                              double t[3])
+{
+    double u[3];
+    grid_coords(g, R.geo, ys.eta, ys.dx, u);
     const double sl = (double)(1 << lvl);
-    double t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double q = u[d] * sl - 0.5;
         t[d] = q - floor(q);
     }
-    const float4* rec = g.dual + 8 * (int64_t)base;
-    float4 c[8];
+}
+
+// Value and t-derivatives of one trilinear component
+// f = c0 + tx (c1 + ty (c4 + tz c7) + tz c5) + ty (c2 + tz c6) + tz c3.
+template <class T>
+__device__ __forceinline__ void trilinear_jet(const T c[8], T tx, T ty, T tz, T& f, T& fx, T& fy, T& fz)
+{
+    f = c[0] + tx * (c[1] + ty * (c[4] + tz * c[7]) + tz * c[5]) + ty * (c[2] + tz * c[6]) + tz * c[3];
+    fx = c[1] + ty * c[4] + tz * c[5] + ty * tz * c[7];
+    fy = c[2] + tx * c[4] + tz * c[6] + tx * tz * c[7];
+    fz = c[3] + tx * c[5] + ty * c[6] + tx * ty * c[7];
+}
+
+// What the transposed stage Jacobian needs at one stage (single precision).
+struct Jet32 {
+    float k0, k[3];
+    float G[3];
+    float JG[3][3];     // dG_j / dx_l of the trilinear interpolant
+    float H, dH;        // a'/a and its eta-derivative
+    float t[3];         // CIC offsets (weights) at the stencil level
+    int base;
+};
+
+// Stage quantities that need no stencil coefficients.
+__device__ __forceinline__ void jet_from_stage(const AdjointArgs& A, const RayCtx& R, const StageData& d,
+                                               const HubbleCubic& Hc, Jet32& J)
+{
+    const float K = (float)d.y.K;
+    J.k0 = -K;
 #pragma unroll
-    for (int o = 0; o < 8; ++o) c[o] = rec[o];
-    const double tx = t[0], ty = t[1], tz = t[2];
-    const double scale = sl * g.inv_h0;      // d t / d x
-    double f[4], fx[4], fy[4], fz[4];
-#define MPATH_JET(q, m)                                                                       \
-    {                                                                                         \
-        const double c0 = c[0].m, c1 = c[1].m, c2 = c[2].m, c3 = c[3].m;                       \
-        const double c4 = c[4].m, c5 = c[5].m, c6 = c[6].m, c7 = c[7].m;                       \
-        f[q] = c0 + tx * (c1 + ty * (c4 + tz * c7) + tz * c5) + ty * (c2 + tz * c6) + tz * c3; \
-        fx[q] = c1 + ty * c4 + tz * c5 + ty * tz * c7;                                        \
-        fy[q] = c2 + tx * c4 + tz * c6 + tx * tz * c7;                                        \
-        fz[q] = c3 + tx * c5 + ty * c6 + tx * ty * c7;                                        \
+    for (int i = 0; i < 3; ++i) {
+        J.k[i] = K * ((float)R.geo.n[i] + d.y.d[i]);
+        J.G[i] = d.G[i];
+        J.t[i] = d.t[i];
     }
-    MPATH_JET(0, x) MPATH_JET(1, y) MPATH_JET(2, z) MPATH_JET(3, w)
-#undef MPATH_JET
-    J.phi = f[0];
-    J.gphi[0] = fx[0] * scale; J.gphi[1] = fy[0] * scale; J.gphi[2] = fz[0] * scale;
+    J.H = (float)Hc(A.c.cosmo, d.y.eta);
+    J.dH = (float)Hc.deriv(A.c.cosmo, d.y.eta);
+    J.base = d.base;
+}
+
+// Spatial derivatives of the interpolated gradient at the stage: the
+// t-derivatives of the trilinear interpolant (Eq. W_CIC) times 2^lvl / h0.
+template <bool AMR>
+__device__ __forceinline__ void jet_gradient(const GridDev& g, const FieldCache<AMR>& F, const StageData& d,
+                                             Jet32& J)
+{
+    float c[32];
+    stencil_coefs<AMR>(g, F, d.base, c);
+    const float tx = d.t[0], ty = d.t[1], tz = d.t[2];
+    const float scale = (float)((double)(1 << d.lvl) * g.inv_h0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        J.G[j] = f[j + 1];
-        J.JG[j][0] = fx[j + 1] * scale;
-        J.JG[j][1] = fy[j + 1] * scale;
-        J.JG[j][2] = fz[j + 1] * scale;
+        const float* k = c + 8 * (j + 1);
+        J.JG[j][0] = (k[1] + ty * k[4] + tz * k[5] + ty * tz * k[7]) * scale;
+        J.JG[j][1] = (k[2] + tx * k[4] + tz * k[6] + tx * tz * k[7]) * scale;
+        J.JG[j][2] = (k[3] + tx * k[5] + ty * k[6] + tx * ty * k[7]) * scale;
     }
-    const CosmoDev& cz = A.c.cosmo;
-    J.H = Hc(cz, ys.eta);
-    J.dH = Hc.deriv(cz, ys.eta);
-    // right-hand side of the geodesic equations (Sect. 2.2) at the stage
-    const double k0 = J.Y.k0;
-    const double psi = J.G[0] * J.Y.k[0] + J.G[1] * J.Y.k[1] + J.G[2] * J.Y.k[2];
-    J.F.eta = k0;
-    J.F.k0 = -2.0 * J.H * k0 * k0 - 2.0 * psi * k0;
+}
+
+// Right-hand side of the geodesic equations (Sect. 2.2) at a stage.
+__device__ __forceinline__ Phys32 rhs32(const Jet32& J)
+{
+    Phys32 F;
+    const float k0 = J.k0;
+    const float psi = J.G[0] * J.k[0] + J.G[1] * J.k[1] + J.G[2] * J.k[2];
+    F.eta = k0;
+    F.k0 = -2.0f * J.H * k0 * k0 - 2.0f * psi * k0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        J.F.x[j] = J.Y.k[j];
-        J.F.k[j] = -2.0 * J.H * k0 * J.Y.k[j] + 2.0 * psi * J.Y.k[j] - 2.0 * J.G[j] * k0 * k0;
+        F.x[j] = J.k[j];
+        F.k[j] = -2.0f * J.H * k0 * J.k[j] + 2.0f * psi * J.k[j] - 2.0f * J.G[j] * k0 * k0;
     }
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        const double wx = (o & 1) ? tx : 1.0 - tx;
-        const double wy = (o & 2) ? ty : 1.0 - ty;
-        const double wz = (o & 4) ? tz : 1.0 - tz;
-        J.w[o] = (float)(wx * wy * wz);
-    }
-    J.base = base;
+    return F;
 }
 
 // Transposed Jacobian of the right-hand side at a stage applied to v:
 // Yb = (dF/dY)^T v and the cotangent Gb of the interpolated grad Phi.
-__device__ __forceinline__ void rhs_vjp(const Jet& J, const Phys& v, Phys& Yb, double Gb[3])
+//   F = (k0, k, -2 H k0^2 - 2 psi k0, -2 H k0 k + 2 psi k - 2 G k0^2), psi = G.k
+__device__ __forceinline__ void rhs_vjp32(const Jet32& J, const Phys32& v, Phys32& Yb, float Gb[3])
 {
-    const double k0 = J.Y.k0;
-    const double a = v.k0;
-    const double bk = v.k[0] * J.Y.k[0] + v.k[1] * J.Y.k[1] + v.k[2] * J.Y.k[2];
-    const double bG = v.k[0] * J.G[0] + v.k[1] * J.G[1] + v.k[2] * J.G[2];
-    const double psi = J.G[0] * J.Y.k[0] + J.G[1] * J.Y.k[1] + J.G[2] * J.Y.k[2];
+    const float k0 = J.k0;
+    const float a = v.k0;
+    const float bk = v.k[0] * J.k[0] + v.k[1] * J.k[1] + v.k[2] * J.k[2];
+    const float bG = v.k[0] * J.G[0] + v.k[1] * J.G[1] + v.k[2] * J.G[2];
+    const float psi = J.G[0] * J.k[0] + J.G[1] * J.k[1] + J.G[2] * J.k[2];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Gb[j] = -2.0 * k0 * a * J.Y.k[j] + 2.0 * bk * J.Y.k[j] - 2.0 * k0 * k0 * v.k[j];
-    Yb.eta = -2.0 * J.dH * k0 * (a * k0 + bk);
-    Yb.k0 = v.eta + a * (-4.0 * J.H * k0 - 2.0 * psi) - 2.0 * J.H * bk - 4.0 * k0 * bG;
+    for (int j = 0; j < 3; ++j) Gb[j] = -2.0f * k0 * a * J.k[j] + 2.0f * bk * J.k[j] - 2.0f * k0 * k0 * v.k[j];
+    Yb.eta = -2.0f * J.dH * k0 * (a * k0 + bk);
+    Yb.k0 = v.eta + a * (-4.0f * J.H * k0 - 2.0f * psi) - 2.0f * J.H * bk - 4.0f * k0 * bG;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-        Yb.k[j] = v.x[j] - 2.0 * k0 * a * J.G[j] + (-2.0 * J.H * k0 + 2.0 * psi) * v.k[j] + 2.0 * J.G[j] * bk;
+        Yb.k[j] = v.x[j] - 2.0f * k0 * a * J.G[j] + (-2.0f * J.H * k0 + 2.0f * psi) * v.k[j] + 2.0f * J.G[j] * bk;
 #pragma unroll
     for (int l = 0; l < 3; ++l) Yb.x[l] = J.JG[0][l] * Gb[0] + J.JG[1][l] * Gb[1] + J.JG[2][l] * Gb[2];
 }
 
-// Per-lane accumulator of cell cotangents for the current stencil (in LDS),
-// flushed to global memory with atomics when the stencil changes.
-struct Scatter {
-    float* acc;         // 32 slots, stride kBlock: (corner o, component q) at (4 o + q) * kBlock
-    int cur;
-
-    __device__ __forceinline__ void init(float* lds)
-    {
-        acc = lds;
-        cur = -1;
+__device__ __forceinline__ void cic_weights(const float t[3], float w[8])
+{
 #pragma unroll
-        for (int i = 0; i < 32; ++i) acc[i * kBlock] = 0.0f;
+    for (int o = 0; o < 8; ++o)
+        w[o] = ((o & 1) ? t[0] : 1.0f - t[0]) * ((o & 2) ? t[1] : 1.0f - t[1]) * ((o & 4) ? t[2] : 1.0f - t[2]);
+}
+
+// Cell cotangents in the adjoint workspace: component-major (phi, gx, gy,
+// gz), and within a component the ids of every aligned group of 8
+// consecutive cells (a Morton 2x2x2 block) spread over 8 regions, so that
+// the atomics of one stencil flush land in different cache lines instead of
+// serialising on one.
+__device__ __forceinline__ int64_t grad_slot(int64_t id, int q, int64_t n)
+{
+    const int64_t m = (n + 7) >> 3;
+    return (int64_t)q * (m << 3) + (id & 7) * m + (id >> 3);
+}
+
+// Per-wave table in LDS aggregating the gradient cotangents of recently
+// touched cells: open addressing on the cell id (linear probing), filled
+// with LDS atomics by the lanes of one wave and evicted to the cell array
+// with device atomics when it fills.  The 64 rays of a wave start from
+// neighbouring sky pixels and cross the same cells many times, so the table
+// absorbs most additions and the device atomics (which resolve beyond the
+// per-XCD L2) drop by that reuse factor.
+constexpr int kTab = 512;               // entries per wave (power of two)
+constexpr int kTabWords = 4 * kTab + 4; // keys, 3 value planes, fill counter (padded)
+
+struct WaveTable {
+    int* keys;
+    float* vals;        // [3][kTab]
+    int* count;
+
+    __device__ __forceinline__ void bind(float* base)
+    {
+        keys = reinterpret_cast<int*>(base);
+        vals = base + kTab;
+        count = reinterpret_cast<int*>(base + 4 * kTab);
     }
 
-    __device__ __forceinline__ void flush(const AdjointArgs& A)
+    // every lane of the (full) wave clears a share of the table
+    __device__ __forceinline__ void clear(int lane)
     {
-        if (cur < 0) return;
-        const int32_t* ids = A.c.grid.dual_ids + 8 * (int64_t)cur;
+        for (int e = lane; e < kTab; e += 64) {
+            keys[e] = -1;
+            vals[e] = 0.0f;
+            vals[kTab + e] = 0.0f;
+            vals[2 * kTab + e] = 0.0f;
+        }
+        if (lane == 0) *count = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+
+    // Move every entry to the cell array; the currently active lanes share
+    // the work.
+    __device__ __forceinline__ void evict(const AdjointArgs& A)
+    {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int lane = threadIdx.x & 63;
+        const uint64_t act = __ballot(1);
+        const int nact = __popcll(act);
+        const int rank = __popcll(act & ((1ull << lane) - 1ull));
+        for (int e = rank; e < kTab; e += nact) {
+            const int key = keys[e];
+            if (key >= 0) {
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const int id = ids[o];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float v = acc[(4 * o + q) * kBlock];
-                if (v != 0.0f && id >= 0) unsafeAtomicAdd(A.grad + 4 * (int64_t)id + q, v);
-                acc[(4 * o + q) * kBlock] = 0.0f;
+                for (int q = 0; q < 3; ++q) {
+                    const float v = vals[q * kTab + e];
+                    if (v != 0.0f) unsafeAtomicAdd(A.grad + grad_slot(key, 1 + q, A.n_cells), v);
+                    vals[q * kTab + e] = 0.0f;
+                }
+                keys[e] = -1;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (rank == 0) *count = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+
+    // Add v to cell id.  The caller keeps at least one free slot per active
+    // lane, so the probe ends.
+    __device__ __forceinline__ void add(int id, const float v[3])
+    {
+        uint32_t h = ((uint32_t)id * 2654435761u) >> (32 - 9);
+        for (;;) {
+            const int old = atomicCAS(&keys[h], -1, id);
+            if (old == -1) {
+                atomicAdd(count, 1);
+                break;
+            }
+            if (old == id) break;
+            h = (h + 1) & (kTab - 1);
+        }
+        atomicAdd(&vals[h], v[0]);
+        atomicAdd(&vals[kTab + h], v[1]);
+        atomicAdd(&vals[2 * kTab + h], v[2]);
+    }
+};
+static_assert(kTab == 512, "the probe hash takes the top 9 bits");
+
+// Per-lane accumulator (registers) of the gradient cotangents of the 8 cells
+// of the current stencil, moved into the wave's table when the stencil
+// changes.  The cell ids of the current stencil are loaded when it becomes
+// current, so the load is in flight long before the flush needs it.
+struct Scatter {
+    float acc[8][3];
+    int ids[8];
+    int cur;
+
+    __device__ __forceinline__ void init()
+    {
+        cur = -1;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            ids[o] = -1;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[o][q] = 0.0f;
+        }
+    }
+
+    __device__ __forceinline__ void flush(const AdjointArgs& A, WaveTable& T)
+    {
+        if (cur < 0) return;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            // at most one insertion per active lane follows: keep 64 slots free
+            if (*T.count > kTab - 64) T.evict(A);
+            if (ids[o] >= 0 && (acc[o][0] != 0.0f || acc[o][1] != 0.0f || acc[o][2] != 0.0f)) T.add(ids[o], acc[o]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[o][q] = 0.0f;
+        }
         cur = -1;
     }
 
-    // add w_o * vals[q] to component q0 + q of corner o
-    __device__ __forceinline__ void add(const AdjointArgs& A, int base, const float w[8], int q0, int nq,
-                                        const double* vals)
+    __device__ __forceinline__ void add(const AdjointArgs& A, WaveTable& T, int base, const float t[3],
+                                        const float Gb[3])
     {
         if (base != cur) {
-            flush(A);
+            flush(A, T);
             cur = base;
+            const int4* p = reinterpret_cast<const int4*>(A.c.grid.dual_ids + 8 * (int64_t)base);
+            const int4 a = p[0], b = p[1];
+            ids[0] = a.x; ids[1] = a.y; ids[2] = a.z; ids[3] = a.w;
+            ids[4] = b.x; ids[5] = b.y; ids[6] = b.z; ids[7] = b.w;
         }
+        float w[8];
+        cic_weights(t, w);
 #pragma unroll
         for (int o = 0; o < 8; ++o)
-            for (int q = 0; q < nq; ++q) acc[(4 * o + q0 + q) * kBlock] += w[o] * (float)vals[q];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[o][q] += w[o] * Gb[q];
     }
 };
+
+// Direct atomics of a Phi cotangent onto the 8 cells of a stencil.
+__device__ __forceinline__ void scatter_phi(const AdjointArgs& A, int base, const double t[3], double v)
+{
+    if (v == 0.0) return;
+    const int32_t* ids = A.c.grid.dual_ids + 8 * (int64_t)base;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const double w = ((o & 1) ? t[0] : 1.0 - t[0]) * ((o & 2) ? t[1] : 1.0 - t[1]) *
+                         ((o & 4) ? t[2] : 1.0 - t[2]);
+        const int id = ids[o];
+        if (id >= 0) unsafeAtomicAdd(A.grad + grad_slot(id, 0, A.n_cells), (float)(w * v));
+    }
+}
 
 // Step length and landing decision at the start of a step, exactly as the
 // forward kernels take them.
@@ -247,55 +463,31 @@ __device__ __forceinline__ bool plan_step(const CastArgs& a, FieldCache<AMR>& F,
     const int lstep = a.adaptive ? L : 0;
     ds = g.h0 / (double)(1 << lstep) / (double)a.steps_per_cell;
     dl = ds / y.K;
-    landing = y.eta - y.K * dl < eta_s;
+    landing = fma(-y.K, dl, y.eta) < eta_s;
     return true;
 }
 
 // One forward step (regular or landing) from y, as in the forward kernels;
-// records the stages of the final RK4 pass when rec is given.  Returns the
-// affine length of the step taken through *dl_taken.
+// records the stages of the final RK4 pass into rec when record is set.  Returns the
+// affine length of the step taken through dl_taken.
 template <bool AMR, class Rec>
 __device__ __forceinline__ bool forward_step(const CastArgs& a, FieldCache<AMR>& F, const RayGeom& geo,
-                                             const GeoState& y, double eta_s, GeoState& yn, Rec* rec,
+                                             const GeoState& y, double eta_s, GeoState& yn, Rec& rec, bool record,
                                              double& dl_taken, double& ds_out, bool& landing)
 {
     double ds, dl;
     if (!plan_step<AMR>(a, F, geo, y, eta_s, ds, dl, landing)) return false;
     double dlx = landing ? (y.eta - eta_s) / y.K : dl;
     uint32_t h = 0;
-    if (landing) {
-        for (int k = 0; k < 2; ++k) {
-            if (rk4_step<AMR>(a.grid, a.cosmo, F, geo, y, dlx, yn, h)) return false;
-            dlx = dlx + (yn.eta - eta_s) / yn.K;
-        }
+    // landing: two Newton passes for the step length, then the step
+    const int passes = landing ? 3 : 1;
+    for (int k = 0; k < passes; ++k) {
+        if (rk4_step<AMR, Rec>(a.grid, a.cosmo, F, geo, y, dlx, yn, h, rec, record && k + 1 == passes))
+            return false;
+        if (k + 1 < passes) dlx = dlx + (yn.eta - eta_s) / yn.K;
     }
-    if (rk4_step<AMR, Rec>(a.grid, a.cosmo, F, geo, y, dlx, yn, h, rec)) return false;
     dl_taken = dlx;
     ds_out = ds;
-    return true;
-}
-
-// Recompute segment seg (steps [seg K, min(N, (seg + 1) K))) from its
-// checkpoint, storing the state before each step in the tape; returns the
-// state after the segment.
-template <bool AMR>
-__device__ __forceinline__ bool recompute_segment(const AdjointArgs& A, FieldCache<AMR>& F, const RayGeom& geo,
-                                                  double eta_s, int64_t ray, int seg, int N, GeoState& yend)
-{
-    const CastArgs& a = A.c;
-    const int K = a.ckpt_every;
-    GeoState y = a.ckpt[(int64_t)seg * a.n_rays + ray];
-    const int j1 = min(N, (seg + 1) * K);
-    for (int j = seg * K; j < j1; ++j) {
-        A.tape[(int64_t)(j - seg * K) * a.n_rays + ray] = y;
-        GeoState yn;
-        double dl, ds;
-        bool landing;
-        if (!forward_step<AMR, NoRecord>(a, F, geo, y, eta_s, yn, (NoRecord*)nullptr, dl, ds, landing))
-            return false;
-        y = yn;
-    }
-    yend = y;
     return true;
 }
 
@@ -306,48 +498,72 @@ __device__ __forceinline__ bool recompute_segment(const AdjointArgs& A, FieldCac
 //   Fbar_4 = dl/6 v,  Ybar_i = J_i^T Fbar_i,
 //   Fbar_{i-1} = w_{i-1}/6 dl v + c_i dl Ybar_i,  ybar = v + sum_i Ybar_i,
 //   dlbar = sum_i (w_i/6) v.F_i + sum_{i>1} c_i Ybar_i.F_{i-1}.
-template <bool AMR, int W, bool SCATTER>
-__device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx& R, const StageRecord& rec,
-                                             const HubbleCubic& Hc, double dl, double ds_reg, double k0_step,
-                                             Phys (&yb)[W], Scatter& S)
+// Stage I (0-based) is handled with J holding its jet; the recursion moves
+// to stage I - 1.
+template <int I, bool AMR, int W, bool SCATTER>
+__device__ __forceinline__ void reverse_stage(const AdjointArgs& A, const RayCtx& R, const FieldCache<AMR>& F,
+                                              const StageRecord& rec, const HubbleCubic& Hc, float dlf, Jet32& J,
+                                              const Phys32 (&v)[W], Phys32 (&Fb)[W], float (&dlbar)[W],
+                                              Phys (&yb)[W], Scatter& S, WaveTable& T)
 {
-    Phys v[W], Fb[W];
-    double dlbar[W];
-    Jet J;
-    make_jet(A, R, rec.y[3], rec.base[3], rec.lvl[3], Hc, J);
+    Jet32 P;
+    Phys32 FP;
+    if constexpr (I > 0) {
+        jet_from_stage(A, R, rec.template get<I - 1>(), Hc, P);
+        FP = rhs32(P);
+    }
+    constexpr float ci = (I == 3) ? 1.0f : 0.5f;
+    constexpr float wprev = (I == 1) ? 1.0f : 2.0f;
 #pragma unroll
     for (int c = 0; c < W; ++c) {
-        v[c] = yb[c];
-        dlbar[c] = phys_dot(v[c], J.F) / 6.0;
-        phys_zero(Fb[c]);
-        phys_axpy(Fb[c], dl / 6.0, v[c]);
+        Phys32 Yb;
+        float Gb[3];
+        rhs_vjp32(J, Fb[c], Yb, Gb);
+        phys_axpy(yb[c], 1.0, Yb);
+        if (SCATTER && c == W - 1) S.add(A, T, J.base, J.t, Gb);
+        if constexpr (I > 0) {
+            dlbar[c] += ci * phys_dot(Yb, FP) + (wprev * (1.0f / 6.0f)) * phys_dot(v[c], FP);
+            phys_zero(Fb[c]);
+            phys_axpy(Fb[c], wprev * (1.0f / 6.0f) * dlf, v[c]);
+            phys_axpy(Fb[c], ci * dlf, Yb);
+        }
     }
-#pragma unroll 1
-    for (int i = 3; i >= 0; --i) {
-        Jet P;
-        if (i > 0) make_jet(A, R, rec.y[i - 1], rec.base[i - 1], rec.lvl[i - 1], Hc, P);
-        const double ci = (i == 3) ? 1.0 : 0.5;
-        const double wprev = (i == 1) ? 1.0 : 2.0;
+    if constexpr (I > 0) {
+        J = P;
+        jet_gradient<AMR>(A.c.grid, F, rec.template get<I - 1>(), J);
+        reverse_stage<I - 1, AMR, W, SCATTER>(A, R, F, rec, Hc, dlf, J, v, Fb, dlbar, yb, S, T);
+    }
+}
+
+template <bool AMR, int W, bool SCATTER>
+__device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx& R, const FieldCache<AMR>& F,
+                                             const StageRecord& rec, const HubbleCubic& Hc, double dl,
+                                             double ds_reg, double k0_step, Phys (&yb)[W], Scatter& S,
+                                             WaveTable& T)
+{
+    const float dlf = (float)dl;
+    Phys32 v[W], Fb[W];
+    float dlbar[W];
+    Jet32 J;
+    const StageData d3 = rec.template get<3>();
+    jet_from_stage(A, R, d3, Hc, J);
+    jet_gradient<AMR>(A.c.grid, F, d3, J);
+    {
+        const Phys32 F4 = rhs32(J);
 #pragma unroll
         for (int c = 0; c < W; ++c) {
-            Phys Yb;
-            double Gb[3];
-            rhs_vjp(J, Fb[c], Yb, Gb);
-            phys_axpy(yb[c], 1.0, Yb);
-            if (SCATTER && c == W - 1) S.add(A, J.base, J.w, 1, 3, Gb);
-            if (i > 0) {
-                dlbar[c] += ci * phys_dot(Yb, P.F) + (wprev / 6.0) * phys_dot(v[c], P.F);
-                phys_zero(Fb[c]);
-                phys_axpy(Fb[c], wprev / 6.0 * dl, v[c]);
-                phys_axpy(Fb[c], ci * dl, Yb);
-            }
+            v[c] = to32(yb[c]);
+            dlbar[c] = phys_dot(v[c], F4) * (1.0f / 6.0f);
+            phys_zero(Fb[c]);
+            phys_axpy(Fb[c], dlf * (1.0f / 6.0f), v[c]);
         }
-        if (i > 0) J = P;
     }
+    reverse_stage<3, AMR, W, SCATTER>(A, R, F, rec, Hc, dlf, J, v, Fb, dlbar, yb, S, T);
     // a regular step has dl = ds / |k0| with ds fixed by the leaf level
     if (ds_reg > 0.0) {
+        const double f = ds_reg / (k0_step * k0_step);
 #pragma unroll
-        for (int c = 0; c < W; ++c) yb[c].k0 += dlbar[c] * ds_reg / (k0_step * k0_step);
+        for (int c = 0; c < W; ++c) yb[c].k0 += (double)dlbar[c] * f;
     }
 }
 
@@ -379,64 +595,70 @@ __device__ __forceinline__ void screen_basis(const double v[3], double e1[3], do
     e2[0] = -cp * ct; e2[1] = -sp * ct; e2[2] = st;
 }
 
-// W cotangent columns: W = 4 (beta_1, beta_2, z, L), 3 (beta_1, beta_2, z)
-// or 1 (L).  SCATTER: the last column is L and its cell cotangents are kept.
-template <bool AMR, int W, bool SCATTER>
-__global__ __launch_bounds__(kBlock, kMinWavesAdj) void adjoint_kernel(AdjointArgs A)
+// Double-precision interpolation jet at one point (end point and observer):
+// Phi, its gradient, grad Phi and the right-hand side there.
+struct PointJet {
+    double phi, gphi[3], G[3], t[3];
+    Phys F;
+};
+
+__device__ __forceinline__ void point_jet(const AdjointArgs& A, const RayCtx& R, const GeoState& ys, int base,
+                                          int lvl, const HubbleCubic& Hc, PointJet& P)
 {
-    extern __shared__ float lds[];      // [32][kBlock] stencil coefficients, [32][kBlock] scatter
-    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const CastArgs& a = A.c;
-    if (ray >= a.n_rays) return;
-    constexpr bool HAS_JAC = W >= 3;
-    const int N = A.n_steps[ray];
-    if (A.status[ray] != MPATH_RAY_REACHED || N <= 0) {
-        if (HAS_JAC) write_nan_jacobian(A, ray);
-        return;
-    }
-    const GridDev& g = a.grid;
-    int j = a.n_obs - 1;
-    while (j > 0 && a.obs[j].ray_first > ray) --j;
-    const ObsDev& ob = a.obs[j];
-    RayCtx R;
+    const GridDev& g = A.c.grid;
+    stage_offsets(g, R, ys, lvl, P.t);
+    const float4* rec = g.dual + 8 * (int64_t)base;
+    double c[4][8];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        R.xobs[i] = ob.x[i];
-        R.geo.uo[i] = ob.x[i] / g.h0;
-        R.geo.n[i] = a.dirs[3 * ray + i];
+    for (int o = 0; o < 8; ++o) {
+        const float4 q = rec[o];
+        c[0][o] = q.x; c[1][o] = q.y; c[2][o] = q.z; c[3][o] = q.w;
     }
-    const double eta_s = ob.eta_s;
-    FieldCache<AMR> F;
-    F.bind(lds + threadIdx.x);
-    F.reset();
-    Scatter S;
-    S.init(lds + 32 * kBlock + threadIdx.x);
+    const double scale = (double)(1 << lvl) * g.inv_h0;
+    double fx, fy, fz;
+    trilinear_jet<double>(c[0], P.t[0], P.t[1], P.t[2], P.phi, fx, fy, fz);
+    P.gphi[0] = fx * scale; P.gphi[1] = fy * scale; P.gphi[2] = fz * scale;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) trilinear_jet<double>(c[j + 1], P.t[0], P.t[1], P.t[2], P.G[j], fx, fy, fz);
+    const double H = Hc(A.c.cosmo, ys.eta);
+    const double k0 = -ys.K;
+    double k[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k[i] = ys.K * (R.geo.n[i] + (double)ys.d[i]);
+    const double psi = P.G[0] * k[0] + P.G[1] * k[1] + P.G[2] * k[2];
+    P.F.eta = k0;
+    P.F.k0 = -2.0 * H * k0 * k0 - 2.0 * psi * k0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        P.F.x[j] = k[j];
+        P.F.k[j] = -2.0 * H * k0 * k[j] + 2.0 * psi * k[j] - 2.0 * P.G[j] * k0 * k0;
+    }
+}
 
-    // potential at the observer and the initial |k| (as in the forward)
-    float phio_f, Gt[3];
+// Cotangents of the state at the end point yf (on the source surface):
+// beta_a and z columns, and the loss column from dL/dalpha and dL/dz5; the
+// direct Phi_s term of the loss is scattered to the end point's stencil and
+// the Phi_o term returned.  The landing step has its length set by
+// eta(y_f) = eta_s, so the cotangent along the flow F(y_f) is removed.
+template <bool AMR, int W, bool SCATTER>
+__device__ __forceinline__ void end_cotangents(const AdjointArgs& A, const RayCtx& R, FieldCache<AMR>& F,
+                                               const ObsDev& ob, const GeoState& yf, double phio,
+                                               const double e1[3], const double e2[3], Phys (&yb)[W],
+                                               double& phio_bar)
+{
+    constexpr bool HAS_JAC = W >= 3;
+    const GridDev& g = A.c.grid;
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float ph_f, Gt[3];
     int ll, lv;
-    F.eval(g, R.geo.uo, phio_f, Gt, ll, lv);
-    const int obs_base = F.base, obs_lvl = F.lvl;
-    const double phio = (double)phio_f;
-    const double kmag = sqrt((1.0 + 2.0 * phio) / (1.0 - 2.0 * phio));
-
-    const int K = a.ckpt_every;
-    const int nseg = (N + K - 1) / K;
-    GeoState yf;
-    if (!recompute_segment<AMR>(A, F, R.geo, eta_s, ray, nseg - 1, N, yf)) {
-        if (HAS_JAC) write_nan_jacobian(A, ray);
-        return;
-    }
-
-    // ---- cotangents at the end point ----
-    float ph_f;
     double uf[3];
     grid_coords(g, R.geo, yf.eta, yf.dx, uf);
     F.eval(g, uf, ph_f, Gt, ll, lv);
     HubbleCubic Hf;
-    Hf.init(a.cosmo, yf.eta);
-    Jet Jf;
-    make_jet(A, R, yf, F.base, F.lvl, Hf, Jf);
+    Hf.init(A.c.cosmo, yf.eta);
+    PointJet Jf;
+    point_jet(A, R, yf, F.base, F.lvl, Hf, Jf);
+    const int end_base = F.base;
     const double* n = R.geo.n;
     double r[3];
     const double sf = g.eta0 - yf.eta;
@@ -444,15 +666,12 @@ __global__ __launch_bounds__(kBlock, kMinWavesAdj) void adjoint_kernel(AdjointAr
     for (int i = 0; i < 3; ++i) r[i] = sf * n[i] + (double)yf.dx[i];
     const double chi = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
     const double rh[3] = {r[0] / chi, r[1] / chi, r[2] / chi};
-    double f1[3], f2[3], e1[3], e2[3];
+    double f1[3], f2[3];
     screen_basis(rh, f1, f2);
-    screen_basis(n, e1, e2);
     const double phis = Jf.phi;
     const double dz_dK = ob.a_s * (1.0 + phis) / (1.0 + phio);
     const double dz_dphis = ob.a_s * yf.K / (1.0 + phio);
     const double dz_dphio = -ob.a_s * yf.K * (1.0 + phis) / ((1.0 + phio) * (1.0 + phio));
-
-    Phys yb[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) phys_zero(yb[c]);
     if (HAS_JAC) {
@@ -464,9 +683,8 @@ __global__ __launch_bounds__(kBlock, kMinWavesAdj) void adjoint_kernel(AdjointAr
         }
         yb[2].k0 = -dz_dK;
     }
-    double phio_bar = 0.0;
+    phio_bar = 0.0;
     if (SCATTER) {
-        // loss column: dL/dalpha through alpha(r^) and dL/dz5
         const float ga0 = A.dL_dalpha ? A.dL_dalpha[2 * ray] : 0.0f;
         const float ga1 = A.dL_dalpha ? A.dL_dalpha[2 * ray + 1] : 0.0f;
         const double gz = A.dL_dz ? A.dL_dz[ray] : 0.0;
@@ -478,7 +696,7 @@ __global__ __launch_bounds__(kBlock, kMinWavesAdj) void adjoint_kernel(AdjointAr
         for (int i = 0; i < 3; ++i) t[i] = rh[i] - cth * n[i];
         const double st = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
         const double sig = atan2(st, cth);
-        double fs, fps;           // f and f'/sin sigma
+        double fs, fps;           // f and f'/sin sigma (series below 1e-3 rad)
         if (sig < 1e-3) {
             fs = 1.0 + sig * sig / 6.0;
             fps = 1.0 / 3.0 + sig * sig * (2.0 / 15.0);
@@ -504,44 +722,130 @@ __global__ __launch_bounds__(kBlock, kMinWavesAdj) void adjoint_kernel(AdjointAr
 #pragma unroll
         for (int i = 0; i < 3; ++i) L.x[i] = (cb[0] * f1[i] + cb[1] * f2[i]) / chi + gz * dz_dphis * Jf.gphi[i];
         L.k0 = -gz * dz_dK;
-        const double phis_bar = gz * dz_dphis;
-        S.add(A, Jf.base, Jf.w, 0, 1, &phis_bar);
+        scatter_phi(A, end_base, Jf.t, gz * dz_dphis);
         phio_bar = gz * dz_dphio;
     }
-    // landing: eta_s fixed, so the last affine step depends on the state;
-    // remove the cotangent along the flow (d y_f / d dl ~ F(y_f), d eta_f / d dl = k0)
 #pragma unroll
     for (int c = 0; c < W; ++c) yb[c].eta -= phys_dot(yb[c], Jf.F) / Jf.F.eta;
+}
 
-    // ---- reverse sweep ----
-    for (int seg = nseg - 1; seg >= 0; --seg) {
-        GeoState ytmp;
-        if (seg != nseg - 1)
-            if (!recompute_segment<AMR>(A, F, R.geo, eta_s, ray, seg, N, ytmp)) {
-                if (HAS_JAC) write_nan_jacobian(A, ray);
-                return;
-            }
+// W cotangent columns: W = 4 (beta_1, beta_2, z, L), 3 (beta_1, beta_2, z)
+// or 1 (L).  SCATTER: the last column is L and its cell cotangents are kept.
+template <bool AMR, int W, bool SCATTER>
+__global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
+{
+    // LDS: [32][kBlock] stencil coefficients, [4 * 18][kBlock] stage records,
+    // then one table per wave
+    extern __shared__ float lds[];
+    WaveTable T;
+    if (SCATTER) {
+        T.bind(lds + (32 + 4 * StageRecord::kWords) * kBlock + (threadIdx.x >> 6) * kTabWords);
+        T.clear(threadIdx.x & 63);
+    }
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const CastArgs& a = A.c;
+    if (ray >= a.n_rays) return;
+    constexpr bool HAS_JAC = W >= 3;
+    const int N = A.n_steps[ray];
+    if (A.status[ray] != MPATH_RAY_REACHED || N <= 0) {
+        if (HAS_JAC) write_nan_jacobian(A, ray);
+        if (A.ray_status) A.ray_status[ray] = 1;
+        return;
+    }
+    const GridDev& g = a.grid;
+    int j = a.n_obs - 1;
+    while (j > 0 && a.obs[j].ray_first > ray) --j;
+    const ObsDev& ob = a.obs[j];
+    RayCtx R;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        R.xobs[i] = ob.x[i];
+        R.geo.uo[i] = ob.x[i] / g.h0;
+        R.geo.n[i] = a.dirs[3 * ray + i];
+    }
+    const double eta_s = ob.eta_s;
+    FieldCache<AMR> F;
+    F.bind(lds + threadIdx.x);
+    F.reset();
+
+    // potential at the observer and the initial |k| (as in the forward)
+    float phio_f, Gt[3];
+    int ll, lv;
+    F.eval(g, R.geo.uo, phio_f, Gt, ll, lv);
+    const int obs_base = F.base, obs_lvl = F.lvl;
+    const double phio = (double)phio_f;
+    const double kmag = sqrt((1.0 + 2.0 * phio) / (1.0 - 2.0 * phio));
+
+    const int K = a.ckpt_every;
+    const int nseg = (N + K - 1) / K;
+    const double* n = R.geo.n;
+    double e1[3], e2[3];
+    screen_basis(n, e1, e2);
+    Phys yb[W];
+    double phio_bar = 0.0;
+    Scatter S;
+    S.init();
+
+    // Segments from the source back to the observer.  Each is traversed
+    // forwards from its checkpoint (storing the state before every step in
+    // the tape; the last step of a segment other than the final one is not
+    // needed, its result being the next checkpoint), then backwards with the
+    // stages of every step re-recorded and reversed.  One loop with a single
+    // step call site serves both directions.
+    bool ok = true;
+    for (int seg = nseg - 1; seg >= 0 && ok; --seg) {
+        const bool last = seg == nseg - 1;
         const int j0 = seg * K;
-        const int j1 = min(N, (seg + 1) * K) - 1;
-        for (int jj = j1; jj >= j0; --jj) {
-            const GeoState y = A.tape[(int64_t)(jj - j0) * a.n_rays + ray];
+        const int len = min(N, j0 + K) - j0;
+        const int nf = last ? len : len - 1;
+        GeoState y = a.ckpt[(int64_t)seg * a.n_rays + ray];
+        for (int it = 0; it < nf + len; ++it) {
+            const bool fwd = it < nf;
+            if (it == nf) {
+                if (!last) {
+                    A.tape[(int64_t)(len - 1) * a.n_rays + ray] = y;
+                } else {
+                    // the replay must end where the forward cast ended, bit for bit
+                    const RayEnd e = a.ends[ray];
+                    if (y.eta != e.eta || y.dx[0] != e.dx[0] || y.dx[1] != e.dx[1] || y.dx[2] != e.dx[2]) {
+                        ok = false;
+                        break;
+                    }
+                    end_cotangents<AMR, W, SCATTER>(A, R, F, ob, y, phio, e1, e2, yb, phio_bar);
+                }
+            }
+            const int jl = fwd ? it : len - 1 - (it - nf);
+            GeoState ys;
+            if (fwd) {
+                A.tape[(int64_t)jl * a.n_rays + ray] = y;
+                ys = y;
+            } else {
+                ys = A.tape[(int64_t)jl * a.n_rays + ray];
+            }
             StageRecord rec;
+            rec.p = lds + 32 * kBlock + threadIdx.x;
             GeoState yn;
             double dl, ds;
             bool landing;
-            if (!forward_step<AMR, StageRecord>(a, F, R.geo, y, eta_s, yn, &rec, dl, ds, landing)) {
-                if (HAS_JAC) write_nan_jacobian(A, ray);
-                return;
+            if (!forward_step<AMR, StageRecord>(a, F, R.geo, ys, eta_s, yn, rec, !fwd, dl, ds, landing)) {
+                ok = false;
+                break;
             }
-            HubbleCubic Hc;
-            Hc.init(a.cosmo, y.eta);
-            const double ds_reg = landing ? 0.0 : ds;
-            reverse_step<AMR, W, SCATTER>(A, R, rec, Hc, dl, ds_reg, -y.K, yb, S);
+            if (fwd) {
+                y = yn;
+            } else {
+                HubbleCubic Hc;
+                Hc.init(a.cosmo, ys.eta);
+                const double ds_reg = landing ? 0.0 : ds;
+                reverse_step<AMR, W, SCATTER>(A, R, F, rec, Hc, dl, ds_reg, -ys.K, yb, S, T);
+            }
         }
     }
 
     // ---- the initial state: k = kmag(Phi_o) n (theta), k0 = -1 ----
-    if (HAS_JAC) {
+    if (HAS_JAC && !ok) write_nan_jacobian(A, ray);
+    if (A.ray_status) A.ray_status[ray] = ok ? 0 : 2;
+    if (HAS_JAC && ok) {
         const double* eb[2] = {e1, e2};
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb) {
@@ -556,19 +860,22 @@ __global__ __launch_bounds__(kBlock, kMinWavesAdj) void adjoint_kernel(AdjointAr
         }
     }
     if (SCATTER) {
-        const Phys& L = yb[W - 1];
-        const double dkmag = kmag * 2.0 / (1.0 - 4.0 * phio * phio);
-        phio_bar += (L.k[0] * n[0] + L.k[1] * n[1] + L.k[2] * n[2]) * dkmag;
-        // CIC weights at the observer
-        GeoState y0;
-        y0.eta = g.eta0;
-        y0.K = 1.0;
+        if (ok) {
+            S.flush(A, T);
+            const Phys& L = yb[W - 1];
+            const double dkmag = kmag * 2.0 / (1.0 - 4.0 * phio * phio);
+            phio_bar += (L.k[0] * n[0] + L.k[1] * n[1] + L.k[2] * n[2]) * dkmag;
+            GeoState y0;
+            y0.eta = g.eta0;
+            y0.K = 1.0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) { y0.d[i] = 0.0f; y0.dx[i] = 0.0f; }
-        Jet J0;
-        make_jet(A, R, y0, obs_base, obs_lvl, Hf, J0);
-        S.add(A, obs_base, J0.w, 0, 1, &phio_bar);
-        S.flush(A);
+            for (int i = 0; i < 3; ++i) { y0.d[i] = 0.0f; y0.dx[i] = 0.0f; }
+            double t0[3];
+            stage_offsets(g, R, y0, obs_lvl, t0);
+            scatter_phi(A, obs_base, t0, phio_bar);
+        }
+        // every lane that took a ray arrives here together: empty the table
+        T.evict(A);
     }
 }
 
@@ -578,13 +885,15 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t n)
     if (i < n) p[i] = 0.0f;
 }
 
-// Cell cotangents from library order to the caller's order (overwrites).
-__global__ void scatter_grad_kernel(const float4* __restrict__ g_lib, const int64_t* __restrict__ perm,
+// Cell cotangents from the workspace layout to the caller's order and
+// layout [n][4] (overwrites).
+__global__ void scatter_grad_kernel(const float* __restrict__ g_lib, const int64_t* __restrict__ perm,
                                     float4* __restrict__ out, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    out[perm[i]] = g_lib[i];
+    out[perm[i]] = make_float4(g_lib[grad_slot(i, 0, n)], g_lib[grad_slot(i, 1, n)], g_lib[grad_slot(i, 2, n)],
+                               g_lib[grad_slot(i, 3, n)]);
 }
 
 // On a uniform periodic grid whose gradient is the central difference of the
@@ -592,7 +901,7 @@ __global__ void scatter_grad_kernel(const float4* __restrict__ g_lib, const int6
 // cotangent of Phi is the direct one plus the transposed difference operator
 // applied to the cotangents of g:
 //   dL/dPhi[c] += sum_d (gbar_d[c - e_d] - gbar_d[c + e_d]) / (2 h0).
-__global__ void central_transpose_kernel(const float4* __restrict__ g_lib, const int4* __restrict__ cellpos,
+__global__ void central_transpose_kernel(const float* __restrict__ g_lib, const int4* __restrict__ cellpos,
                                          const int64_t* __restrict__ perm, float* __restrict__ out, int n0,
                                          double inv_2h, int64_t n)
 {
@@ -601,10 +910,11 @@ __global__ void central_transpose_kernel(const float4* __restrict__ g_lib, const
     const int4 p = cellpos[c];
     const uint32_t m = (uint32_t)n0 - 1u;
     auto id = [m](int i, int j, int k) { return (int64_t)morton3((uint32_t)i & m, (uint32_t)j & m, (uint32_t)k & m); };
-    double acc = (double)g_lib[c].x;
-    acc += ((double)g_lib[id(p.x - 1, p.y, p.z)].y - (double)g_lib[id(p.x + 1, p.y, p.z)].y) * inv_2h;
-    acc += ((double)g_lib[id(p.x, p.y - 1, p.z)].z - (double)g_lib[id(p.x, p.y + 1, p.z)].z) * inv_2h;
-    acc += ((double)g_lib[id(p.x, p.y, p.z - 1)].w - (double)g_lib[id(p.x, p.y, p.z + 1)].w) * inv_2h;
+    auto gq = [&](int64_t cell, int q) { return (double)g_lib[grad_slot(cell, q, n)]; };
+    double acc = gq(c, 0);
+    acc += (gq(id(p.x - 1, p.y, p.z), 1) - gq(id(p.x + 1, p.y, p.z), 1)) * inv_2h;
+    acc += (gq(id(p.x, p.y - 1, p.z), 2) - gq(id(p.x, p.y + 1, p.z), 2)) * inv_2h;
+    acc += (gq(id(p.x, p.y, p.z - 1), 3) - gq(id(p.x, p.y, p.z + 1), 3)) * inv_2h;
     out[perm[c]] = (float)acc;
 }
 
@@ -615,7 +925,8 @@ hipError_t launch_adjoint(const AdjointArgs& A, int columns, hipStream_t s)
     const int64_t n = A.c.n_rays;
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
-    const size_t lds = (size_t)64 * kBlock * sizeof(float);
+    const size_t lds_cache = (size_t)(32 + 4 * StageRecord::kWords) * kBlock * sizeof(float);
+    const size_t lds = lds_cache + (columns == 3 ? 0 : (size_t)(kBlock / 64) * kTabWords * sizeof(float));
     const bool amr = A.c.grid.max_level > 0;
     if (columns == 4) {
         if (amr) hipLaunchKernelGGL((adjoint_kernel<true, 4, true>), grid, block, lds, s, A);
@@ -637,7 +948,7 @@ hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_grad(const float4* grad_lib, const int64_t* perm, float4* out_user, int64_t n,
+hipError_t launch_scatter_grad(const float* grad_lib, const int64_t* perm, float4* out_user, int64_t n,
                                hipStream_t s)
 {
     if (n == 0) return hipSuccess;
@@ -646,7 +957,7 @@ hipError_t launch_scatter_grad(const float4* grad_lib, const int64_t* perm, floa
     return hipGetLastError();
 }
 
-hipError_t launch_central_transpose(const float4* g_lib, const int4* cellpos, const int64_t* perm, float* out,
+hipError_t launch_central_transpose(const float* g_lib, const int4* cellpos, const int64_t* perm, float* out,
                                     int n0, double h0, int64_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;

@@ -100,7 +100,7 @@ struct RayRun {
             const double dl = ds / y.K;
             // landing on the iso-eta surface: Newton on eta_RK4(dl) = eta_s
             // with derivative -K at the trial end, two iterations, then the step
-            const bool landing = y.eta - y.K * dl < eta_s;
+            const bool landing = fma(-y.K, dl, y.eta) < eta_s;
             double dlx = landing ? (y.eta - eta_s) / y.K : dl;
             const int passes = landing ? 3 : 1;
             GeoState yn;

@@ -78,6 +78,7 @@ struct HubbleCubic {
 
     __device__ __forceinline__ void init(const CosmoDev& c, double eta)
     {
+        #pragma clang fp contract(off)
         eta_n = eta;
         if (c.is_static) { b0 = b1 = b2 = b3 = 0.0; return; }
         const double u = (eta - c.eta_lo) * c.inv_deta;
@@ -88,19 +89,21 @@ struct HubbleCubic {
         const double2 p1 = c.table[i + 1];
         // Hermite cubic in t: a0 + a1 t + a2 t^2 + a3 t^3
         const double a0 = p0.x, a1 = c.deta * p0.y;
-        const double a2 = 3.0 * (p1.x - p0.x) - c.deta * (2.0 * p0.y + p1.y);
-        const double a3 = 2.0 * (p0.x - p1.x) + c.deta * (p0.y + p1.y);
+        const double a2 = fma(-c.deta, fma(2.0, p0.y, p1.y), 3.0 * (p1.x - p0.x));
+        const double a3 = fma(c.deta, p0.y + p1.y, 2.0 * (p0.x - p1.x));
         // Taylor coefficients about t
-        b0 = a0 + t * (a1 + t * (a2 + t * a3));
-        b1 = a1 + t * (2.0 * a2 + 3.0 * t * a3);
-        b2 = a2 + 3.0 * t * a3;
+        const double t3 = 3.0 * t;
+        b0 = fma(t, fma(t, fma(t, a3, a2), a1), a0);
+        b1 = fma(t, fma(t3, a3, 2.0 * a2), a1);
+        b2 = fma(t3, a3, a2);
         b3 = a3;
     }
 
     __device__ __forceinline__ double operator()(const CosmoDev& c, double eta) const
     {
+        #pragma clang fp contract(off)
         const double tau = (eta - eta_n) * c.inv_deta;
-        return b0 + tau * (b1 + tau * (b2 + tau * b3));
+        return fma(tau, fma(tau, fma(tau, b3, b2), b1), b0);
     }
 
     // d(a'/a)/d eta of the same cubic
@@ -171,7 +174,10 @@ __device__ __forceinline__ void trilinear_coefficients(const float4 v[8], float4
 __device__ __forceinline__ float trilinear_eval(float c0, float c1, float c2, float c3, float c4, float c5,
                                                 float c6, float c7, float tx, float ty, float tz)
 {
-    return c0 + tx * (c1 + ty * (c4 + tz * c7) + tz * c5) + ty * (c2 + tz * c6) + tz * c3;
+    #pragma clang fp contract(off)
+    const float a = fmaf(tz, c5, fmaf(ty, fmaf(tz, c7, c4), c1));
+    const float b = fmaf(tz, c6, c2);
+    return fmaf(tz, c3, fmaf(ty, b, fmaf(tx, a, c0)));
 }
 
 // Field value interpolated at one point, with the lane's cache of the leaf
@@ -191,6 +197,7 @@ struct FieldCache {
     int key[3];         // unwrapped coordinates at level keyL + 1
     int lvl;            // level of the resolved stencil
     int base;           // id of its lowest corner cell
+    float t[3];         // offsets of the last evaluated point in that stencil
     float* c;           // trilinear coefficients in LDS: coefficient k of
                         // component f (phi, gx, gy, gz) at c[(8 f + k) * kBlock]
     static constexpr int cstride = kBlock;
@@ -294,6 +301,7 @@ struct FieldCache {
     __device__ __forceinline__ int eval(const GridDev& g, const double u[3], float& phi, float G[3],
                                         int& leaf_level, int& stencil_level)
     {
+        #pragma clang fp contract(off)
         const int Lm = AMR ? g.max_level : 0;
         const double scale = (double)(2 << Lm);      // 2^(Lm+1)
         int I[3];
@@ -310,6 +318,7 @@ struct FieldCache {
         const float tx = (float)(u[0] * sl - 0.5 - (double)(((I[0] >> s) - 1) >> 1));
         const float ty = (float)(u[1] * sl - 0.5 - (double)(((I[1] >> s) - 1) >> 1));
         const float tz = (float)(u[2] * sl - 0.5 - (double)(((I[2] >> s) - 1) >> 1));
+        t[0] = tx; t[1] = ty; t[2] = tz;
         // f = c0 + tx (c1 + ty (c4 + tz c7) + tz c5) + ty (c2 + tz c6) + tz c3
         float f[4];
 #pragma unroll
@@ -353,25 +362,28 @@ struct RayGeom {
 __device__ __forceinline__ void grid_coords(const GridDev& g, const RayGeom& r, double eta, const float dx[3],
                                             double u[3])
 {
+    #pragma clang fp contract(off)
     const double s = g.eta0 - eta;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) u[i] = r.uo[i] + (s * r.n[i] + (double)dx[i]) * g.inv_h0;
+    for (int i = 0; i < 3; ++i) u[i] = fma(fma(s, r.n[i], (double)dx[i]), g.inv_h0, r.uo[i]);
 }
 
 // No-op stage recorder of the forward kernels.
 struct NoRecord {
-    __device__ __forceinline__ void stage(int, const GeoState&, int, int) {}
+    __device__ __forceinline__ void stage(int, const GeoState&, const FieldCache<true>&, const float*) {}
+    __device__ __forceinline__ void stage(int, const GeoState&, const FieldCache<false>&, const float*) {}
 };
 
 // One RK4 step of affine length dl from y into out.  The four stencil levels
-// are appended to *hash only when all four stages succeed (return 0).  The
-// recorder receives every stage's state and stencil (base id, level); the
-// reverse sweep uses it to replay the forward stages exactly.
-template <bool AMR, class Rec = NoRecord>
+// are appended to hash only when all four stages succeed (return 0).  When
+// record is set, the recorder receives every stage's state and stencil (base
+// id, level); the reverse sweep uses it to replay the forward stages exactly.
+template <bool AMR, class Rec>
 __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FieldCache<AMR>& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
-                                        uint32_t& hash, Rec* rec = nullptr)
+                                        uint32_t& hash, Rec& rec, bool record)
 {
+    #pragma clang fp contract(off)
     const float nf[3] = {(float)r.n[0], (float)r.n[1], (float)r.n[2]};
     double acc_eta = 0.0, acc_K = 0.0;
     float acc_dx[3] = {0.f, 0.f, 0.f}, acc_P[3] = {0.f, 0.f, 0.f};
@@ -381,35 +393,36 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
     uint32_t h = hash;
     HubbleCubic Hc;
     Hc.init(cz, y.eta);
-#pragma unroll 1
-    for (int st = 0; st < 4; ++st) {
+    // one stage; true when no complete stencil exists at its position
+    auto stage = [&](const int st) -> bool {
+        #pragma clang fp contract(off)
         GeoState yi;
         if (st == 0) {
             yi = y;
         } else {
             const double c = (st == 3 ? 1.0 : 0.5) * dl;
-            yi.eta = y.eta - c * Kprev;            // f_eta = -K of the previous stage
-            yi.K = y.K + c * f_K;
+            yi.eta = fma(-c, Kprev, y.eta);        // f_eta = -K of the previous stage
+            yi.K = fma(c, f_K, y.K);
             const float cf = (float)c;
             const float inv = 1.0f / (float)yi.K;
             const float ratio = yKf * inv;
             const float cK = cf * inv;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                yi.dx[i] = y.dx[i] + cf * f_dx[i];
-                yi.d[i] = ratio * y.d[i] + cK * f_P[i];
+                yi.dx[i] = fmaf(cf, f_dx[i], y.dx[i]);
+                yi.d[i] = fmaf(ratio, y.d[i], cK * f_P[i]);
             }
         }
         double u[3];
         grid_coords(g, r, yi.eta, yi.dx, u);
         float phi, G[3];
         int leafl, l;
-        if (F.eval(g, u, phi, G, leafl, l)) return 1;
+        if (F.eval(g, u, phi, G, leafl, l)) return true;
         h = fnv(h, (uint32_t)l);
-        if (rec) rec->stage(st, yi, F.base, F.lvl);
+        if (record) rec.stage(st, yi, F, G);
         const double H = Hc(cz, yi.eta);
         const float m[3] = {nf[0] + yi.d[0], nf[1] + yi.d[1], nf[2] + yi.d[2]};
-        const float mG = m[0] * G[0] + m[1] * G[1] + m[2] * G[2];
+        const float mG = fmaf(m[2], G[2], fmaf(m[1], G[1], m[0] * G[0]));
         Kprev = yi.K;
         f_K = yi.K * yi.K * (2.0 * H - 2.0 * (double)mG);
         const float Kf = (float)yi.K;
@@ -418,32 +431,45 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             f_dx[i] = Kf * yi.d[i];
-            f_P[i] = K2 * (4.0f * mG * m[i] - 2.0f * G[i] + hm * yi.d[i]);
+            f_P[i] = K2 * fmaf(hm, yi.d[i], fmaf(4.0f * mG, m[i], -2.0f * G[i]));
         }
         const double w = (st == 0 || st == 3) ? 1.0 : 2.0;
         const float wf = (float)w;
-        acc_eta -= w * yi.K;
-        acc_K += w * f_K;
+        acc_eta = fma(-w, yi.K, acc_eta);
+        acc_K = fma(w, f_K, acc_K);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            acc_dx[i] += wf * f_dx[i];
-            acc_P[i] += wf * f_P[i];
+            acc_dx[i] = fmaf(wf, f_dx[i], acc_dx[i]);
+            acc_P[i] = fmaf(wf, f_P[i], acc_P[i]);
         }
-    }
+        return false;
+    };
+#pragma unroll 1
+    for (int st = 0; st < 4; ++st)
+        if (stage(st)) return 1;
     const double h6 = dl / 6.0;
-    out.eta = y.eta + h6 * acc_eta;
-    out.K = y.K + h6 * acc_K;
+    out.eta = fma(h6, acc_eta, y.eta);
+    out.K = fma(h6, acc_K, y.K);
     const float h6f = (float)h6;
     const float inv = 1.0f / (float)out.K;
     const float ratio = yKf * inv;
     const float cK = h6f * inv;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        out.dx[i] = y.dx[i] + h6f * acc_dx[i];
-        out.d[i] = ratio * y.d[i] + cK * acc_P[i];
+        out.dx[i] = fmaf(h6f, acc_dx[i], y.dx[i]);
+        out.d[i] = fmaf(ratio, y.d[i], cK * acc_P[i]);
     }
     hash = h;
     return 0;
+}
+
+template <bool AMR>
+__device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FieldCache<AMR>& F,
+                                        const RayGeom& r, const GeoState& y, double dl, GeoState& out,
+                                        uint32_t& hash)
+{
+    NoRecord none;
+    return rk4_step<AMR, NoRecord>(g, cz, F, r, y, dl, out, hash, none, false);
 }
 
 __device__ __forceinline__ bool finite_state(const GeoState& y)

@@ -119,8 +119,13 @@ struct AdjointArgs {
     const double* dL_dz;         // [n_rays] or NULL
     float* jac;                  // [n_rays][2][2] or NULL
     float* dz_dtheta;            // [n_rays][2] or NULL
-    float* grad;                 // [n_cells][4] accumulated cotangent of (phi, grad) (library order) or NULL
+    int32_t* ray_status;         // [n_rays] or NULL: 0 ok, 1 not reached, 2 replay mismatch
+    float* grad;                 // cotangents of (phi, grad) per cell (see grad_slot) or NULL
+    int64_t n_cells;
 };
+
+// Floats of the cell-cotangent accumulator of the adjoint for n cells.
+inline int64_t grad_accumulator_floats(int64_t n) { return 4 * (((n + 7) >> 3) << 3); }
 
 // Kernel launchers (defined in cast.hip).
 hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s);
@@ -138,9 +143,9 @@ hipError_t launch_build_dual_ids(const GridDev& g, const int4* cellpos, int32_t*
 hipError_t launch_cast_checkpointed(const CastArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjointArgs& a, int columns, hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
-hipError_t launch_scatter_grad(const float4* grad_lib, const int64_t* perm, float4* out_user, int64_t n,
+hipError_t launch_scatter_grad(const float* grad_lib, const int64_t* perm, float4* out_user, int64_t n,
                                hipStream_t s);
-hipError_t launch_central_transpose(const float4* g_lib, const int4* cellpos, const int64_t* perm, float* out,
+hipError_t launch_central_transpose(const float* g_lib, const int4* cellpos, const int64_t* perm, float* out,
                                     int n0, double h0, int64_t n, hipStream_t s);
 int cast_occupancy_blocks_per_cu(int block, bool amr);
 

@@ -586,7 +586,7 @@ AdjointLayout adjoint_layout(const mpath_grid* g, const mpath_cast_desc* d, int6
     AdjointLayout L;
     L.off_tape = 0;
     L.off_grad = align_up((size_t)d->checkpoint_every * (size_t)n_rays * sizeof(GeoState), 256);
-    L.total = align_up(L.off_grad + (size_t)g->n_cells * 16, 256);
+    L.total = align_up(L.off_grad + (size_t)grad_accumulator_floats(g->n_cells) * 4, 256);
     return L;
 }
 
@@ -703,7 +703,7 @@ int mpath_adjoint(const mpath_grid* g, const mpath_cast_desc* d, const mpath_obs
     if (ws_bytes < al.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "adjoint workspace too small");
     if (ad->dL_dphi_total && !(g->max_level == 0 && g->periodic))
         return fail(MPATH_ERR_UNSUPPORTED, "dL_dphi_total needs a uniform periodic grid");
-    const bool jac = ad->jac || ad->dz_dtheta;
+    const bool jac = ad->jac || ad->dz_dtheta || ad->ray_status;
     const bool loss = ad->dL_dvalues || ad->dL_dphi_total;
     if (!jac && !loss) return MPATH_OK;
 
@@ -719,15 +719,17 @@ int mpath_adjoint(const mpath_grid* g, const mpath_cast_desc* d, const mpath_obs
     A.dL_dz = ad->dL_dz;
     A.jac = ad->jac;
     A.dz_dtheta = ad->dz_dtheta;
+    A.ray_status = ad->ray_status;
     float* grad = (float*)(ws + al.off_grad);
     A.grad = loss ? grad : nullptr;
+    A.n_cells = g->n_cells;
     hipError_t e = hipSuccess;
-    if (loss) e = launch_fill_zero(grad, g->n_cells * 4, s);
+    if (loss) e = launch_fill_zero(grad, grad_accumulator_floats(g->n_cells), s);
     if (!e) e = launch_adjoint(A, jac && loss ? 4 : (jac ? 3 : 1), s);
     if (!e && ad->dL_dvalues)
-        e = launch_scatter_grad((const float4*)grad, g->perm, (float4*)ad->dL_dvalues, g->n_cells, s);
+        e = launch_scatter_grad(grad, g->perm, (float4*)ad->dL_dvalues, g->n_cells, s);
     if (!e && ad->dL_dphi_total)
-        e = launch_central_transpose((const float4*)grad, g->cellpos, g->perm, ad->dL_dphi_total, g->n0,
+        e = launch_central_transpose(grad, g->cellpos, g->perm, ad->dL_dphi_total, g->n0,
                                      g->box / g->n0, g->n_cells, s);
     if (e) return hip_fail(e, "adjoint launch");
     return MPATH_OK;

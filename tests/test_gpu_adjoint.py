@@ -94,6 +94,7 @@ def test_jacobian_vs_oracle_complex_step(M, gauss64):
     res = M.adjoint(grid, cfg, out, jacobian=True)
     torch.cuda.synchronize()
     jac, dz = _np(res["jac"]).astype(np.float64), _np(res["dz_dtheta"]).astype(np.float64)
+    assert (_np(res["ray_status"]) == 0).all()     # every replay retraced its forward path
     field = O.Field.grid(gauss64)
     c = O.cosmo(*COSMO)
     p = _oracle_params(0.3)
@@ -151,6 +152,7 @@ def test_loss_gradient_directional(M, gauss64):
     torch.cuda.synchronize()
     g = _np(res["dL_dvalues"]).astype(np.float64)
     g1 = _np(res1["dL_dvalues"]).astype(np.float64)
+    assert (_np(res["ray_status"]) == 0).all() and (_np(res1["ray_status"]) == 0).all()
     # the loss-only sweep and the combined one give the same cell gradient
     assert np.allclose(g, g1, rtol=1e-5, atol=1e-6 * np.abs(g).max())
     field = O.Field.grid(gauss64)
