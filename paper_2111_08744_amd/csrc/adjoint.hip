@@ -297,7 +297,7 @@ __device__ __forceinline__ int64_t grad_slot(int64_t id, int q, int64_t n)
 // Per-wave table in LDS aggregating the gradient cotangents of recently
 // touched cells: open addressing on the cell id (linear probing), filled
 // with LDS atomics by the lanes of one wave and evicted to the cell array
-// with device atomics when it fills.  The 64 rays of a wave start from
+// with device atomics when half full.  The 64 rays of a wave start from
 // neighbouring sky pixels and cross the same cells many times, so the table
 // absorbs most additions and the device atomics (which resolve beyond the
 // per-XCD L2) drop by that reuse factor.
@@ -355,23 +355,54 @@ struct WaveTable {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 
-    // Add v to cell id.  The caller keeps at least one free slot per active
-    // lane, so the probe ends.
-    __device__ __forceinline__ void add(int id, const float v[3])
+    // Add the cotangents acc[o] of the 8 stencil cells ids[o] (-1: no cell).
+    // The 8 first probes are issued together; a slot taken by another cell
+    // continues with linear probing, and a full table (possible only when
+    // many lanes insert new cells at once) sends the value straight to the
+    // cell array.
+    __device__ __forceinline__ void add8(const AdjointArgs& A, const int ids[8], const float (&acc)[8][3])
     {
-        uint32_t h = ((uint32_t)id * 2654435761u) >> (32 - 9);
-        for (;;) {
-            const int old = atomicCAS(&keys[h], -1, id);
-            if (old == -1) {
-                atomicAdd(count, 1);
-                break;
-            }
-            if (old == id) break;
-            h = (h + 1) & (kTab - 1);
+        int h[8], old[8];
+        bool use[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            use[o] = ids[o] >= 0 && (acc[o][0] != 0.0f || acc[o][1] != 0.0f || acc[o][2] != 0.0f);
+            h[o] = (int)(((uint32_t)ids[o] * 2654435761u) >> (32 - 9));
+            old[o] = use[o] ? atomicCAS(&keys[h[o]], -1, ids[o]) : 0;
         }
-        atomicAdd(&vals[h], v[0]);
-        atomicAdd(&vals[kTab + h], v[1]);
-        atomicAdd(&vals[2 * kTab + h], v[2]);
+        int claimed = 0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            if (!use[o]) continue;
+            if (old[o] == -1) {
+                ++claimed;
+            } else if (old[o] != ids[o]) {
+                int slot = -1;
+                for (int k = 1; k < kTab; ++k) {
+                    const int hh = (h[o] + k) & (kTab - 1);
+                    const int o2 = atomicCAS(&keys[hh], -1, ids[o]);
+                    if (o2 == -1) ++claimed;
+                    if (o2 == -1 || o2 == ids[o]) {
+                        slot = hh;
+                        break;
+                    }
+                }
+                h[o] = slot;
+                if (slot < 0) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        unsafeAtomicAdd(A.grad + grad_slot(ids[o], 1 + q, A.n_cells), acc[o][q]);
+                }
+            }
+        }
+        if (claimed) atomicAdd(count, claimed);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            if (!use[o] || h[o] < 0) continue;
+            atomicAdd(&vals[h[o]], acc[o][0]);
+            atomicAdd(&vals[kTab + h[o]], acc[o][1]);
+            atomicAdd(&vals[2 * kTab + h[o]], acc[o][2]);
+        }
     }
 };
 static_assert(kTab == 512, "the probe hash takes the top 9 bits");
@@ -399,14 +430,11 @@ struct Scatter {
     __device__ __forceinline__ void flush(const AdjointArgs& A, WaveTable& T)
     {
         if (cur < 0) return;
+        T.add8(A, ids, acc);
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            // at most one insertion per active lane follows: keep 64 slots free
-            if (*T.count > kTab - 64) T.evict(A);
-            if (ids[o] >= 0 && (acc[o][0] != 0.0f || acc[o][1] != 0.0f || acc[o][2] != 0.0f)) T.add(ids[o], acc[o]);
+        for (int o = 0; o < 8; ++o)
 #pragma unroll
             for (int q = 0; q < 3; ++q) acc[o][q] = 0.0f;
-        }
         cur = -1;
     }
 
@@ -801,6 +829,8 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
         GeoState y = a.ckpt[(int64_t)seg * a.n_rays + ray];
         for (int it = 0; it < nf + len; ++it) {
             const bool fwd = it < nf;
+            // the lanes still iterating empty the table when it is half full
+            if (SCATTER && *T.count > kTab / 2) T.evict(A);
             if (it == nf) {
                 if (!last) {
                     A.tape[(int64_t)(len - 1) * a.n_rays + ray] = y;
