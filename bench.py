@@ -93,6 +93,88 @@ def cpu_baseline(w, cells, sample_stride, threads):
             "rays_per_s": len(pix) / dt}
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time_ms(torch, fn, reps=2):
+    """Minimum over reps of fn's GPU time (HIP events on the current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = _events(torch)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def measure_adjoint(M, torch, dev):
+    """Differentiated workload: 2^20 rays (NESTED nside 512, pixels [0, 2^20))
+    to z = 1 on the uniform 64^3 grid, 10 steps per cell, checkpoints every 32
+    steps; the reverse sweep gives the 2x2 distortion matrix and dz/dtheta of
+    every ray and dL/d(cell values) for L = sum |alpha|^2."""
+    import synth
+    w = synth.WORKLOADS["differentiated"]
+    grid = M.Grid(synth.make_cells(w.grid), (0.3, 0.7, 0.7), device=dev)
+    kw = dict(steps_per_cell=w.steps_per_cell, adaptive=w.adaptive)
+    cfg0 = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, schedule=1, **kw)
+    cfgK = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, checkpoint_every=32, **kw)
+    out0 = M.alloc_outputs(w.n_rays, dev)
+    t_fwd = _time_ms(torch, lambda: M.cast(grid, cfg0, out0, out0.get("_ws")))
+    outK = M.alloc_outputs(w.n_rays, dev)
+    t_ckpt = _time_ms(torch, lambda: M.cast(grid, cfgK, outK, outK.get("_ws")))
+    alpha2 = 2.0 * outK["alpha"]
+    res = {}
+    t_adj = _time_ms(torch, lambda: res.update(M.adjoint(grid, cfgK, outK, dL_dalpha=alpha2, jacobian=True,
+                                                          cells=True, ws=res.get("_ws"))), reps=1)
+    steps = int(outK["n_steps"].to(torch.int64).sum())
+    bad = int((res["ray_status"] != 0).sum())
+    log(f"[bench] adjoint: forward {t_fwd:.1f} ms, checkpointed forward {t_ckpt:.1f} ms, "
+        f"reverse sweep {t_adj:.1f} ms ({t_adj / t_fwd:.2f}x), {steps} ray-steps, {bad} rays not differentiated")
+    return {"workload": "2^20 rays (nside 512) to z = 1 on the uniform 64^3 grid, 10 steps per cell, "
+                        "checkpoint every 32 steps; A, dz/dtheta per ray and dL/dcells, L = sum |alpha|^2",
+            "ray_steps": steps, "forward_ms": t_fwd, "checkpointed_forward_ms": t_ckpt,
+            "reverse_ms": t_adj, "adjoint_forward_ratio": t_adj / t_fwd,
+            "forward_plus_adjoint_ratio": (t_ckpt + t_adj) / t_fwd, "rays_not_differentiated": bad}
+
+
+def measure_batched(M, torch, dev):
+    """64 observers at seeded positions, z_src U[0.1, 2], one NESTED base
+    pixel at nside 128 each (1,048,576 rays of uneven length) on the uniform
+    64^3 grid: one autotuned launch against 64 one-cone launches."""
+    import synth
+    w = synth.WORKLOADS["batched"]
+    grid = M.Grid(synth.make_cells(w.grid), (0.3, 0.7, 0.7), device=dev)
+    kw = dict(steps_per_cell=w.steps_per_cell, adaptive=w.adaptive)
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, schedule=1, **kw)
+    tuned, tune_ms = M.autotune(grid, cfg, sample_div=8)
+    out = M.alloc_outputs(w.n_rays, dev)
+    t_one = _time_ms(torch, lambda: M.cast(grid, tuned, out, out.get("_ws")))
+    steps = int(out["n_steps"].to(torch.int64).sum())
+    t_static = _time_ms(torch, lambda: M.cast(grid, cfg, out, out.get("_ws")))
+    cones = [M.CastConfig(w.obs[j], w.z_src[j], w.nside, [w.pix_first[j]], [w.pix_count[j]], schedule=1, **kw)
+             for j in range(len(w.obs))]
+    outs = [M.alloc_outputs(int(w.pix_count[j]), dev) for j in range(len(w.obs))]
+
+    def per_cone():
+        for c, o in zip(cones, outs):
+            M.cast(grid, c, o, o.get("_ws"))
+    t_cones = _time_ms(torch, per_cone, reps=1)
+    log(f"[bench] batched: tuned launch (schedule {tuned.schedule}, waves/CU {tuned.waves_per_cu}, "
+        f"batch {tuned.batch}) {t_one:.1f} ms, static launch {t_static:.1f} ms, "
+        f"64 one-cone launches {t_cones:.1f} ms ({t_cones / t_one:.2f}x)")
+    return {"workload": "64 cones x 16384 rays (nside 128 base pixels), z_src U[0.1, 2], uniform 64^3 grid",
+            "ray_steps": steps, "tuned": {"schedule": tuned.schedule, "waves_per_cu": tuned.waves_per_cu,
+                                          "batch": tuned.batch, "sample_ms": tune_ms},
+            "one_launch_ms": t_one, "static_launch_ms": t_static, "one_cone_per_launch_ms": t_cones,
+            "one_launch_ray_steps_per_s": steps / (t_one / 1e3),
+            "speedup_vs_one_cone_per_launch": t_cones / t_one}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +186,8 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the adjoint and batched-launch measurements")
     ap.add_argument("--cpu-stride", type=int, default=48)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the casts, copy MIB mebibytes once with a plain device copy "
@@ -207,6 +291,10 @@ def main():
                      "traffic": traffic, "kernel": "cast_kernel",
                      "launch_ms_mean": float(np.mean(launch_ms))},
     }
+    if not args.no_secondary:
+        sec = {"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev)}
+        res["secondary"] = sec
+        res["adjoint_forward_ratio"] = sec["adjoint"]["adjoint_forward_ratio"]
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         env = os.environ.get("OMP_NUM_THREADS")

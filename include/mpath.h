@@ -159,7 +159,7 @@ typedef struct {
     int32_t steps_per_cell;     /* N >= 1: comoving step length h / N                   */
     int32_t adaptive;           /* 1: h of the leaf cell at the step start; 0: coarse h */
     int64_t max_steps;          /* per ray, including the landing step                   */
-    /* launch shape; 0 = library default (see mpath_autotune) */
+    /* launch shape; 0 = library default (mpath_autotune picks them by timing) */
     int32_t schedule;
     int32_t block_size;         /* threads per block: 0 or 256                          */
     int32_t waves_per_cu;       /* persistent schedule: resident waves per CU            */
@@ -264,6 +264,21 @@ int mpath_adjoint_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc*
 int mpath_adjoint(const mpath_grid* grid, const mpath_cast_desc* desc, const mpath_observables* fwd,
                   const void* cast_ws, size_t cast_ws_bytes, const mpath_adjoint_desc* adj, void* dev_ws,
                   size_t ws_bytes, void* stream);
+
+/* ---- launch autotuner ----
+ * Times candidate launch shapes on a sample of the rays of desc (the first
+ * ceil(count / sample_div) pixels of every observer, keeping the observers'
+ * mix of source distances) and returns in *tuned a copy of desc with the
+ * fastest schedule, waves_per_cu and batch.  Candidates: the static schedule
+ * and the persistent one at the resident occupancy, half and twice that,
+ * with queue refills every 8, 16, 32, 64 or 128 steps.  The launch shape
+ * does not change any result.  Synchronises the stream; dev_ws (size from
+ * mpath_autotune_workspace_bytes) is scratch for the sample casts; best_ms
+ * (may be NULL) receives the sample's time with the chosen shape. */
+int mpath_autotune_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* desc, int32_t sample_div,
+                                   size_t* bytes);
+int mpath_autotune(const mpath_grid* grid, const mpath_cast_desc* desc, int32_t sample_div, void* dev_ws,
+                   size_t ws_bytes, void* stream, mpath_cast_desc* tuned, float* best_ms);
 
 /* Number of rays a desc describes. */
 int mpath_cast_count_rays(const mpath_cast_desc* desc, int64_t* n_rays);

@@ -24,7 +24,8 @@ from ._abi import (MPATH_RAY_LEFT_DOMAIN, MPATH_RAY_MAX_STEPS, MPATH_RAY_NONFINI
                    MPATH_RAY_REACHED, MPATH_SCHED_AUTO, MPATH_SCHED_PERSISTENT,
                    MPATH_SCHED_STATIC, MPATH_STOP_CHI, MPATH_STOP_REDSHIFT, MpathError)
 
-__all__ = ["Grid", "cast", "CastConfig", "adjoint", "cast_differentiable", "library_path", "MpathError"]
+__all__ = ["Grid", "cast", "CastConfig", "adjoint", "autotune", "cast_differentiable", "library_path",
+           "MpathError"]
 
 
 def library_path() -> str:
@@ -313,3 +314,27 @@ def cast_differentiable(values, grid: Grid, cfg: CastConfig):
     if _CAST_FN is None:
         _CAST_FN = _autograd_function()
     return _CAST_FN.apply(values, grid, cfg)
+
+
+def autotune(grid: Grid, cfg: CastConfig, sample_div: int = 8):
+    """mpath_autotune: time candidate launch shapes on a sample of cfg's rays
+    (1/sample_div of every observer's pixels) and return (a copy of cfg with
+    the fastest schedule, waves_per_cu and batch, the sample's time in ms)."""
+    import copy
+    torch = _torch()
+    L = _abi.lib()
+    d = cfg.desc()
+    nbytes = C.c_size_t()
+    _abi.check(L.mpath_autotune_workspace_bytes(grid.handle, C.byref(d), int(sample_div), C.byref(nbytes)),
+               "mpath_autotune_workspace_bytes")
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=grid.device)
+    tuned = _abi.mpath_cast_desc()
+    ms = C.c_float()
+    with torch.cuda.device(grid.device):
+        _abi.check(L.mpath_autotune(grid.handle, C.byref(d), int(sample_div), _ptr(ws), ws.numel(),
+                                    _stream_ptr(grid.device), C.byref(tuned), C.byref(ms)), "mpath_autotune")
+    out = copy.copy(cfg)
+    out.schedule = tuned.schedule
+    out.waves_per_cu = tuned.waves_per_cu
+    out.batch = tuned.batch
+    return out, ms.value

@@ -736,3 +736,108 @@ int mpath_adjoint(const mpath_grid* g, const mpath_cast_desc* d, const mpath_obs
 }
 
 }  // extern "C"
+
+// ---- autotuner ----
+
+namespace {
+
+// The sample the tuner casts: the first ceil(count / sample_div) pixels of
+// every observer, so that the mix of observers and path lengths is kept.
+struct TuneSample {
+    std::vector<int64_t> first, count;
+    mpath_cast_desc desc;
+};
+
+TuneSample tune_sample(const mpath_cast_desc* d, int32_t sample_div)
+{
+    TuneSample t;
+    const int64_t npix = 12ll * d->nside * d->nside;
+    t.first.resize(d->n_obs);
+    t.count.resize(d->n_obs);
+    for (int j = 0; j < d->n_obs; ++j) {
+        const int64_t c = d->pix_count ? d->pix_count[j] : npix;
+        t.first[j] = d->pix_first ? d->pix_first[j] : 0;
+        t.count[j] = c > 0 ? std::max<int64_t>(1, (c + sample_div - 1) / sample_div) : 0;
+    }
+    t.desc = *d;
+    t.desc.pix_first = t.first.data();
+    t.desc.pix_count = t.count.data();
+    t.desc.checkpoint_every = 0;
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpath_autotune_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, int32_t sample_div,
+                                   size_t* bytes)
+{
+    if (!bytes || sample_div < 1) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL or sample_div < 1");
+    int64_t n_rays;
+    const int rc = check_cast_desc(g, d, &n_rays);
+    if (rc) return rc;
+    const TuneSample t = tune_sample(d, sample_div);
+    return mpath_cast_workspace_bytes(g, &t.desc, bytes);
+}
+
+int mpath_autotune(const mpath_grid* g, const mpath_cast_desc* d, int32_t sample_div, void* dev_ws,
+                   size_t ws_bytes, void* stream, mpath_cast_desc* tuned, float* best_ms)
+{
+    if (!tuned) return fail(MPATH_ERR_INVALID_ARG, "tuned is NULL");
+    size_t need = 0;
+    int rc = mpath_autotune_workspace_bytes(g, d, sample_div, &need);
+    if (rc) return rc;
+    if (!dev_ws || ws_bytes < need) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "autotune workspace too small");
+    const TuneSample t = tune_sample(d, sample_div);
+    hipStream_t s = (hipStream_t)stream;
+    // candidates: the static schedule, and the persistent one at the
+    // resident occupancy, half and twice that, with refills every 8..128 steps
+    const int occ = std::max(1, cast_occupancy_blocks_per_cu(256, g->max_level > 0) * 4);
+    struct Cand { int32_t schedule, wpc, batch; };
+    std::vector<Cand> cands = {{MPATH_SCHED_STATIC, 0, 0}};
+    for (int w : {occ, std::max(1, occ / 2), 2 * occ})
+        for (int b : {8, 16, 32, 64, 128}) cands.push_back({MPATH_SCHED_PERSISTENT, w, b});
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(MPATH_ERR_DEVICE, "autotune: event creation failed");
+    mpath_observables none;
+    std::memset(&none, 0, sizeof none);
+    float best = 1e30f;
+    Cand bestc = cands[0];
+    for (size_t i = 0; i < cands.size() && rc == MPATH_OK; ++i) {
+        mpath_cast_desc c = t.desc;
+        c.schedule = cands[i].schedule;
+        c.waves_per_cu = cands[i].wpc;
+        c.batch = cands[i].batch;
+        float ms = 1e30f;
+        // the first candidate runs once more untimed (warm caches and code)
+        for (int rep = (i == 0 ? -1 : 0); rep < 2 && rc == MPATH_OK; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(MPATH_ERR_DEVICE, "autotune: event record"); break; }
+            rc = mpath_cast(g, &c, &none, dev_ws, ws_bytes, stream);
+            if (rc) break;
+            float m = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&m, e0, e1) != hipSuccess) {
+                rc = fail(MPATH_ERR_DEVICE, "autotune: event timing");
+                break;
+            }
+            if (rep >= 0) ms = std::min(ms, m);
+        }
+        if (rc == MPATH_OK && ms < best) {
+            best = ms;
+            bestc = cands[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *tuned = *d;
+    tuned->schedule = bestc.schedule;
+    tuned->waves_per_cu = bestc.wpc;
+    tuned->batch = bestc.batch;
+    if (best_ms) *best_ms = best;
+    return MPATH_OK;
+}
+
+}  // extern "C"
