@@ -117,7 +117,10 @@ class Grid:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _abi.lib().mpath_grid_free(h)
+            try:
+                _abi.lib().mpath_grid_free(h)
+            except Exception:   # interpreter shutdown: module globals already gone
+                pass
             self._h = None
 
 

@@ -184,3 +184,41 @@ def test_invalid_arguments_raise(M, gauss64):
     from paper_2111_08744_amd import _abi
     n = C.c_size_t()
     assert _abi.lib().mpath_cast_workspace_bytes(grid.handle, C.byref(d), C.byref(n)) == _abi.MPATH_ERR_UNSUPPORTED
+
+
+def test_amr128_full_size_sampled(M):
+    """The benchmark configuration itself: AMR 128^3 + 3 levels (10,035,832
+    cells), all 786,432 rays (nside 256) to z = 1 in the launch the benchmark
+    times; 384 seeded random rays recomputed by the oracle one by one."""
+    w = synth.WORKLOADS["amr"]
+    cells = synth.make_cells(w.grid)
+    _print("amr128 cells", cells.n_cells)
+    grid = M.Grid(cells, COSMO)
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, steps_per_cell=w.steps_per_cell,
+                       adaptive=w.adaptive)
+    g = run_gpu(grid, cfg)
+    assert np.all(g["status"] == M.MPATH_RAY_REACHED)
+    idx = np.sort(np.random.default_rng(2024).choice(w.n_rays, 384, replace=False))
+    o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), w.obs, w.z_src, w.nside, w.pix_first, w.pix_count,
+                   w.steps_per_cell, w.adaptive, ray_index=idx)
+    s = compare(g, o, idx=idx, max_flip_frac=0.02, flip_tol_arcsec=1.0)
+    _print(s)
+
+
+def test_empty_and_ragged_ray_lists(M, gauss64):
+    """Observers with no pixels, and one pixel, next to a full cone."""
+    import torch
+    grid = M.Grid(gauss64, COSMO)
+    cfg0 = M.CastConfig([[250.0, 250.0, 250.0]], [0.3], 4, [0], [0], steps_per_cell=10)
+    assert cfg0.n_rays() == 0
+    out = M.cast(grid, cfg0)
+    torch.cuda.synchronize()
+    assert out["z5"].numel() == 0
+    obs = [[250.0, 250.0, 250.0], [100.0, 120.0, 140.0], [400.0, 30.0, 260.0]]
+    z = [0.2, 0.1, 0.3]
+    first, count = [5, 0, 37], [0, 1, 16]
+    for sched in (1, 2):
+        cfg = M.CastConfig(obs, z, 4, first, count, steps_per_cell=10, schedule=sched)
+        g = run_gpu(grid, cfg)
+        o = run_oracle(O.Field.grid(gauss64), O.cosmo(*COSMO), obs, z, 4, first, count, 10, False)
+        _print(compare(g, o))
