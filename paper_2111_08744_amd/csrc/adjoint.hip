@@ -488,8 +488,7 @@ __device__ __forceinline__ bool plan_step(const CastArgs& a, FieldCache<AMR>& F,
     for (int d = 0; d < 3; ++d) I[d] = (int)floor(u[d] * scale);
     const int L = F.leaf(g, I);
     if (L < 0) return false;
-    const int lstep = a.adaptive ? L : 0;
-    ds = g.h0 / (double)(1 << lstep) / (double)a.steps_per_cell;
+    ds = a.ds_level[L];
     dl = ds / y.K;
     landing = fma(-y.K, dl, y.eta) < eta_s;
     return true;
@@ -670,13 +669,12 @@ __device__ __forceinline__ void point_jet(const AdjointArgs& A, const RayCtx& R,
 // eta(y_f) = eta_s, so the cotangent along the flow F(y_f) is removed.
 template <bool AMR, int W, bool SCATTER>
 __device__ __forceinline__ void end_cotangents(const AdjointArgs& A, const RayCtx& R, FieldCache<AMR>& F,
-                                               const ObsDev& ob, const GeoState& yf, double phio,
+                                               const ObsDev& ob, int64_t ray, const GeoState& yf, double phio,
                                                const double e1[3], const double e2[3], Phys (&yb)[W],
                                                double& phio_bar)
 {
     constexpr bool HAS_JAC = W >= 3;
     const GridDev& g = A.c.grid;
-    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float ph_f, Gt[3];
     int ll, lv;
     double uf[3];
@@ -770,7 +768,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
         T.bind(lds + (32 + 4 * StageRecord::kWords) * kBlock + (threadIdx.x >> 6) * kTabWords);
         T.clear(threadIdx.x & 63);
     }
-    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ray = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const CastArgs& a = A.c;
     if (ray >= a.n_rays) return;
     constexpr bool HAS_JAC = W >= 3;
@@ -841,7 +839,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
                         ok = false;
                         break;
                     }
-                    end_cotangents<AMR, W, SCATTER>(A, R, F, ob, y, phio, e1, e2, yb, phio_bar);
+                    end_cotangents<AMR, W, SCATTER>(A, R, F, ob, ray, y, phio, e1, e2, yb, phio_bar);
                 }
             }
             const int jl = fwd ? it : len - 1 - (it - nf);

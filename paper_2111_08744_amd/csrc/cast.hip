@@ -95,8 +95,7 @@ struct RayRun {
             const int L = F.leaf(g, I);
             if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
             hash = fnv(hash, (uint32_t)L);
-            const int lstep = a.adaptive ? L : 0;
-            const double ds = g.h0 / (double)(1 << lstep) / (double)a.steps_per_cell;
+            const double ds = a.ds_level[L];
             const double dl = ds / y.K;
             // landing on the iso-eta surface: Newton on eta_RK4(dl) = eta_s
             // with derivative -K at the trial end, two iterations, then the step
@@ -219,7 +218,7 @@ template <bool AMR>
 __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_static_kernel(CastArgs a)
 {
     extern __shared__ float coef_lds[];
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (r >= a.n_rays) return;
     RayRun<AMR> R;
     R.F.bind(coef_lds + threadIdx.x);
@@ -233,7 +232,7 @@ template <bool AMR>
 __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_ckpt_kernel(CastArgs a)
 {
     extern __shared__ float coef_lds[];
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (r >= a.n_rays) return;
     RayRun<AMR> R;
     R.F.bind(coef_lds + threadIdx.x);

@@ -14,6 +14,20 @@ constexpr uint32_t kFnvPrime = 16777619u;
 
 __device__ __forceinline__ uint32_t fnv(uint32_t h, uint32_t v) { return (h ^ v) * kFnvPrime; }
 
+// The GPU hands consecutive workgroups to its 8 XCDs in turn, and each XCD
+// has its own L2.  Renumber workgroups so that each XCD runs a contiguous
+// range of them (consecutive rays are neighbouring sky pixels whose paths
+// share cells): XCD x = b mod 8 takes logical blocks
+// [start(x), start(x) + count(x)) in the order it receives them.
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks)
+{
+    const int64_t q = nblocks / kNumXcd, r = nblocks % kNumXcd;
+    const int64_t x = b % kNumXcd, idx = b / kNumXcd;
+    return x < r ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
+}
+
 // ---------------------------------------------------------------------------
 // HEALPix NESTED pixel centre (Gorski et al. 2005; Sect. 2.4 starts one photon
 // at every pixel centre).  Within base face f the nested index interleaves
@@ -307,10 +321,23 @@ struct FieldCache {
         int I[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) I[d] = (int)floor(u[d] * scale);
-        const int L = leaf(g, I);
+        int L;
+        if (AMR && keyL >= 0 && (I[0] >> (Lm - keyL)) == key[0] && (I[1] >> (Lm - keyL)) == key[1] &&
+            (I[2] >> (Lm - keyL)) == key[2]) {
+            // same half-cell of the same leaf as the cached stencil
+            L = keyL;
+        } else {
+            L = leaf(g, I);
+            if (L < 0) {
+                leaf_level = L;
+                return 1;
+            }
+            if (!stencil(g, L, I)) {
+                leaf_level = L;
+                return 1;
+            }
+        }
         leaf_level = L;
-        if (L < 0) return 1;
-        if (!stencil(g, L, I)) return 1;
         stencil_level = lvl;
         // offsets from the stencil base (lowest corner) at level lvl
         const int s = Lm - lvl;
@@ -389,7 +416,6 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
     float acc_dx[3] = {0.f, 0.f, 0.f}, acc_P[3] = {0.f, 0.f, 0.f};
     double f_K = 0.0, Kprev = y.K;
     float f_dx[3] = {0.f, 0.f, 0.f}, f_P[3] = {0.f, 0.f, 0.f};
-    const float yKf = (float)y.K;
     uint32_t h = hash;
     HubbleCubic Hc;
     Hc.init(cz, y.eta);
@@ -403,14 +429,16 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
             const double c = (st == 3 ? 1.0 : 0.5) * dl;
             yi.eta = fma(-c, Kprev, y.eta);        // f_eta = -K of the previous stage
             yi.K = fma(c, f_K, y.K);
+            // d_stage = (K d + c P) / K_stage = d + (K / K_stage - 1) d + (c / K_stage) P:
+            // d is carried exactly and only the small corrections are rounded
             const float cf = (float)c;
-            const float inv = 1.0f / (float)yi.K;
-            const float ratio = yKf * inv;
+            const float inv = __builtin_amdgcn_rcpf((float)yi.K);   // 1 ulp
+            const float rm1 = (float)(y.K - yi.K) * inv;
             const float cK = cf * inv;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 yi.dx[i] = fmaf(cf, f_dx[i], y.dx[i]);
-                yi.d[i] = fmaf(ratio, y.d[i], cK * f_P[i]);
+                yi.d[i] = fmaf(cK, f_P[i], fmaf(rm1, y.d[i], y.d[i]));
             }
         }
         double u[3];
@@ -451,13 +479,13 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
     out.eta = fma(h6, acc_eta, y.eta);
     out.K = fma(h6, acc_K, y.K);
     const float h6f = (float)h6;
-    const float inv = 1.0f / (float)out.K;
-    const float ratio = yKf * inv;
+    const float inv = __builtin_amdgcn_rcpf((float)out.K);
+    const float rm1 = (float)(y.K - out.K) * inv;
     const float cK = h6f * inv;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         out.dx[i] = fmaf(h6f, acc_dx[i], y.dx[i]);
-        out.d[i] = fmaf(ratio, y.d[i], cK * acc_P[i]);
+        out.d[i] = fmaf(cK, acc_P[i], fmaf(rm1, y.d[i], y.d[i]));
     }
     hash = h;
     return 0;
@@ -472,12 +500,12 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
     return rk4_step<AMR, NoRecord>(g, cz, F, r, y, dl, out, hash, none, false);
 }
 
+// NaN or infinity anywhere in the state (a sum of the small FP32 parts is
+// non-finite exactly when one of them is; they cannot overflow together).
 __device__ __forceinline__ bool finite_state(const GeoState& y)
 {
-    bool ok = isfinite(y.eta) && isfinite(y.K);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) ok = ok && isfinite(y.d[i]) && isfinite(y.dx[i]);
-    return ok;
+    const float s = ((y.d[0] + y.d[1]) + (y.d[2] + y.dx[0])) + (y.dx[1] + y.dx[2]);
+    return isfinite(y.eta) && isfinite(y.K) && isfinite(s);
 }
 
 }  // namespace mpath

@@ -547,6 +547,8 @@ CastArgs make_cast_args(const mpath_grid* g, const mpath_cast_desc* d, const Cas
     a.nside = d->nside;
     a.steps_per_cell = d->steps_per_cell;
     a.adaptive = d->adaptive ? 1 : 0;
+    for (int l = 0; l <= kMaxLevels; ++l)
+        a.ds_level[l] = (g->box / g->n0) / (double)(1 << (a.adaptive ? l : 0)) / (double)d->steps_per_cell;
     a.max_steps = d->max_steps;
     a.n_rays = n_rays;
     a.queue = (unsigned long long*)(ws + lay.off_queue);
