@@ -124,6 +124,28 @@ struct StageRecord {
         put(q, 17, __int_as_float(F.lvl));
     }
 
+    // After a stage's transposed Jacobian its gradient words are free: they
+    // take the loss cotangent of the interpolated gradient at that stage.
+    template <int I>
+    __device__ __forceinline__ void put_gbar(const float g[3]) const
+    {
+        float* q = p + I * kWords * kBlock;
+        put(q, 10, g[0]);
+        put(q, 11, g[1]);
+        put(q, 12, g[2]);
+    }
+    // stage i (run-time index): stencil base, offsets and the loss cotangent
+    __device__ __forceinline__ void scatter_data(int i, int& base, float t[3], float g[3]) const
+    {
+        const float* q = p + i * kWords * kBlock;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            g[k] = q[(10 + k) * kBlock];
+            t[k] = q[(13 + k) * kBlock];
+        }
+        base = __float_as_int(q[16 * kBlock]);
+    }
+
     template <int I>
     __device__ __forceinline__ StageData get() const
     {
@@ -295,9 +317,9 @@ __device__ __forceinline__ int64_t grad_slot(int64_t id, int q, int64_t n)
 }
 
 // Per-wave table in LDS aggregating the gradient cotangents of recently
-// touched cells: open addressing on the cell id (linear probing), filled
-// with LDS atomics by the lanes of one wave and evicted to the cell array
-// with device atomics when half full.  The 64 rays of a wave start from
+// touched cells: direct-mapped on a hash of the cell id, filled with LDS
+// atomics by the lanes of one wave and evicted to the cell array with device
+// atomics when half full.  The 64 rays of a wave start from
 // neighbouring sky pixels and cross the same cells many times, so the table
 // absorbs most additions and the device atomics (which resolve beyond the
 // per-XCD L2) drop by that reuse factor.
@@ -356,61 +378,53 @@ struct WaveTable {
     }
 
     // Add the cotangents acc[o] of the 8 stencil cells ids[o] (-1: no cell).
-    // The 8 first probes are issued together; a slot taken by another cell
-    // continues with linear probing, and a full table (possible only when
-    // many lanes insert new cells at once) sends the value straight to the
-    // cell array.
+    // The table is direct-mapped on a hash of the cell id: a cell whose slot
+    // is free or already its own is added in LDS; one whose slot holds
+    // another cell goes straight to the cell array.  The 8 slot claims are
+    // issued together and the LDS additions carry a zero where the slot is
+    // not the cell's, so that the common path has no branches.
     __device__ __forceinline__ void add8(const AdjointArgs& A, const int ids[8], const float (&acc)[8][3])
     {
         int h[8], old[8];
-        bool use[8];
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
-            use[o] = ids[o] >= 0 && (acc[o][0] != 0.0f || acc[o][1] != 0.0f || acc[o][2] != 0.0f);
             h[o] = (int)(((uint32_t)ids[o] * 2654435761u) >> (32 - 9));
-            old[o] = use[o] ? atomicCAS(&keys[h[o]], -1, ids[o]) : 0;
+            old[o] = ids[o] >= 0 ? atomicCAS(&keys[h[o]], -1, ids[o]) : ids[o];
         }
         int claimed = 0;
+        uint32_t conflict = 0;
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
-            if (!use[o]) continue;
-            if (old[o] == -1) {
-                ++claimed;
-            } else if (old[o] != ids[o]) {
-                int slot = -1;
-                for (int k = 1; k < kTab; ++k) {
-                    const int hh = (h[o] + k) & (kTab - 1);
-                    const int o2 = atomicCAS(&keys[hh], -1, ids[o]);
-                    if (o2 == -1) ++claimed;
-                    if (o2 == -1 || o2 == ids[o]) {
-                        slot = hh;
-                        break;
-                    }
-                }
-                h[o] = slot;
-                if (slot < 0) {
+            const bool cell = ids[o] >= 0;
+            const bool mine = cell && (old[o] == -1 || old[o] == ids[o]);
+            claimed += (cell && old[o] == -1) ? 1 : 0;
+            conflict |= (cell && !mine) ? (1u << o) : 0u;
+            const float m = mine ? 1.0f : 0.0f;
+            atomicAdd(&vals[h[o]], m * acc[o][0]);
+            atomicAdd(&vals[kTab + h[o]], m * acc[o][1]);
+            atomicAdd(&vals[2 * kTab + h[o]], m * acc[o][2]);
+        }
+        if (claimed) atomicAdd(count, claimed);
+        if (conflict) {
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                if (conflict & (1u << o)) {
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
                         unsafeAtomicAdd(A.grad + grad_slot(ids[o], 1 + q, A.n_cells), acc[o][q]);
                 }
             }
         }
-        if (claimed) atomicAdd(count, claimed);
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            if (!use[o] || h[o] < 0) continue;
-            atomicAdd(&vals[h[o]], acc[o][0]);
-            atomicAdd(&vals[kTab + h[o]], acc[o][1]);
-            atomicAdd(&vals[2 * kTab + h[o]], acc[o][2]);
-        }
     }
 };
-static_assert(kTab == 512, "the probe hash takes the top 9 bits");
+static_assert(kTab == 512, "the slot hash takes the top 9 bits");
 
 // Per-lane accumulator (registers) of the gradient cotangents of the 8 cells
 // of the current stencil, moved into the wave's table when the stencil
 // changes.  The cell ids of the current stencil are loaded when it becomes
 // current, so the load is in flight long before the flush needs it.
+
+template <bool AMR>
 struct Scatter {
     float acc[8][3];
     int ids[8];
@@ -531,7 +545,7 @@ template <int I, bool AMR, int W, bool SCATTER>
 __device__ __forceinline__ void reverse_stage(const AdjointArgs& A, const RayCtx& R, const FieldCache<AMR>& F,
                                               const StageRecord& rec, const HubbleCubic& Hc, float dlf, Jet32& J,
                                               const Phys32 (&v)[W], Phys32 (&Fb)[W], float (&dlbar)[W],
-                                              Phys (&yb)[W], Scatter& S, WaveTable& T)
+                                              Phys32 (&dy)[W], const float (&lc)[W], Scatter<AMR>& S, WaveTable& T)
 {
     Jet32 P;
     Phys32 FP;
@@ -541,13 +555,17 @@ __device__ __forceinline__ void reverse_stage(const AdjointArgs& A, const RayCtx
     }
     constexpr float ci = (I == 3) ? 1.0f : 0.5f;
     constexpr float wprev = (I == 1) ? 1.0f : 2.0f;
+    float gL[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int c = 0; c < W; ++c) {
         Phys32 Yb;
         float Gb[3];
         rhs_vjp32(J, Fb[c], Yb, Gb);
-        phys_axpy(yb[c], 1.0, Yb);
-        if (SCATTER && c == W - 1) S.add(A, T, J.base, J.t, Gb);
+        phys_axpy(dy[c], 1.0f, Yb);
+        if (SCATTER) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) gL[q] = fmaf(lc[c], Gb[q], gL[q]);
+        }
         if constexpr (I > 0) {
             dlbar[c] += ci * phys_dot(Yb, FP) + (wprev * (1.0f / 6.0f)) * phys_dot(v[c], FP);
             phys_zero(Fb[c]);
@@ -555,21 +573,27 @@ __device__ __forceinline__ void reverse_stage(const AdjointArgs& A, const RayCtx
             phys_axpy(Fb[c], ci * dlf, Yb);
         }
     }
+    if (SCATTER) rec.template put_gbar<I>(gL);
     if constexpr (I > 0) {
         J = P;
         jet_gradient<AMR>(A.c.grid, F, rec.template get<I - 1>(), J);
-        reverse_stage<I - 1, AMR, W, SCATTER>(A, R, F, rec, Hc, dlf, J, v, Fb, dlbar, yb, S, T);
+        reverse_stage<I - 1, AMR, W, SCATTER>(A, R, F, rec, Hc, dlf, J, v, Fb, dlbar, dy, lc, S, T);
     }
 }
 
+// The loss column is a fixed linear combination of the others when the
+// Jacobian columns are carried (its end-point cotangent is
+// lc_0 beta_1 + lc_1 beta_2 + lc_2 z, and the sweep is linear), so it is
+// not propagated separately: its gradient cotangents are that combination of
+// the columns' ones.  Alone (W = 1) it is the only column, with lc_0 = 1.
 template <bool AMR, int W, bool SCATTER>
 __device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx& R, const FieldCache<AMR>& F,
                                              const StageRecord& rec, const HubbleCubic& Hc, double dl,
-                                             double ds_reg, double k0_step, Phys (&yb)[W], Scatter& S,
-                                             WaveTable& T)
+                                             double ds_reg, double k0_step, Phys (&yb)[W], const float (&lc)[W],
+                                             Scatter<AMR>& S, WaveTable& T)
 {
     const float dlf = (float)dl;
-    Phys32 v[W], Fb[W];
+    Phys32 v[W], Fb[W], dy[W];
     float dlbar[W];
     Jet32 J;
     const StageData d3 = rec.template get<3>();
@@ -583,9 +607,25 @@ __device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx&
             dlbar[c] = phys_dot(v[c], F4) * (1.0f / 6.0f);
             phys_zero(Fb[c]);
             phys_axpy(Fb[c], dlf * (1.0f / 6.0f), v[c]);
+            phys_zero(dy[c]);
         }
     }
-    reverse_stage<3, AMR, W, SCATTER>(A, R, F, rec, Hc, dlf, J, v, Fb, dlbar, yb, S, T);
+    reverse_stage<3, AMR, W, SCATTER>(A, R, F, rec, Hc, dlf, J, v, Fb, dlbar, dy, lc, S, T);
+    if (SCATTER) {
+        // the stages' gradient cotangents to the cells, last stage first (one
+        // copy of the accumulate-and-flush code)
+#pragma unroll 1
+        for (int i = 3; i >= 0; --i) {
+            int base;
+            float t[3], g[3];
+            rec.scatter_data(i, base, t, g);
+            S.add(A, T, base, t, g);
+        }
+    }
+    // the four stage increments, summed in single precision, enter the
+    // double-precision cotangent once per step
+#pragma unroll
+    for (int c = 0; c < W; ++c) phys_axpy(yb[c], 1.0, dy[c]);
     // a regular step has dl = ds / |k0| with ds fixed by the leaf level
     if (ds_reg > 0.0) {
         const double f = ds_reg / (k0_step * k0_step);
@@ -671,7 +711,7 @@ template <bool AMR, int W, bool SCATTER>
 __device__ __forceinline__ void end_cotangents(const AdjointArgs& A, const RayCtx& R, FieldCache<AMR>& F,
                                                const ObsDev& ob, int64_t ray, const GeoState& yf, double phio,
                                                const double e1[3], const double e2[3], Phys (&yb)[W],
-                                               double& phio_bar)
+                                               float (&lc)[W], double& phio_bar)
 {
     constexpr bool HAS_JAC = W >= 3;
     const GridDev& g = A.c.grid;
@@ -744,10 +784,17 @@ __device__ __forceinline__ void end_cotangents(const AdjointArgs& A, const RayCt
                 cb[bb] += ga[aa] * (-fs * ee + fps * et * ne);
             }
         }
-        Phys& L = yb[W - 1];
+        if constexpr (W == 1) {
+            Phys& L = yb[0];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) L.x[i] = (cb[0] * f1[i] + cb[1] * f2[i]) / chi + gz * dz_dphis * Jf.gphi[i];
-        L.k0 = -gz * dz_dK;
+            for (int i = 0; i < 3; ++i) L.x[i] = (cb[0] * f1[i] + cb[1] * f2[i]) / chi + gz * dz_dphis * Jf.gphi[i];
+            L.k0 = -gz * dz_dK;
+            lc[0] = 1.0f;
+        } else {
+            lc[0] = (float)cb[0];
+            lc[1] = (float)cb[1];
+            lc[2] = (float)gz;
+        }
         scatter_phi(A, end_base, Jf.t, gz * dz_dphis);
         phio_bar = gz * dz_dphio;
     }
@@ -755,8 +802,9 @@ __device__ __forceinline__ void end_cotangents(const AdjointArgs& A, const RayCt
     for (int c = 0; c < W; ++c) yb[c].eta -= phys_dot(yb[c], Jf.F) / Jf.F.eta;
 }
 
-// W cotangent columns: W = 4 (beta_1, beta_2, z, L), 3 (beta_1, beta_2, z)
-// or 1 (L).  SCATTER: the last column is L and its cell cotangents are kept.
+// W cotangent columns: W = 3 (beta_1, beta_2, z) or 1 (the loss L).
+// SCATTER: the cell cotangents of L are kept (with W = 3, L is the
+// combination lc of the three columns).
 template <bool AMR, int W, bool SCATTER>
 __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
 {
@@ -808,8 +856,11 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
     double e1[3], e2[3];
     screen_basis(n, e1, e2);
     Phys yb[W];
+    float lc[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) lc[c] = 0.0f;
     double phio_bar = 0.0;
-    Scatter S;
+    Scatter<AMR> S;
     S.init();
 
     // Segments from the source back to the observer.  Each is traversed
@@ -839,7 +890,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
                         ok = false;
                         break;
                     }
-                    end_cotangents<AMR, W, SCATTER>(A, R, F, ob, ray, y, phio, e1, e2, yb, phio_bar);
+                    end_cotangents<AMR, W, SCATTER>(A, R, F, ob, ray, y, phio, e1, e2, yb, lc, phio_bar);
                 }
             }
             const int jl = fwd ? it : len - 1 - (it - nf);
@@ -865,7 +916,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
                 HubbleCubic Hc;
                 Hc.init(a.cosmo, ys.eta);
                 const double ds_reg = landing ? 0.0 : ds;
-                reverse_step<AMR, W, SCATTER>(A, R, F, rec, Hc, dl, ds_reg, -ys.K, yb, S, T);
+                reverse_step<AMR, W, SCATTER>(A, R, F, rec, Hc, dl, ds_reg, -ys.K, yb, lc, S, T);
             }
         }
     }
@@ -890,9 +941,13 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
     if (SCATTER) {
         if (ok) {
             S.flush(A, T);
-            const Phys& L = yb[W - 1];
+            double Lk[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < W; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) Lk[i] += (double)lc[c] * yb[c].k[i];
             const double dkmag = kmag * 2.0 / (1.0 - 4.0 * phio * phio);
-            phio_bar += (L.k[0] * n[0] + L.k[1] * n[1] + L.k[2] * n[2]) * dkmag;
+            phio_bar += (Lk[0] * n[0] + Lk[1] * n[1] + Lk[2] * n[2]) * dkmag;
             GeoState y0;
             y0.eta = g.eta0;
             y0.K = 1.0;
@@ -957,8 +1012,8 @@ hipError_t launch_adjoint(const AdjointArgs& A, int columns, hipStream_t s)
     const size_t lds = lds_cache + (columns == 3 ? 0 : (size_t)(kBlock / 64) * kTabWords * sizeof(float));
     const bool amr = A.c.grid.max_level > 0;
     if (columns == 4) {
-        if (amr) hipLaunchKernelGGL((adjoint_kernel<true, 4, true>), grid, block, lds, s, A);
-        else hipLaunchKernelGGL((adjoint_kernel<false, 4, true>), grid, block, lds, s, A);
+        if (amr) hipLaunchKernelGGL((adjoint_kernel<true, 3, true>), grid, block, lds, s, A);
+        else hipLaunchKernelGGL((adjoint_kernel<false, 3, true>), grid, block, lds, s, A);
     } else if (columns == 3) {
         if (amr) hipLaunchKernelGGL((adjoint_kernel<true, 3, false>), grid, block, lds, s, A);
         else hipLaunchKernelGGL((adjoint_kernel<false, 3, false>), grid, block, lds, s, A);
