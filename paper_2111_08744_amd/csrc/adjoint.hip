@@ -323,7 +323,7 @@ __device__ __forceinline__ int64_t grad_slot(int64_t id, int q, int64_t n)
 // neighbouring sky pixels and cross the same cells many times, so the table
 // absorbs most additions and the device atomics (which resolve beyond the
 // per-XCD L2) drop by that reuse factor.
-constexpr int kTab = 512;               // entries per wave (power of two)
+constexpr int kTab = 256;               // entries per wave (power of two)
 constexpr int kTabWords = 4 * kTab + 4; // keys, 3 value planes, fill counter (padded)
 
 struct WaveTable {
@@ -388,7 +388,7 @@ struct WaveTable {
         int h[8], old[8];
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
-            h[o] = (int)(((uint32_t)ids[o] * 2654435761u) >> (32 - 9));
+            h[o] = (int)(((uint32_t)ids[o] * 2654435761u) >> (32 - 8));
             old[o] = ids[o] >= 0 ? atomicCAS(&keys[h[o]], -1, ids[o]) : ids[o];
         }
         int claimed = 0;
@@ -417,21 +417,29 @@ struct WaveTable {
         }
     }
 };
-static_assert(kTab == 512, "the slot hash takes the top 9 bits");
+static_assert(kTab == 256, "the slot hash takes the top 8 bits");
 
 // Per-lane accumulator (registers) of the gradient cotangents of the 8 cells
-// of the current stencil, moved into the wave's table when the stencil
-// changes.  The cell ids of the current stencil are loaded when it becomes
-// current, so the load is in flight long before the flush needs it.
+// of the current stencil.  When the stencil changes the sums move to a
+// pending slot in LDS, and pending slots enter the wave's table once per
+// step, so that a wave runs the table insertion about once per step rather
+// than at every stage where one of its lanes changes stencil.  The cell ids
+// of a stencil are loaded when it becomes current, long before they are
+// needed.
+constexpr int kPendWords = 33;          // 24 sums, 8 cell ids, spare
 
 template <bool AMR>
 struct Scatter {
     float acc[8][3];
     int ids[8];
     int cur;
+    bool pending;
+    float* pend;        // this lane's pending slot: word w at pend[w * kBlock]
 
-    __device__ __forceinline__ void init()
+    __device__ __forceinline__ void init(float* slot)
     {
+        pend = slot;
+        pending = false;
         cur = -1;
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
@@ -441,22 +449,55 @@ struct Scatter {
         }
     }
 
-    __device__ __forceinline__ void flush(const AdjointArgs& A, WaveTable& T)
+    __device__ __forceinline__ void flush_pending(const AdjointArgs& A, WaveTable& T)
+    {
+        float pa[8][3];
+        int pi[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) pa[o][q] = pend[(3 * o + q) * kBlock];
+            pi[o] = __float_as_int(pend[(24 + o) * kBlock]);
+        }
+        T.add8(A, pi, pa);
+        pending = false;
+    }
+
+    // move the current sums to the pending slot (inserting an older pending
+    // slot first)
+    __device__ __forceinline__ void stash(const AdjointArgs& A, WaveTable& T)
     {
         if (cur < 0) return;
-        T.add8(A, ids, acc);
+        if (pending) flush_pending(A, T);
 #pragma unroll
-        for (int o = 0; o < 8; ++o)
+        for (int o = 0; o < 8; ++o) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) acc[o][q] = 0.0f;
+            for (int q = 0; q < 3; ++q) {
+                pend[(3 * o + q) * kBlock] = acc[o][q];
+                acc[o][q] = 0.0f;
+            }
+            pend[(24 + o) * kBlock] = __int_as_float(ids[o]);
+        }
+        pending = true;
         cur = -1;
+    }
+
+    __device__ __forceinline__ void end_step(const AdjointArgs& A, WaveTable& T)
+    {
+        if (pending) flush_pending(A, T);
+    }
+
+    __device__ __forceinline__ void flush(const AdjointArgs& A, WaveTable& T)
+    {
+        stash(A, T);
+        end_step(A, T);
     }
 
     __device__ __forceinline__ void add(const AdjointArgs& A, WaveTable& T, int base, const float t[3],
                                         const float Gb[3])
     {
         if (base != cur) {
-            flush(A, T);
+            stash(A, T);
             cur = base;
             const int4* p = reinterpret_cast<const int4*>(A.c.grid.dual_ids + 8 * (int64_t)base);
             const int4 a = p[0], b = p[1];
@@ -621,6 +662,7 @@ __device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx&
             rec.scatter_data(i, base, t, g);
             S.add(A, T, base, t, g);
         }
+        S.end_step(A, T);
     }
     // the four stage increments, summed in single precision, enter the
     // double-precision cotangent once per step
@@ -809,11 +851,11 @@ template <bool AMR, int W, bool SCATTER>
 __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
 {
     // LDS: [32][kBlock] stencil coefficients, [4 * 18][kBlock] stage records,
-    // then one table per wave
+    // [33][kBlock] pending scatter sums, then one table per wave
     extern __shared__ float lds[];
     WaveTable T;
     if (SCATTER) {
-        T.bind(lds + (32 + 4 * StageRecord::kWords) * kBlock + (threadIdx.x >> 6) * kTabWords);
+        T.bind(lds + (32 + 4 * StageRecord::kWords + kPendWords) * kBlock + (threadIdx.x >> 6) * kTabWords);
         T.clear(threadIdx.x & 63);
     }
     const int64_t ray = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -861,7 +903,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
     for (int c = 0; c < W; ++c) lc[c] = 0.0f;
     double phio_bar = 0.0;
     Scatter<AMR> S;
-    S.init();
+    S.init(lds + (32 + 4 * StageRecord::kWords) * kBlock + threadIdx.x);
 
     // Segments from the source back to the observer.  Each is traversed
     // forwards from its checkpoint (storing the state before every step in
@@ -1009,7 +1051,8 @@ hipError_t launch_adjoint(const AdjointArgs& A, int columns, hipStream_t s)
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
     const size_t lds_cache = (size_t)(32 + 4 * StageRecord::kWords) * kBlock * sizeof(float);
-    const size_t lds = lds_cache + (columns == 3 ? 0 : (size_t)(kBlock / 64) * kTabWords * sizeof(float));
+    const size_t lds = lds_cache + (columns == 3 ? 0 : ((size_t)kPendWords * kBlock + (size_t)(kBlock / 64) * kTabWords) *
+                                                          sizeof(float));
     const bool amr = A.c.grid.max_level > 0;
     if (columns == 4) {
         if (amr) hipLaunchKernelGGL((adjoint_kernel<true, 3, true>), grid, block, lds, s, A);
