@@ -912,20 +912,24 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
     // stages of every step re-recorded and reversed.  One loop with a single
     // step call site serves both directions.
     bool ok = true;
+    // the tape entry of the next reverse step and the next segment's
+    // checkpoint are loaded one iteration ahead of their use
+    GeoState pre, ck = a.ckpt[(int64_t)(nseg - 1) * a.n_rays + ray];
     for (int seg = nseg - 1; seg >= 0 && ok; --seg) {
         const bool last = seg == nseg - 1;
         const int j0 = seg * K;
         const int len = min(N, j0 + K) - j0;
         const int nf = last ? len : len - 1;
-        GeoState y = a.ckpt[(int64_t)seg * a.n_rays + ray];
+        GeoState y = ck, yin = ck;
         for (int it = 0; it < nf + len; ++it) {
             const bool fwd = it < nf;
             // the lanes still iterating empty the table when it is half full
             if (SCATTER && *T.count > kTab / 2) T.evict(A);
             if (it == nf) {
-                if (!last) {
-                    A.tape[(int64_t)(len - 1) * a.n_rays + ray] = y;
-                } else {
+                // the state before the segment's last step is in registers
+                pre = last ? yin : y;
+                if (seg > 0) ck = a.ckpt[(int64_t)(seg - 1) * a.n_rays + ray];
+                if (last) {
                     // the replay must end where the forward cast ended, bit for bit
                     const RayEnd e = a.ends[ray];
                     if (y.eta != e.eta || y.dx[0] != e.dx[0] || y.dx[1] != e.dx[1] || y.dx[2] != e.dx[2]) {
@@ -940,8 +944,10 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
             if (fwd) {
                 A.tape[(int64_t)jl * a.n_rays + ray] = y;
                 ys = y;
+                yin = y;
             } else {
-                ys = A.tape[(int64_t)jl * a.n_rays + ray];
+                ys = pre;
+                if (jl > 0) pre = A.tape[(int64_t)(jl - 1) * a.n_rays + ray];
             }
             StageRecord rec;
             rec.p = lds + 32 * kBlock + threadIdx.x;
