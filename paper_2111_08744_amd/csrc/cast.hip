@@ -18,10 +18,12 @@ namespace mpath {
 namespace {
 
 constexpr int kWave = 64;
-// Occupancy target of the integration kernels: 3 waves per SIMD keeps the
-// live state in registers (measured: 2 waves without the bound, 4 waves
-// spill to scratch and run 2x slower).
-constexpr int kMinWavesPerSimd = 3;
+// Occupancy target of the integration kernels: 4 waves per SIMD (128
+// registers).  A wave stalls on every stage where one of its lanes enters a
+// new stencil (a dependent stencil-table and coefficient gather), so latency
+// hiding pays more than the few values the bound spills (measured on the AMR
+// workload: 3 waves 102.6 ms, 4 waves 89.5 ms per cast).
+constexpr int kMinWavesPerSimd = 4;
 
 // Everything one lane carries for its current ray.
 template <bool AMR>
