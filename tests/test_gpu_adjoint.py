@@ -276,3 +276,49 @@ def test_adjoint_argument_errors(M, gauss64):
     out2 = _fwd(M, g2, cfg2)
     with pytest.raises(M.MpathError):
         M.adjoint(g2, cfg2, out2, cells=True, phi_total=True)
+
+
+def test_amr_loss_gradient_directional(M):
+    """Cell gradient on an octree (stencils at several levels, fallback near
+    refinement boundaries): <dL/dvalues, delta> against the oracle."""
+    import torch
+    cells = synth.random_amr_cells(16, 125.0, 3, seed=6)
+    grid = M.Grid(cells, COSMO)
+    obs = [40.0, 70.0, 90.0]
+    cfg = M.CastConfig(obs, 0.1, 2, steps_per_cell=4, adaptive=True, checkpoint_every=16)
+    out = M.cast(grid, cfg)
+    alpha = out["alpha"].to(torch.float64)
+    wz = np.random.default_rng(3).normal(size=alpha.shape[0])
+    res = M.adjoint(grid, cfg, out, dL_dalpha=2.0 * alpha, dL_dz=torch.tensor(wz, device="cuda"), cells=True,
+                    jacobian=True)
+    torch.cuda.synchronize()
+    assert (_np(res["ray_status"]) == 0).all()
+    g = _np(res["dL_dvalues"]).astype(np.float64)
+    field = O.Field.grid(cells)
+    p = O.params(obs, z_src=0.1, steps_per_cell=4, adaptive=True)
+    dirs = oracle_dirs(2, [0], [48])
+    a = _np(alpha)
+    rng = np.random.default_rng(12)
+    for trial in range(2):
+        delta = rng.normal(size=(cells.n_cells, 4)) * 1e-5
+        _, tan = O.cast_cs(field, O.cosmo(*COSMO), p, dirs, dphi=delta[:, 0], dgrad=delta[:, 1:])
+        want = np.sum(2.0 * a * tan["alpha"]) + np.sum(wz * tan["z5"])
+        got = np.sum(g * delta)
+        _print(f"AMR trial {trial}: adjoint {got:.9e} oracle {want:.9e}")
+        assert abs(got - want) <= 1e-5 * abs(want)
+
+
+def test_rays_without_derivative(M):
+    """Rays that leave a non-periodic box get no derivative: NaN Jacobian,
+    ray_status 1, and no contribution to the cell gradient."""
+    import torch
+    cells = synth.random_amr_cells(16, 125.0, 2, seed=8, periodic=False)
+    grid = M.Grid(cells, COSMO)
+    cfg = M.CastConfig([60.0, 62.0, 58.0], 0.2, 2, steps_per_cell=4, adaptive=True, checkpoint_every=32)
+    out = M.cast(grid, cfg)
+    res = M.adjoint(grid, cfg, out, dL_dalpha=torch.ones((48, 2), device="cuda"), jacobian=True, cells=True)
+    torch.cuda.synchronize()
+    assert (_np(out["status"]) == M.MPATH_RAY_LEFT_DOMAIN).all()
+    assert (_np(res["ray_status"]) == 1).all()
+    assert np.isnan(_np(res["jac"])).all() and np.isnan(_np(res["dz_dtheta"])).all()
+    assert (_np(res["dL_dvalues"]) == 0).all()
