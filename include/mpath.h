@@ -158,7 +158,7 @@ typedef struct {
     int32_t order;              /* 1 = CIC; 0 (NGP) and 2 (TSC): MPATH_ERR_UNSUPPORTED */
     int32_t steps_per_cell;     /* N >= 1: comoving step length h / N                   */
     int32_t adaptive;           /* 1: h of the leaf cell at the step start; 0: coarse h */
-    int64_t max_steps;          /* per ray, including the landing step                   */
+    int64_t max_steps;          /* per ray, including the landing step (at most 2^31-1)  */
     /* launch shape; 0 = library default (mpath_autotune picks them by timing) */
     int32_t schedule;
     int32_t block_size;         /* threads per block: 0 or 256                          */

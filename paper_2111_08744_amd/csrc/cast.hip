@@ -29,12 +29,11 @@ constexpr int kMinWavesPerSimd = 4;
 template <bool AMR>
 struct RayRun {
     int64_t ray;          // -1: no ray
-    int obs;
     RayGeom geo;
     double eta_s;
     float phi_o;
     GeoState y;
-    int64_t n_steps;
+    int32_t n_steps;
     uint32_t hash;
     int status;           // -1 while running
     FieldCache<AMR> F;
@@ -45,7 +44,6 @@ struct RayRun {
         // observer owning the ray (observers are few; linear scan from the end)
         int j = a.n_obs - 1;
         while (j > 0 && a.obs[j].ray_first > r) --j;
-        obs = j;
         const ObsDev& ob = a.obs[j];
 #pragma unroll
         for (int i = 0; i < 3; ++i) geo.uo[i] = ob.x[i] / a.grid.h0;
@@ -131,7 +129,9 @@ struct RayRun {
     // transcendental functions out of the integration kernel's registers.
     __device__ __forceinline__ void finish(const CastArgs& a)
     {
-        const ObsDev& ob = a.obs[obs];
+        int j = a.n_obs - 1;
+        while (j > 0 && a.obs[j].ray_first > ray) --j;
+        const ObsDev& ob = a.obs[j];
         double u[3];
         grid_coords(a.grid, geo, y.eta, y.dx, u);
         float phi_s = __builtin_nanf(""), G[3];
@@ -150,7 +150,7 @@ struct RayRun {
         RayEnd e;
         e.eta = y.eta;
         e.dx[0] = y.dx[0]; e.dx[1] = y.dx[1]; e.dx[2] = y.dx[2];
-        e.obs = obs;
+        e.obs = j;
         a.ends[ray] = e;
     }
 };

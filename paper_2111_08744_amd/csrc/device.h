@@ -204,11 +204,9 @@ __device__ __forceinline__ float trilinear_eval(float c0, float c1, float c2, fl
 // (leaf cell, floor(x / h_{L+1})); the build precomputes it per half-cell.
 template <bool AMR>
 struct FieldCache {
-    int leafL;          // level of the cached leaf cell (-1: none)
-    int leafId;         // its id
-    int leafI[3];       // its unwrapped coordinates at level leafL
-    int keyL;           // leaf level the stencil was resolved for (-1: none)
-    int key[3];         // unwrapped coordinates at level keyL + 1
+    int leafId;         // id of the leaf cell containing the cached half-cell
+    int keyL;           // level of that leaf (-1: nothing cached)
+    int key[3];         // unwrapped coordinates of the half-cell at level keyL + 1
     int lvl;            // level of the resolved stencil
     int base;           // id of its lowest corner cell
     float t[3];         // offsets of the last evaluated point in that stencil
@@ -221,14 +219,12 @@ struct FieldCache {
     // for every (f, k) (no bank conflicts) at compile-time offsets
     __device__ __forceinline__ void bind(float* lds) { c = lds; }
 
-    __device__ __forceinline__ void reset()
-    {
-        leafL = -1;
-        keyL = -1;
-    }
+    __device__ __forceinline__ void reset() { keyL = -1; }
 
     // Leaf level at the point with unwrapped coordinates I at level
-    // max_level + 1; -1 outside a non-periodic box.
+    // max_level + 1; -1 outside a non-periodic box.  The cached leaf is the
+    // one holding the cached half-cell; a walk to another leaf drops the
+    // cached stencil, so that leafId always belongs to key.
     __device__ __forceinline__ int leaf(const GridDev& g, const int I[3])
     {
         if (!AMR) {
@@ -241,9 +237,10 @@ struct FieldCache {
             return 0;
         }
         const int Lm = g.max_level;
-        if (leafL >= 0) {
-            const int sh = Lm + 1 - leafL;
-            if ((I[0] >> sh) == leafI[0] && (I[1] >> sh) == leafI[1] && (I[2] >> sh) == leafI[2]) return leafL;
+        if (keyL >= 0) {
+            const int sh = Lm + 1 - keyL;
+            if ((I[0] >> sh) == (key[0] >> 1) && (I[1] >> sh) == (key[1] >> 1) && (I[2] >> sh) == (key[2] >> 1))
+                return keyL;
         }
         int J0 = I[0] >> 1, J1 = I[1] >> 1, J2 = I[2] >> 1;   // level max_level
         const int M = g.n0 << Lm;
@@ -260,10 +257,8 @@ struct FieldCache {
             id = ch + (((J0 >> m) & 1) | (((J1 >> m) & 1) << 1) | (((J2 >> m) & 1) << 2));
             ++L;
         }
-        leafL = L;
         leafId = id;
-        const int sh = Lm + 1 - L;
-        leafI[0] = I[0] >> sh; leafI[1] = I[1] >> sh; leafI[2] = I[2] >> sh;
+        keyL = -1;
         return L;
     }
 

@@ -549,7 +549,7 @@ CastArgs make_cast_args(const mpath_grid* g, const mpath_cast_desc* d, const Cas
     a.adaptive = d->adaptive ? 1 : 0;
     for (int l = 0; l <= kMaxLevels; ++l)
         a.ds_level[l] = (g->box / g->n0) / (double)(1 << (a.adaptive ? l : 0)) / (double)d->steps_per_cell;
-    a.max_steps = d->max_steps;
+    a.max_steps = std::min<int64_t>(d->max_steps, INT32_MAX);   // steps are counted in 32 bits
     a.n_rays = n_rays;
     a.queue = (unsigned long long*)(ws + lay.off_queue);
     a.ends = (RayEnd*)(ws + lay.off_ends);
@@ -559,7 +559,7 @@ CastArgs make_cast_args(const mpath_grid* g, const mpath_cast_desc* d, const Cas
         a.ckpt = (GeoState*)(ws + lay.off_ckpt);
         a.ckpt_every = d->checkpoint_every;
         a.ckpt_slots = (int32_t)lay.ckpt_slots;
-        a.max_steps = std::min<int64_t>(d->max_steps, lay.ckpt_slots * (int64_t)d->checkpoint_every);
+        a.max_steps = std::min<int64_t>(a.max_steps, lay.ckpt_slots * (int64_t)d->checkpoint_every);
     }
     return a;
 }
