@@ -35,6 +35,10 @@ FLOPS_PER_RAY_STEP = 580.0
 # Peak for this kernel: vector FMA on 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
 # Packed FP32 is disabled, so FP32 and FP64 issue at the same rate.
 PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Unique table bytes one ray-step needs with perfect stencil reuse: a new CIC
+# stencil brings 4 new cells of 16 bytes about (|n_x|+|n_y|+|n_z|)/N times per
+# step (N steps per cell; 1.5 on average over directions).
+ALGO_BYTES_PER_RAY_STEP = {"amr": 64 * 1.5 / 4, "uniform": 64 * 1.5 / 10, "batched": 64 * 1.5 / 10}
 
 
 def log(*a):
@@ -116,6 +120,36 @@ def _time_ms(torch, fn, reps=2):
     return best
 
 
+def measure_gather_ceiling(M, torch, table, dev):
+    """Random-record gather throughput (mpath_gather_probe) over a table of the
+    grid image's size: records of 16, 64 and 128 bytes at uniform random
+    indices, 1 or 4 reads in flight per lane, 4 to 32 waves per CU. Returns the
+    best rate per record size in GB/s of records read."""
+    from paper_2111_08744_amd import _abi
+    L = _abi.lib()
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    best = {}
+    for rec in (16, 64, 128):
+        for wpc in (4, 8, 16, 32):
+            for u in (1, 4):
+                n_waves = n_cu * wpc
+                iters = max(1, round((1 << 31) / (n_waves * 64 * u * rec)))
+                out = torch.empty(n_waves * 64, dtype=torch.float32, device=dev)
+
+                def run():
+                    _abi.check(L.mpath_gather_probe(table.data_ptr(), table.numel(), rec, u, n_waves, iters,
+                                                    12345, out.data_ptr(), stream), "mpath_gather_probe")
+                ms = _time_ms(torch, run, reps=3)
+                gbs = n_waves * 64 * iters * u * rec / (ms / 1e3) / 1e9
+                if gbs > best.get(rec, {}).get("GB_per_s", 0.0):
+                    best[rec] = {"GB_per_s": gbs, "waves_per_cu": wpc, "in_flight": u}
+    log("[bench] random gathers over %.2f GB: %s" % (table.numel() / 1e9, ", ".join(
+        f"{r} B records {b['GB_per_s']:.0f} GB/s ({b['waves_per_cu']} waves/CU, {b['in_flight']} in flight)"
+        for r, b in best.items())))
+    return best
+
+
 def measure_adjoint(M, torch, dev):
     """Differentiated workload: 2^20 rays (NESTED nside 512, pixels [0, 2^20))
     to z = 1 on the uniform 64^3 grid, 10 steps per cell, checkpoints every 32
@@ -192,6 +226,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the adjoint and batched-launch measurements")
+    ap.add_argument("--no-gather-probe", action="store_true",
+                    help="skip the random-gather ceiling measurement")
     ap.add_argument("--cpu-stride", type=int, default=48)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the casts, copy MIB mebibytes once with a plain device copy "
@@ -295,6 +331,20 @@ def main():
                      "traffic": traffic, "kernel": "cast_kernel",
                      "launch_ms_mean": float(np.mean(launch_ms))},
     }
+    if not args.no_gather_probe:
+        best = measure_gather_ceiling(M, torch, grid.ws, dev)
+        peak = best[128]["GB_per_s"]
+        hbm = traffic / (kern_s * 1e9) if traffic is not None else None
+        res["gather_roofline"] = {
+            "kernel": "cast_kernel", "unit": "GB/s",
+            "achieved": hbm, "peak": peak, "frac": hbm / peak if hbm is not None else None,
+            "peak_kind": "measured: uniform random 128-byte record gathers over a table of the grid image's size",
+            "achieved_kind": "HBM bytes per launch from FETCH_SIZE + WRITE_SIZE counters / mean launch time",
+            "table_bytes": int(grid.ws.numel()),
+            "probe_best": {str(r): b for r, b in best.items()},
+            "hbm_bytes_per_ray_step": traffic / ray_steps if traffic is not None else None,
+            "algorithmic_bytes_per_ray_step": ALGO_BYTES_PER_RAY_STEP.get(w.name),
+        }
     if not args.no_secondary:
         sec = {"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev)}
         res["secondary"] = sec

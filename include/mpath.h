@@ -283,6 +283,26 @@ int mpath_autotune(const mpath_grid* grid, const mpath_cast_desc* desc, int32_t 
 /* Number of rays a desc describes. */
 int mpath_cast_count_rays(const mpath_cast_desc* desc, int64_t* n_rays);
 
+/* ---- measurement utility (not a step of the method) ----
+ *
+ * mpath_gather_probe: random-record gather throughput, the ceiling that the
+ * integration kernel's data-dependent table lookups are measured against.
+ * Launches n_waves one-wave workgroups; each of the n_waves * 64 lanes reads
+ * `iters * in_flight` records of `record_bytes` (16, 64 or 128) bytes at
+ * indices drawn uniformly in [0, table_bytes / record_bytes) from its own
+ * xorshift32 sequence (seeded by `seed` and the lane number), with
+ * `in_flight` (1, 2 or 4) independent reads outstanding per lane, and writes
+ * the float sum of what it read to out[lane].
+ *   table: DEVICE, 16-byte aligned, table_bytes readable bytes (any content;
+ *          at most 2^32 - 1 records).
+ *   out:   DEVICE float[n_waves * 64], written.
+ *   n_waves in [1, 2^24], iters >= 1.
+ * Bytes gathered = n_waves * 64 * iters * in_flight * record_bytes.  The call
+ * is asynchronous on the stream (time it with events on that stream).
+ * Errors: INVALID_ARG for the ranges above, DEVICE for a launch failure. */
+int mpath_gather_probe(const void* table, size_t table_bytes, int32_t record_bytes, int32_t in_flight,
+                       int64_t n_waves, int32_t iters, uint32_t seed, float* out, void* stream);
+
 const char* mpath_status_string(int status);
 const char* mpath_last_error(void);
 const char* mpath_version(void);

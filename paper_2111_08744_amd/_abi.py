@@ -95,6 +95,7 @@ def lib():
         L.mpath_autotune_workspace_bytes.argtypes = [vp, P(mpath_cast_desc), C.c_int32, P(sz)]
         L.mpath_autotune.argtypes = [vp, P(mpath_cast_desc), C.c_int32, vp, sz, vp, P(mpath_cast_desc),
                                      P(C.c_float)]
+        L.mpath_gather_probe.argtypes = [vp, sz, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_uint32, vp, vp]
         L.mpath_status_string.restype = C.c_char_p
         L.mpath_status_string.argtypes = [C.c_int]
         L.mpath_last_error.restype = C.c_char_p
@@ -102,7 +103,7 @@ def lib():
         for name in ("mpath_grid_workspace_bytes", "mpath_grid_build", "mpath_grid_free",
                      "mpath_grid_get_info", "mpath_grid_set_values", "mpath_cast_workspace_bytes",
                      "mpath_cast", "mpath_cast_count_rays", "mpath_adjoint_workspace_bytes",
-                     "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune"):
+                     "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune", "mpath_gather_probe"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

@@ -194,12 +194,12 @@ __device__ __forceinline__ void stencil_coefs(const GridDev& g, const FieldCache
 __device__ __forceinline__ void stage_offsets(const GridDev& g, const RayCtx& R, const GeoState& ys, int lvl,
                                               double t[3])
 {
-    double u[3];
-    grid_coords(g, R.geo, ys.eta, ys.dx, u);
-    const double sl = (double)(1 << lvl);
+    double v[3];
+    grid_coords(g, R.geo, ys.eta, ys.dx, v);
+    const double sl = ldexp(1.0, lvl - g.max_level - 1);    // v sl = x 2^lvl / h0 exactly
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double q = u[d] * sl - 0.5;
+        const double q = v[d] * sl - 0.5;
         t[d] = q - floor(q);
     }
 }
@@ -534,13 +534,11 @@ __device__ __forceinline__ bool plan_step(const CastArgs& a, FieldCache<AMR>& F,
                                           const GeoState& y, double eta_s, double& ds, double& dl, bool& landing)
 {
     const GridDev& g = a.grid;
-    double u[3];
-    grid_coords(g, geo, y.eta, y.dx, u);
-    const int Lm = AMR ? g.max_level : 0;
-    const double scale = (double)(2 << Lm);
+    double v[3];
+    grid_coords(g, geo, y.eta, y.dx, v);
     int I[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) I[d] = (int)floor(u[d] * scale);
+    for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
     const int L = F.leaf(g, I);
     if (L < 0) return false;
     ds = a.ds_level[L];
@@ -759,9 +757,9 @@ __device__ __forceinline__ void end_cotangents(const AdjointArgs& A, const RayCt
     const GridDev& g = A.c.grid;
     float ph_f, Gt[3];
     int ll, lv;
-    double uf[3];
-    grid_coords(g, R.geo, yf.eta, yf.dx, uf);
-    F.eval(g, uf, ph_f, Gt, ll, lv);
+    double vf[3];
+    grid_coords(g, R.geo, yf.eta, yf.dx, vf);
+    F.eval(g, vf, ph_f, Gt, ll, lv);
     HubbleCubic Hf;
     Hf.init(A.c.cosmo, yf.eta);
     PointJet Jf;
@@ -876,7 +874,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         R.xobs[i] = ob.x[i];
-        R.geo.uo[i] = ob.x[i] / g.h0;
+        R.geo.vo[i] = ldexp(ob.x[i] / g.h0, g.max_level + 1);
         R.geo.n[i] = a.dirs[3 * ray + i];
     }
     const double eta_s = ob.eta_s;
@@ -887,7 +885,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
     // potential at the observer and the initial |k| (as in the forward)
     float phio_f, Gt[3];
     int ll, lv;
-    F.eval(g, R.geo.uo, phio_f, Gt, ll, lv);
+    F.eval(g, R.geo.vo, phio_f, Gt, ll, lv);
     const int obs_base = F.base, obs_lvl = F.lvl;
     const double phio = (double)phio_f;
     const double kmag = sqrt((1.0 + 2.0 * phio) / (1.0 - 2.0 * phio));

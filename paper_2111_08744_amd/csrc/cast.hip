@@ -46,7 +46,7 @@ struct RayRun {
         while (j > 0 && a.obs[j].ray_first > r) --j;
         const ObsDev& ob = a.obs[j];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) geo.uo[i] = ob.x[i] / a.grid.h0;
+        for (int i = 0; i < 3; ++i) geo.vo[i] = ldexp(ob.x[i] / a.grid.h0, a.grid.max_level + 1);
         geo.n[0] = a.dirs[3 * r];
         geo.n[1] = a.dirs[3 * r + 1];
         geo.n[2] = a.dirs[3 * r + 2];
@@ -57,7 +57,7 @@ struct RayRun {
         status = -1;
         float G[3];
         int leafl, l;
-        if (F.eval(a.grid, geo.uo, phi_o, G, leafl, l)) {
+        if (F.eval(a.grid, geo.vo, phi_o, G, leafl, l)) {
             status = MPATH_RAY_LEFT_DOMAIN;
             phi_o = __builtin_nanf("");
         }
@@ -85,13 +85,11 @@ struct RayRun {
             if (CKPT && n_steps % a.ckpt_every == 0)
                 a.ckpt[(n_steps / a.ckpt_every) * a.n_rays + ray] = y;
             // leaf level at the step start sets the step length (N steps per cell)
-            double u[3];
-            grid_coords(g, geo, y.eta, y.dx, u);
-            const int Lm = AMR ? g.max_level : 0;
-            const double scale = (double)(2 << Lm);
+            double v[3];
+            grid_coords(g, geo, y.eta, y.dx, v);
             int I[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) I[d] = (int)floor(u[d] * scale);
+            for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
             const int L = F.leaf(g, I);
             if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
             hash = fnv(hash, (uint32_t)L);
@@ -132,11 +130,11 @@ struct RayRun {
         int j = a.n_obs - 1;
         while (j > 0 && a.obs[j].ray_first > ray) --j;
         const ObsDev& ob = a.obs[j];
-        double u[3];
-        grid_coords(a.grid, geo, y.eta, y.dx, u);
+        double v[3];
+        grid_coords(a.grid, geo, y.eta, y.dx, v);
         float phi_s = __builtin_nanf(""), G[3];
         int leafl, l;
-        if (F.eval(a.grid, u, phi_s, G, leafl, l)) phi_s = __builtin_nanf("");
+        if (F.eval(a.grid, v, phi_s, G, leafl, l)) phi_s = __builtin_nanf("");
         const OutDev& o = a.out;
         const bool ok = status == MPATH_RAY_REACHED;
         if (o.z5)

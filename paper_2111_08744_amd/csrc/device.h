@@ -152,14 +152,18 @@ __device__ __forceinline__ int lookup_cell(const GridDev& g, int l, int J0, int 
     return id;
 }
 
-// Level of a cell id (ids are level-major).  Unrolled comparisons keep the
+// Level of a cell id (ids are level-major).  The scan stops at the grid's
+// deepest level (a uniform branch), and the unrolled comparisons keep the
 // level table in scalar registers (a dynamically indexed array would be
 // copied to vector registers).
 __device__ __forceinline__ int level_of(const GridDev& g, int id)
 {
     int l = 0;
 #pragma unroll
-    for (int k = 1; k < kMaxLevels; ++k) l += (k <= g.max_level && id >= g.level_start[k]) ? 1 : 0;
+    for (int k = 1; k < kMaxLevels; ++k) {
+        if (k > g.max_level) break;
+        l += (id >= g.level_start[k]) ? 1 : 0;
+    }
     return l;
 }
 
@@ -303,19 +307,19 @@ struct FieldCache {
         return true;
     }
 
-    // Phi and grad Phi at the point with coarse-grid coordinates u (CIC,
+    // Phi and grad Phi at the point with fine-grid coordinates v = x / h_f,
+    // h_f = h0 / 2^(max_level + 1) (CIC,
     // Eq. W_CIC, with the level fallback).  Returns 0, or 1 when no complete
     // stencil exists.  leaf_level and stencil_level receive the levels of the
     // deepest cell containing the point and of the stencil used.
-    __device__ __forceinline__ int eval(const GridDev& g, const double u[3], float& phi, float G[3],
+    __device__ __forceinline__ int eval(const GridDev& g, const double v[3], float& phi, float G[3],
                                         int& leaf_level, int& stencil_level)
     {
         #pragma clang fp contract(off)
         const int Lm = AMR ? g.max_level : 0;
-        const double scale = (double)(2 << Lm);      // 2^(Lm+1)
         int I[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) I[d] = (int)floor(u[d] * scale);
+        for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
         int L;
         if (AMR && keyL >= 0 && (I[0] >> (Lm - keyL)) == key[0] && (I[1] >> (Lm - keyL)) == key[1] &&
             (I[2] >> (Lm - keyL)) == key[2]) {
@@ -334,12 +338,13 @@ struct FieldCache {
         }
         leaf_level = L;
         stencil_level = lvl;
-        // offsets from the stencil base (lowest corner) at level lvl
+        // offsets from the stencil base (lowest corner) at level lvl;
+        // v 2^(lvl - Lm - 1) is exact
         const int s = Lm - lvl;
-        const double sl = (double)(1 << lvl);
-        const float tx = (float)(u[0] * sl - 0.5 - (double)(((I[0] >> s) - 1) >> 1));
-        const float ty = (float)(u[1] * sl - 0.5 - (double)(((I[1] >> s) - 1) >> 1));
-        const float tz = (float)(u[2] * sl - 0.5 - (double)(((I[2] >> s) - 1) >> 1));
+        const double sl = ldexp(1.0, -s - 1);
+        const float tx = (float)(v[0] * sl - 0.5 - (double)(((I[0] >> s) - 1) >> 1));
+        const float ty = (float)(v[1] * sl - 0.5 - (double)(((I[1] >> s) - 1) >> 1));
+        const float tz = (float)(v[2] * sl - 0.5 - (double)(((I[2] >> s) - 1) >> 1));
         t[0] = tx; t[1] = ty; t[2] = tz;
         // f = c0 + tx (c1 + ty (c4 + tz c7) + tz c5) + ty (c2 + tz c6) + tz c3
         float f[4];
@@ -373,21 +378,23 @@ struct FieldCache {
 // exactly and is not carried.
 // ---------------------------------------------------------------------------
 struct RayGeom {
-    double uo[3];       // observer in coarse-grid coordinates (x_obs / h0)
+    double vo[3];       // observer in fine-grid coordinates (x_obs / h_f)
     double n[3];        // initial direction (unit)
 };
 
-// Coarse-grid coordinates u = x / h0 of x = x_obs + s n + dx, s = eta0 - eta.
-// The observer term is the exact quotient; the displacement is scaled by
-// 1/h0 (at the observer both agree exactly with x / h0, elsewhere to one
-// rounding).
+// Fine-grid coordinates v = x / h_f, h_f = h0 / 2^(max_level + 1), of
+// x = x_obs + s n + dx, s = eta0 - eta.  The observer term is the exact
+// quotient; the displacement is scaled by 1/h_f (at the observer both agree
+// exactly with x / h_f, elsewhere to one rounding).  Scaling by the power of
+// two is exact, so v is 2^(max_level + 1) times the coarse-grid coordinates
+// computed the same way.
 __device__ __forceinline__ void grid_coords(const GridDev& g, const RayGeom& r, double eta, const float dx[3],
-                                            double u[3])
+                                            double v[3])
 {
     #pragma clang fp contract(off)
     const double s = g.eta0 - eta;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) u[i] = fma(fma(s, r.n[i], (double)dx[i]), g.inv_h0, r.uo[i]);
+    for (int i = 0; i < 3; ++i) v[i] = fma(fma(s, r.n[i], (double)dx[i]), g.inv_hf, r.vo[i]);
 }
 
 // No-op stage recorder of the forward kernels.

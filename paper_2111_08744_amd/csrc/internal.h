@@ -45,6 +45,7 @@ struct GridDev {
     const int32_t* dual_ids;  // [n][8] ids of the 8 cells of dual[c] (-1: missing)
     double h0;                // coarse cell size
     double inv_h0;
+    double inv_hf;            // 2^(max_level + 1) / h0: fine-grid coordinates
     double eta0;              // conformal time at the observers (a = 1)
     int32_t n0;               // coarse cells per side (power of two)
     int32_t max_level;
@@ -149,6 +150,8 @@ hipError_t launch_scatter_grad(const float* grad_lib, const int64_t* perm, float
 hipError_t launch_central_transpose(const float* g_lib, const int4* cellpos, const int64_t* perm, float* out,
                                     int n0, double h0, int64_t n, hipStream_t s);
 int cast_occupancy_blocks_per_cu(int block, bool amr);
+hipError_t launch_gather_probe(const void* table, size_t table_bytes, int record_bytes, int in_flight,
+                               int64_t n_waves, int iters, uint32_t seed, float* out, hipStream_t s);
 
 // Morton interleave of three 10-bit coordinates (host and device).
 __host__ __device__ inline uint32_t part1by2(uint32_t x)

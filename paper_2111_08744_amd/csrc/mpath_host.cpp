@@ -174,6 +174,7 @@ GridDev make_griddev(const mpath_grid* g)
     d.dual_ids = g->dual_ids;
     d.h0 = g->box / g->n0;
     d.inv_h0 = g->n0 / g->box;
+    d.inv_hf = std::ldexp(d.inv_h0, g->max_level + 1);
     d.eta0 = g->eta0;
     d.n0 = g->n0;
     d.max_level = g->max_level;
@@ -840,6 +841,26 @@ int mpath_autotune(const mpath_grid* g, const mpath_cast_desc* d, int32_t sample
     tuned->batch = bestc.batch;
     if (best_ms) *best_ms = best;
     return MPATH_OK;
+}
+
+
+int mpath_gather_probe(const void* table, size_t table_bytes, int32_t record_bytes, int32_t in_flight,
+                       int64_t n_waves, int32_t iters, uint32_t seed, float* out, void* stream)
+{
+    if (!table || !out) return fail(MPATH_ERR_INVALID_ARG, "table and out must be device pointers");
+    if (reinterpret_cast<uintptr_t>(table) % 16) return fail(MPATH_ERR_INVALID_ARG, "table must be 16-byte aligned");
+    if (record_bytes != 16 && record_bytes != 64 && record_bytes != 128)
+        return fail(MPATH_ERR_INVALID_ARG, "record_bytes must be 16, 64 or 128");
+    if (table_bytes < (size_t)record_bytes) return fail(MPATH_ERR_INVALID_ARG, "table smaller than one record");
+    if (table_bytes / (size_t)record_bytes > 0xffffffffull)
+        return fail(MPATH_ERR_INVALID_ARG, "at most 2^32 - 1 records");
+    if (in_flight != 1 && in_flight != 2 && in_flight != 4)
+        return fail(MPATH_ERR_INVALID_ARG, "in_flight must be 1, 2 or 4");
+    if (n_waves < 1 || n_waves > (1 << 24)) return fail(MPATH_ERR_INVALID_ARG, "n_waves must be in [1, 2^24]");
+    if (iters < 1) return fail(MPATH_ERR_INVALID_ARG, "iters must be >= 1");
+    const hipError_t e = launch_gather_probe(table, table_bytes, record_bytes, in_flight, n_waves, iters, seed, out,
+                                             static_cast<hipStream_t>(stream));
+    return e ? hip_fail(e, "gather probe launch") : MPATH_OK;
 }
 
 }  // extern "C"

@@ -103,3 +103,20 @@ def test_count_rays(abi):
     cfg = CastConfig([[0, 0, 0], [1, 1, 1]], [0.5, 1.0], 4, pix_first=[0, 10], pix_count=[5, 7])
     assert cfg.n_rays() == 12
     assert CastConfig([0, 0, 0], 0.5, 16).n_rays() == 3072
+
+
+def test_gather_probe_argument_checks(abi):
+    """Every rejected argument returns before any launch (the table pointer
+    here is never dereferenced)."""
+    L = abi.lib()
+    fake = C.c_void_p(1 << 20)
+    out = C.c_void_p(1 << 21)
+    ok = dict(table=fake, nbytes=1 << 16, rec=64, u=4, waves=8, iters=2)
+    cases = [dict(table=None), dict(table=C.c_void_p((1 << 20) + 8)), dict(rec=32), dict(nbytes=32),
+             dict(u=3), dict(waves=0), dict(waves=(1 << 24) + 1), dict(iters=0),
+             dict(nbytes=(1 << 32) * 16, rec=16)]
+    for bad in cases:
+        a = {**ok, **bad}
+        rc = L.mpath_gather_probe(a["table"], a["nbytes"], a["rec"], a["u"], a["waves"], a["iters"], 1, out, None)
+        assert rc == abi.MPATH_ERR_INVALID_ARG, (bad, L.mpath_last_error())
+    assert L.mpath_gather_probe(fake, 1 << 16, 64, 4, 8, 2, 1, None, None) == abi.MPATH_ERR_INVALID_ARG
