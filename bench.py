@@ -213,6 +213,32 @@ def measure_batched(M, torch, dev):
             "speedup_vs_one_cone_per_launch": t_cones / t_one}
 
 
+def measure_lensing(M, torch, dev):
+    """Lensing products on the 64^3 uniform grid: 196,608 rays (nside 128, full
+    sky) to z = 1, 10 steps per cell.  Plain cast, cast with the
+    infinitesimal-beam matrix, finite beam (five rays per beam, one launch)
+    and the kappa/gamma/omega/mu decomposition of the matrices."""
+    import synth
+    grid = M.Grid(synth.make_cells("gauss64"), (0.3, 0.7, 0.7), device=dev)
+    cfg = M.CastConfig([250.0, 250.0, 250.0], 1.0, 128, steps_per_cell=10, schedule=1)
+    n = cfg.n_rays()
+    out = M.alloc_outputs(n, dev)
+    t_plain = _time_ms(torch, lambda: M.cast(grid, cfg, out, out.get("_ws")))
+    inf = {}
+    t_inf = _time_ms(torch, lambda: inf.update(M.infinitesimal_beam(grid, cfg, ws=inf.get("_ws"))))
+    fb = {}
+    t_fb = _time_ms(torch, lambda: fb.update(M.finite_beam(grid, cfg, 1e-3, ws=fb.get("_ws"))))
+    maps = {}
+    t_maps = _time_ms(torch, lambda: maps.update(m=M.lensing_maps(inf["A"])))
+    kap = maps["m"][:, 0]
+    log(f"[bench] lensing ({n} rays): cast {t_plain:.2f} ms, infinitesimal beam {t_inf:.2f} ms, "
+        f"finite beam {t_fb:.2f} ms, maps {t_maps:.3f} ms; kappa rms {float(kap.std()):.3e}")
+    return {"workload": "196608 rays (nside 128) to z = 1 on the uniform 64^3 grid, 10 steps per cell",
+            "rays": n, "cast_ms": t_plain, "infinitesimal_beam_ms": t_inf, "finite_beam_ms": t_fb,
+            "finite_beam_eps": 1e-3, "lensing_maps_ms": t_maps,
+            "infinitesimal_beam_rays_per_s": n / (t_inf / 1e3), "finite_beam_rays_per_s": n / (t_fb / 1e3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,7 +372,8 @@ def main():
             "algorithmic_bytes_per_ray_step": ALGO_BYTES_PER_RAY_STEP.get(w.name),
         }
     if not args.no_secondary:
-        sec = {"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev)}
+        sec = {"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev),
+               "lensing": measure_lensing(M, torch, dev)}
         res["secondary"] = sec
         res["adjoint_forward_ratio"] = sec["adjoint"]["adjoint_forward_ratio"]
     if not args.no_cpu_baseline:

@@ -172,6 +172,13 @@ typedef struct {
        (ds_min the smallest comoving step length), rounded up to a multiple
        of K; a ray that would need more ends with MPATH_RAY_MAX_STEPS. */
     int32_t checkpoint_every;
+    /* initial directions: NULL = the NESTED pixel centres above; else a
+       DEVICE array [n_rays][3] of unit vectors (norm 1 to rounding), ray r
+       starting along dirs[r].  With dirs, pix_first is ignored (may be NULL)
+       and pix_count[j] (NULL: 12 nside^2 each) is the number of rays of
+       observer j.  The array is read during the call (copied to the
+       workspace before the integration starts). */
+    const double* dirs;
 } mpath_cast_desc;
 
 /* Per-ray outputs: caller-allocated DEVICE arrays of length n_rays
@@ -282,6 +289,122 @@ int mpath_autotune(const mpath_grid* grid, const mpath_cast_desc* desc, int32_t 
 
 /* Number of rays a desc describes. */
 int mpath_cast_count_rays(const mpath_cast_desc* desc, int64_t* n_rays);
+
+/* ---- weak-lensing products (Sect. 2.3) ----
+ *
+ * Distortion matrices A (2x2, row-major A[a][b] = A_ab, screen basis
+ * e1 = e_phi, e2 = -e_theta: at the initial direction on the theta side, at
+ * the end point on the beta side) are those of mpath_adjoint (jac), of
+ * mpath_finite_beam, or any other source. */
+
+/* mpath_lensing_maps: convergence, shear, rotation and magnification of n
+ * distortion matrices, inverting the decomposition of Sect. 2.3,
+ *   A = R(omega) [[1 - kappa - g1, -g2], [-g2, 1 - kappa + g1]]:
+ *   tan omega = (A21 - A12) / (A11 + A22),
+ *   1 - kappa = |(A11 + A22, A21 - A12)| / 2,
+ *   S = R(-omega) A, g1 = (S22 - S11) / 2, g2 = -(S12 + S21) / 2,
+ *   mu = 1 / det A  (computed in FP64).
+ *   A:   DEVICE float[n][2][2];  out: DEVICE float[n][5] =
+ *        (kappa, gamma1, gamma2, omega, mu), written.
+ * Asynchronous on the stream.  Errors: INVALID_ARG (n < 0, NULL pointers
+ * with n > 0), DEVICE. */
+int mpath_lensing_maps(const float* A, int64_t n, float* out, void* stream);
+
+/* mpath_finite_beam: finite-beam distortion matrix (Sect. 2.3.2) of every ray
+ * of desc.  Around each reference direction n four more rays start along
+ * n + tan(eps) e1 (A), n - tan(eps) e1 (B), n - tan(eps) e2 (C) and
+ * n + tan(eps) e2 (D), normalised, with (e1, e2) the screen basis at n; all
+ * five are cast in one launch to the reference ray's stop surface, and
+ *   A-hat = [[(r_A - r_B).f1, (r_D - r_C).f1], [(r_A - r_B).f2, (r_D - r_C).f2]]
+ *           / (2 chi_0 tan(eps)),
+ * with r = x_s - x_obs, chi_0 = |r_ref| and (f1, f2) the screen basis at
+ * r_ref.  The second column is taken as (r_D - r_C), the sign that makes
+ * A-hat the identity without lensing (the printed formula's opposite sign
+ * gives -1 there).
+ *   desc:   as for mpath_cast (checkpoint_every ignored); eps in (0, 0.1] rad.
+ *   A:      DEVICE float[n_rays][2][2], written (NaN where a ray of the beam
+ *           did not reach the source).
+ *   status: DEVICE int32[n_rays] or NULL: first non-zero MPATH_RAY_* of the
+ *           reference, A, B, C, D rays (0 when all five reached the source).
+ *   dev_ws: mpath_finite_beam_workspace_bytes bytes (the five-ray cast).
+ * Synchronises the stream once (table upload); the rest is asynchronous.
+ * Errors: as mpath_cast, INVALID_ARG for eps. */
+int mpath_finite_beam_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* desc, size_t* bytes);
+int mpath_finite_beam(const mpath_grid* grid, const mpath_cast_desc* desc, double eps, float* A, int32_t* status,
+                      void* dev_ws, size_t ws_bytes, void* stream);
+
+/* mpath_infinitesimal_beam: a cast (as mpath_cast, same outputs, static
+ * schedule, no checkpoints) that also integrates the infinitesimal-beam
+ * distortion matrix of every ray (Sect. 2.3.1):
+ *   A_ab = delta_ab - 2 int_0^chi_s (chi_s - chi) chi / chi_s T_ab dchi,
+ *   T_ab = e_a . H e_b, H_ij = (G_j(x + h e_i) - G_j(x - h e_i)) / (2 h)
+ * (the finite-difference Hessian of the interpolated force, mixed terms
+ * symmetrised, derivation step h = the size of the leaf cell holding x),
+ * (e_1, e_2) = (e_phi, -e_theta) at the direction of x - x_obs, sampled at
+ * every step start and at the end point, trapezoid rule in chi.  A probe
+ * outside a non-periodic box contributes a zero row of H.
+ *   A: DEVICE float[n_rays][2][2] (symmetric), written; NaN for rays that
+ *      did not reach the source.
+ *   dev_ws: mpath_cast_workspace_bytes of desc.
+ * Errors: as mpath_cast; INVALID_ARG when checkpoint_every != 0. */
+int mpath_infinitesimal_beam(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observables* out, float* A,
+                             void* dev_ws, size_t ws_bytes, void* stream);
+
+/* ---- geodesic finder and relativistic catalogues (Sect. 2.5) ----
+ *
+ * For a source at comoving position x_src the comoving angular position
+ * beta is the direction of x_src - x_obs and chi = |x_src - x_obs| its
+ * distance (unwrapped: on a periodic grid the box is replicated).  The
+ * finder seeks the initial direction theta whose photon, stopped on the
+ * source's light-cone surface eta_s = eta_0 - chi, arrives in the direction
+ * beta, by the Newton iteration theta_{i+1} = theta_i - A^-1 (beta_i - beta):
+ * residual d_a = f_a(beta_i) . beta on the screen basis (f1, f2) at beta_i,
+ * A dtheta = d solved, theta moved by dtheta along its own screen basis
+ * (e1, e2) = (e_phi, -e_theta) and normalised.  The first identity_iters
+ * iterations take A = I (plain casts, as the paper does), later ones the
+ * exact distortion matrix of mpath_adjoint (a checkpointed cast and a
+ * Jacobian sweep).  A source stops iterating when the angle between beta_i
+ * and beta is below tol.  At the end every source is cast once more along
+ * its theta (checkpointed) and, when requested, its exact A and dz5/dtheta
+ * are computed there. */
+typedef struct {
+    const double* obs_pos;      /* HOST [3] observer position                            */
+    int64_t n_src;
+    const double* src_pos;      /* HOST [n_src][3] comoving source positions             */
+    int32_t order;              /* 1 = CIC                                               */
+    int32_t steps_per_cell;     /* as mpath_cast_desc                                     */
+    int32_t adaptive;
+    int64_t max_steps;
+    double tol;                 /* convergence angle (rad), > 0                           */
+    int32_t max_iter;           /* Newton iterations, >= 1                                */
+    int32_t identity_iters;     /* iterations with A = I before the exact Jacobian, >= 0 */
+    int32_t checkpoint_every;   /* K of the Jacobian sweeps, >= 1                         */
+} mpath_finder_desc;
+
+/* DEVICE outputs, arrays of n_src; theta is required, the others may be NULL. */
+typedef struct {
+    double* theta;              /* [n][3] initial direction found (unit)                           */
+    float* A;                   /* [n][2][2] exact distortion matrix d beta / d theta at theta     */
+    float* dz_dtheta;           /* [n][2] d z5 / d theta on (e1, e2) at theta                       */
+    double* z5;                 /* observed redshift (Sect. 2.5, v = 0)                             */
+    double* z0;                 /* FLRW redshift of the source's surface                            */
+    float* phi_src;             /* Phi at the end point                                             */
+    double* sep;                /* angle between the final end direction and beta (rad)             */
+    int32_t* n_iter;            /* iteration of convergence (0: the first cast); -1 not converged
+                                   within max_iter; -2 a cast did not reach the source              */
+    int32_t* status;            /* MPATH_RAY_* of the final cast                                    */
+} mpath_finder_out;
+
+/* Workspace: the checkpointed cast and Jacobian sweep of n_src rays plus
+ * per-source tables (88 bytes per source). */
+int mpath_find_geodesics_workspace_bytes(const mpath_grid* grid, const mpath_finder_desc* desc, size_t* bytes);
+/* Synchronises the stream once per iteration (the count of sources still
+ * iterating decides whether to continue).  Errors: INVALID_ARG (NULL
+ * arrays, tol <= 0, max_iter < 1, identity_iters < 0, checkpoint_every < 1,
+ * a source at the observer), UNSUPPORTED (order != 1, a source beyond the
+ * background table, z > 20), WORKSPACE_TOO_SMALL, DEVICE. */
+int mpath_find_geodesics(const mpath_grid* grid, const mpath_finder_desc* desc, mpath_finder_out* out,
+                         void* dev_ws, size_t ws_bytes, void* stream);
 
 /* ---- measurement utility (not a step of the method) ----
  *

@@ -25,6 +25,7 @@ from ._abi import (MPATH_RAY_LEFT_DOMAIN, MPATH_RAY_MAX_STEPS, MPATH_RAY_NONFINI
                    MPATH_SCHED_STATIC, MPATH_STOP_CHI, MPATH_STOP_REDSHIFT, MpathError)
 
 __all__ = ["Grid", "cast", "CastConfig", "adjoint", "autotune", "cast_differentiable", "library_path",
+           "lensing_maps", "finite_beam", "infinitesimal_beam", "find_geodesics",
            "MpathError"]
 
 
@@ -129,7 +130,7 @@ class CastConfig:
 
     def __init__(self, obs, stop, nside, pix_first=None, pix_count=None, stop_kind="z",
                  steps_per_cell=10, adaptive=False, max_steps=1 << 40, schedule=0,
-                 block_size=0, waves_per_cu=0, batch=0, checkpoint_every=0):
+                 block_size=0, waves_per_cu=0, batch=0, checkpoint_every=0, dirs=None):
         self.obs = np.ascontiguousarray(np.atleast_2d(obs), np.float64)
         self.stop = np.ascontiguousarray(np.atleast_1d(stop), np.float64)
         self.nside = int(nside)
@@ -145,6 +146,13 @@ class CastConfig:
         self.waves_per_cu = int(waves_per_cu)
         self.batch = int(batch)
         self.checkpoint_every = int(checkpoint_every)
+        # initial directions: None = NESTED pixel centres; else a float64 CUDA
+        # tensor [n_rays, 3] of unit vectors (pix_count gives the rays per observer)
+        if dirs is not None:
+            if not (dirs.is_cuda and dirs.dtype == _torch().float64 and dirs.dim() == 2 and dirs.shape[1] == 3):
+                raise ValueError("dirs must be a float64 CUDA tensor of shape [n_rays, 3]")
+            dirs = dirs.contiguous()
+        self.dirs = dirs
 
     def desc(self) -> _abi.mpath_cast_desc:
         d = _abi.mpath_cast_desc()
@@ -164,6 +172,7 @@ class CastConfig:
         d.waves_per_cu = self.waves_per_cu
         d.batch = self.batch
         d.checkpoint_every = self.checkpoint_every
+        d.dirs = self.dirs.data_ptr() if self.dirs is not None else None
         return d
 
     def n_rays(self) -> int:
@@ -205,6 +214,8 @@ def cast(grid: Grid, cfg: CastConfig, out=None, ws=None):
     L = _abi.lib()
     d = cfg.desc()
     n = cfg.n_rays()
+    if cfg.dirs is not None and cfg.dirs.shape[0] != n:
+        raise ValueError(f"dirs has {cfg.dirs.shape[0]} rows for {n} rays")
     if out is None:
         out = alloc_outputs(n, grid.device)
     nbytes = C.c_size_t()
@@ -341,3 +352,113 @@ def autotune(grid: Grid, cfg: CastConfig, sample_div: int = 8):
     out.waves_per_cu = tuned.waves_per_cu
     out.batch = tuned.batch
     return out, ms.value
+
+
+def lensing_maps(A):
+    """mpath_lensing_maps: (kappa, gamma1, gamma2, omega, mu) [n, 5] float32 of
+    distortion matrices A [n, 2, 2] (float32 CUDA tensor)."""
+    torch = _torch()
+    if not (A.is_cuda and A.dtype == torch.float32 and A.dim() == 3 and tuple(A.shape[1:]) == (2, 2)):
+        raise ValueError("A must be a float32 CUDA tensor of shape [n, 2, 2]")
+    A = A.contiguous()
+    out = torch.empty((A.shape[0], 5), dtype=torch.float32, device=A.device)
+    with torch.cuda.device(A.device):
+        _abi.check(_abi.lib().mpath_lensing_maps(_ptr(A), A.shape[0], _ptr(out), _stream_ptr(A.device)),
+                   "mpath_lensing_maps")
+    return out
+
+
+def finite_beam(grid: Grid, cfg: CastConfig, eps: float, ws=None):
+    """mpath_finite_beam: finite-beam distortion matrices [n_rays, 2, 2] and the
+    beam status [n_rays] of every ray of cfg, beams of semi-aperture eps (rad)."""
+    torch = _torch()
+    L = _abi.lib()
+    d = cfg.desc()
+    n = cfg.n_rays()
+    if cfg.dirs is not None and cfg.dirs.shape[0] != n:
+        raise ValueError(f"dirs has {cfg.dirs.shape[0]} rows for {n} rays")
+    nbytes = C.c_size_t()
+    _abi.check(L.mpath_finite_beam_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)),
+               "mpath_finite_beam_workspace_bytes")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=grid.device)
+    A = torch.empty((n, 2, 2), dtype=torch.float32, device=grid.device)
+    st = torch.empty((n,), dtype=torch.int32, device=grid.device)
+    with torch.cuda.device(grid.device):
+        _abi.check(L.mpath_finite_beam(grid.handle, C.byref(d), float(eps), _ptr(A), _ptr(st), _ptr(ws),
+                                       ws.numel(), _stream_ptr(grid.device)), "mpath_finite_beam")
+    return {"A": A, "status": st, "_ws": ws}
+
+
+def infinitesimal_beam(grid: Grid, cfg: CastConfig, out=None, ws=None):
+    """mpath_infinitesimal_beam: cast every ray of cfg (outputs as ``cast``) and
+    integrate its infinitesimal-beam distortion matrix, returned as ``A``
+    [n_rays, 2, 2] float32 (NaN for rays that did not reach the source)."""
+    torch = _torch()
+    L = _abi.lib()
+    d = cfg.desc()
+    n = cfg.n_rays()
+    if cfg.dirs is not None and cfg.dirs.shape[0] != n:
+        raise ValueError(f"dirs has {cfg.dirs.shape[0]} rows for {n} rays")
+    if out is None:
+        out = alloc_outputs(n, grid.device)
+    nbytes = C.c_size_t()
+    _abi.check(L.mpath_cast_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)), "mpath_cast_workspace_bytes")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=grid.device)
+    A = torch.empty((n, 2, 2), dtype=torch.float32, device=grid.device)
+    obs = observables_struct(out)
+    with torch.cuda.device(grid.device):
+        _abi.check(L.mpath_infinitesimal_beam(grid.handle, C.byref(d), C.byref(obs), _ptr(A), _ptr(ws), ws.numel(),
+                                              _stream_ptr(grid.device)), "mpath_infinitesimal_beam")
+    out["A"] = A
+    out["_ws"] = ws
+    return out
+
+
+def find_geodesics(grid: Grid, obs, src, steps_per_cell=10, adaptive=False, tol=1e-10, max_iter=10,
+                   identity_iters=3, checkpoint_every=32, max_steps=1 << 40, ws=None):
+    """mpath_find_geodesics: initial directions theta [n, 3] connecting the
+    observer obs [3] to sources at comoving positions src [n, 3] (host
+    arrays), with the exact distortion matrix A [n, 2, 2], dz5/dtheta [n, 2],
+    z5, z0, phi_src, the final angle sep to beta, n_iter and the status."""
+    torch = _torch()
+    L = _abi.lib()
+    obs = np.ascontiguousarray(obs, np.float64).reshape(3)
+    src = np.ascontiguousarray(src, np.float64).reshape(-1, 3)
+    n = src.shape[0]
+    d = _abi.mpath_finder_desc()
+    d.obs_pos = obs.ctypes.data
+    d.n_src = n
+    d.src_pos = src.ctypes.data if n else None
+    d.order = 1
+    d.steps_per_cell = int(steps_per_cell)
+    d.adaptive = int(bool(adaptive))
+    d.max_steps = int(max_steps)
+    d.tol = float(tol)
+    d.max_iter = int(max_iter)
+    d.identity_iters = int(identity_iters)
+    d.checkpoint_every = int(checkpoint_every)
+    nbytes = C.c_size_t()
+    _abi.check(L.mpath_find_geodesics_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)),
+               "mpath_find_geodesics_workspace_bytes")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=grid.device)
+    dev = grid.device
+    res = {"theta": torch.empty((n, 3), dtype=torch.float64, device=dev),
+           "A": torch.empty((n, 2, 2), dtype=torch.float32, device=dev),
+           "dz_dtheta": torch.empty((n, 2), dtype=torch.float32, device=dev),
+           "z5": torch.empty((n,), dtype=torch.float64, device=dev),
+           "z0": torch.empty((n,), dtype=torch.float64, device=dev),
+           "phi_src": torch.empty((n,), dtype=torch.float32, device=dev),
+           "sep": torch.empty((n,), dtype=torch.float64, device=dev),
+           "n_iter": torch.empty((n,), dtype=torch.int32, device=dev),
+           "status": torch.empty((n,), dtype=torch.int32, device=dev)}
+    o = _abi.mpath_finder_out()
+    for k, v in res.items():
+        setattr(o, k, v.data_ptr() if n else None)
+    with torch.cuda.device(dev):
+        _abi.check(L.mpath_find_geodesics(grid.handle, C.byref(d), C.byref(o), _ptr(ws), ws.numel(),
+                                          _stream_ptr(dev)), "mpath_find_geodesics")
+    res["_ws"] = ws
+    return res

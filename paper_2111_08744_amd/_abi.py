@@ -55,7 +55,7 @@ class mpath_cast_desc(C.Structure):
                 ("pix_count", C.c_void_p), ("order", C.c_int32), ("steps_per_cell", C.c_int32),
                 ("adaptive", C.c_int32), ("max_steps", C.c_int64), ("schedule", C.c_int32),
                 ("block_size", C.c_int32), ("waves_per_cu", C.c_int32), ("batch", C.c_int32),
-                ("checkpoint_every", C.c_int32)]
+                ("checkpoint_every", C.c_int32), ("dirs", C.c_void_p)]
 
 
 class mpath_observables(C.Structure):
@@ -68,6 +68,19 @@ class mpath_adjoint_desc(C.Structure):
     _fields_ = [("dL_dalpha", C.c_void_p), ("dL_dz", C.c_void_p), ("jac", C.c_void_p),
                 ("dz_dtheta", C.c_void_p), ("dL_dvalues", C.c_void_p), ("dL_dphi_total", C.c_void_p),
                 ("ray_status", C.c_void_p)]
+
+
+class mpath_finder_desc(C.Structure):
+    _fields_ = [("obs_pos", C.c_void_p), ("n_src", C.c_int64), ("src_pos", C.c_void_p), ("order", C.c_int32),
+                ("steps_per_cell", C.c_int32), ("adaptive", C.c_int32), ("max_steps", C.c_int64),
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("identity_iters", C.c_int32),
+                ("checkpoint_every", C.c_int32)]
+
+
+class mpath_finder_out(C.Structure):
+    _fields_ = [("theta", C.c_void_p), ("A", C.c_void_p), ("dz_dtheta", C.c_void_p), ("z5", C.c_void_p),
+                ("z0", C.c_void_p), ("phi_src", C.c_void_p), ("sep", C.c_void_p), ("n_iter", C.c_void_p),
+                ("status", C.c_void_p)]
 
 
 _lib = None
@@ -95,6 +108,12 @@ def lib():
         L.mpath_autotune_workspace_bytes.argtypes = [vp, P(mpath_cast_desc), C.c_int32, P(sz)]
         L.mpath_autotune.argtypes = [vp, P(mpath_cast_desc), C.c_int32, vp, sz, vp, P(mpath_cast_desc),
                                      P(C.c_float)]
+        L.mpath_lensing_maps.argtypes = [vp, C.c_int64, vp, vp]
+        L.mpath_finite_beam_workspace_bytes.argtypes = [vp, P(mpath_cast_desc), P(sz)]
+        L.mpath_finite_beam.argtypes = [vp, P(mpath_cast_desc), C.c_double, vp, vp, vp, sz, vp]
+        L.mpath_infinitesimal_beam.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp, vp, sz, vp]
+        L.mpath_find_geodesics_workspace_bytes.argtypes = [vp, P(mpath_finder_desc), P(sz)]
+        L.mpath_find_geodesics.argtypes = [vp, P(mpath_finder_desc), P(mpath_finder_out), vp, sz, vp]
         L.mpath_gather_probe.argtypes = [vp, sz, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_uint32, vp, vp]
         L.mpath_status_string.restype = C.c_char_p
         L.mpath_status_string.argtypes = [C.c_int]
@@ -103,7 +122,9 @@ def lib():
         for name in ("mpath_grid_workspace_bytes", "mpath_grid_build", "mpath_grid_free",
                      "mpath_grid_get_info", "mpath_grid_set_values", "mpath_cast_workspace_bytes",
                      "mpath_cast", "mpath_cast_count_rays", "mpath_adjoint_workspace_bytes",
-                     "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune", "mpath_gather_probe"):
+                     "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune", "mpath_gather_probe",
+                     "mpath_lensing_maps", "mpath_finite_beam_workspace_bytes", "mpath_finite_beam",
+                     "mpath_infinitesimal_beam", "mpath_find_geodesics_workspace_bytes", "mpath_find_geodesics"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmpath.so")
-SOURCES = ["mpath_host.cpp", "grid.hip", "cast.hip", "adjoint.hip", "probe.hip"]
+SOURCES = ["mpath_host.cpp", "grid.hip", "cast.hip", "adjoint.hip", "lensing.hip", "finder.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -775,9 +775,10 @@ __device__ __forceinline__ void end_cotangents(const AdjointArgs& A, const RayCt
     double f1[3], f2[3];
     screen_basis(rh, f1, f2);
     const double phis = Jf.phi;
-    const double dz_dK = ob.a_s * (1.0 + phis) / (1.0 + phio);
-    const double dz_dphis = ob.a_s * yf.K / (1.0 + phio);
-    const double dz_dphio = -ob.a_s * yf.K * (1.0 + phis) / ((1.0 + phio) * (1.0 + phio));
+    const double a_s = A.c.ray_stop ? A.c.ray_stop[ray].y : ob.a_s;
+    const double dz_dK = a_s * (1.0 + phis) / (1.0 + phio);
+    const double dz_dphis = a_s * yf.K / (1.0 + phio);
+    const double dz_dphio = -a_s * yf.K * (1.0 + phis) / ((1.0 + phio) * (1.0 + phio));
 #pragma unroll
     for (int c = 0; c < W; ++c) phys_zero(yb[c]);
     if (HAS_JAC) {
@@ -877,7 +878,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
         R.geo.vo[i] = ldexp(ob.x[i] / g.h0, g.max_level + 1);
         R.geo.n[i] = a.dirs[3 * ray + i];
     }
-    const double eta_s = ob.eta_s;
+    const double eta_s = a.ray_stop ? a.ray_stop[ray].x : ob.eta_s;
     FieldCache<AMR> F;
     F.bind(lds + threadIdx.x);
     F.reset();

@@ -25,6 +25,11 @@ constexpr int kWave = 64;
 // workload: 3 waves 102.6 ms, 4 waves 89.5 ms per cast).
 constexpr int kMinWavesPerSimd = 4;
 
+// Step-start hook of RayRun::advance that does nothing (plain casts).
+struct NoSample {
+    __device__ __forceinline__ void at_step(const CastArgs&, const RayGeom&, const GeoState&, int) {}
+};
+
 // Everything one lane carries for its current ray.
 template <bool AMR>
 struct RayRun {
@@ -38,6 +43,13 @@ struct RayRun {
     int status;           // -1 while running
     FieldCache<AMR> F;
 
+    template <bool CKPT = false>
+    __device__ __forceinline__ bool advance(const CastArgs& a, int max_iter)
+    {
+        NoSample none;
+        return advance<CKPT, NoSample>(a, max_iter, none);
+    }
+
     __device__ __forceinline__ void start(const CastArgs& a, int64_t r)
     {
         ray = r;
@@ -50,7 +62,7 @@ struct RayRun {
         geo.n[0] = a.dirs[3 * r];
         geo.n[1] = a.dirs[3 * r + 1];
         geo.n[2] = a.dirs[3 * r + 2];
-        eta_s = ob.eta_s;
+        eta_s = a.ray_stop ? a.ray_stop[r].x : ob.eta_s;
         F.reset();
         n_steps = 0;
         hash = kFnvOffset;
@@ -75,8 +87,10 @@ struct RayRun {
 
     // Advance by at most max_iter steps; returns true when the ray is done.
     // With CKPT the state before every K-th step is stored for the adjoint.
-    template <bool CKPT = false>
-    __device__ __forceinline__ bool advance(const CastArgs& a, int max_iter)
+    // smp.at_step(y, L) sees the state at every step start (after the leaf
+    // level L there is known, before the step is taken).
+    template <bool CKPT = false, class Smp = NoSample>
+    __device__ __forceinline__ bool advance(const CastArgs& a, int max_iter, Smp& smp)
     {
         if (status >= 0) return true;
         const GridDev& g = a.grid;
@@ -93,6 +107,7 @@ struct RayRun {
             const int L = F.leaf(g, I);
             if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
             hash = fnv(hash, (uint32_t)L);
+            smp.at_step(a, geo, y, L);
             const double ds = a.ds_level[L];
             const double dl = ds / y.K;
             // landing on the iso-eta surface: Newton on eta_RK4(dl) = eta_s
@@ -137,10 +152,10 @@ struct RayRun {
         if (F.eval(a.grid, v, phi_s, G, leafl, l)) phi_s = __builtin_nanf("");
         const OutDev& o = a.out;
         const bool ok = status == MPATH_RAY_REACHED;
+        const double a_s = a.ray_stop ? a.ray_stop[ray].y : ob.a_s;
         if (o.z5)
-            o.z5[ray] = ok ? ob.a_s * y.K * (1.0 + (double)phi_s) / (1.0 + (double)phi_o) - 1.0
-                           : __builtin_nan("");
-        if (o.z0) o.z0[ray] = ok ? ob.z0 : __builtin_nan("");
+            o.z5[ray] = ok ? a_s * y.K * (1.0 + (double)phi_s) / (1.0 + (double)phi_o) - 1.0 : __builtin_nan("");
+        if (o.z0) o.z0[ray] = ok ? (a.ray_stop ? 1.0 / a_s - 1.0 : ob.z0) : __builtin_nan("");
         if (o.phi_src) o.phi_src[ray] = phi_s;
         if (o.n_steps) o.n_steps[ray] = (int32_t)n_steps;
         if (o.status) o.status[ray] = status;
@@ -274,6 +289,141 @@ __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_persistent_kern
     }
 }
 
+// Infinitesimal-beam distortion matrix (Sect. 2.3.1): along the path,
+//   A_ab = delta_ab - 2 int_0^chi_s (chi_s - chi) chi / chi_s T_ab dchi,
+// T_ab = e_a . H e_b with H the Hessian of Phi from centred differences of
+// the interpolated gradient, H_ij = (G_j(x + h e_i) - G_j(x - h e_i)) / 2h
+// (mixed derivatives symmetrised), h the size of the leaf cell holding x,
+// and (e_1, e_2) = (e_phi, -e_theta) at the direction of x - x_obs.  The
+// integrand is sampled at every step start and at the end point and
+// integrated by the trapezoid rule in chi; with w = chi - chi^2 / chi_s the
+// two sums int chi T and int chi^2 T are carried so that chi_s is needed only
+// at the end.  The field at the probe points comes from a second stencil
+// cache so that the integration's own cache is left in place.
+template <bool AMR>
+struct InfBeam {
+    FieldCache<AMR> P;
+    double chi_p, Tp[3];         // previous sample (T11, T12, T22)
+    double J1[3], J2[3];         // trapezoid sums of chi T and chi^2 T
+    int n;
+
+    __device__ __forceinline__ void init(float* lds)
+    {
+        P.bind(lds);
+        P.reset();
+        n = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) J1[k] = J2[k] = 0.0;
+    }
+
+    __device__ __forceinline__ void at_step(const CastArgs& a, const RayGeom& geo, const GeoState& y, int L)
+    {
+        const GridDev& g = a.grid;
+        double v[3];
+        grid_coords(g, geo, y.eta, y.dx, v);
+        const double s = g.eta0 - y.eta;
+        double r[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[i] = s * geo.n[i] + (double)y.dx[i];
+        const double chi = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        const double* dir = chi > 0.0 ? r : geo.n;
+        const double rho = hypot(dir[0], dir[1]);
+        const double rr = sqrt(rho * rho + dir[2] * dir[2]);
+        const double cp = rho > 0.0 ? dir[0] / rho : 1.0, sp = rho > 0.0 ? dir[1] / rho : 0.0;
+        const double ct = dir[2] / rr, st = rho / rr;
+        const double e[2][3] = {{-sp, cp, 0.0}, {-cp * ct, -sp * ct, st}};
+        // h = h0 / 2^L; in fine-grid units 2^(max_level + 1 - L), exact
+        const double h = ldexp(g.h0, -L);
+        const double hf = ldexp(1.0, g.max_level + 1 - L);
+        double H[3][3];
+#pragma unroll 1
+        for (int i = 0; i < 3; ++i) {
+            double vp[3] = {v[0], v[1], v[2]}, vm[3] = {v[0], v[1], v[2]};
+            vp[i] += hf;
+            vm[i] -= hf;
+            float php, phm, gp[3], gm[3];
+            int l0, l1;
+            const bool bad = P.eval(g, vp, php, gp, l0, l1) != 0 || P.eval(g, vm, phm, gm, l0, l1) != 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) H[i][j] = bad ? 0.0 : ((double)gp[j] - (double)gm[j]) / (2.0 * h);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 3; ++j) {
+                const double m = 0.5 * (H[i][j] + H[j][i]);
+                H[i][j] = H[j][i] = m;
+            }
+        double T[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int a0 = k == 2 ? 1 : 0, b0 = k == 0 ? 0 : 1;
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) acc += e[a0][i] * H[i][j] * e[b0][j];
+            T[k] = acc;
+        }
+        if (n > 0) {
+            const double dc = 0.5 * (chi - chi_p);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                J1[k] += dc * (chi_p * Tp[k] + chi * T[k]);
+                J2[k] += dc * (chi_p * chi_p * Tp[k] + chi * chi * T[k]);
+            }
+        }
+        chi_p = chi;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Tp[k] = T[k];
+        ++n;
+    }
+
+    // A at the end of a ray that reached the source (after the end-point
+    // sample); NaN otherwise or without two samples.
+    __device__ __forceinline__ void write(float* A, bool reached) const
+    {
+        if (!reached || n < 2) {
+            A[0] = A[1] = A[2] = A[3] = __builtin_nanf("");
+            return;
+        }
+        const double cs = chi_p;
+        const double I11 = J1[0] - J2[0] / cs, I12 = J1[1] - J2[1] / cs, I22 = J1[2] - J2[2] / cs;
+        A[0] = (float)(1.0 - 2.0 * I11);
+        A[1] = (float)(-2.0 * I12);
+        A[2] = (float)(-2.0 * I12);
+        A[3] = (float)(1.0 - 2.0 * I22);
+    }
+};
+
+// One lane per ray: the static cast with the infinitesimal-beam samples
+// (two stencil caches in LDS, so fewer resident waves than the plain cast).
+template <bool AMR>
+__global__ __launch_bounds__(kBlock, 2) void cast_infbeam_kernel(CastArgs a, float* A)
+{
+    extern __shared__ float coef_lds[];
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    RayRun<AMR> R;
+    R.F.bind(coef_lds + threadIdx.x);
+    InfBeam<AMR> B;
+    B.init(coef_lds + 32 * kBlock + threadIdx.x);
+    R.start(a, r);
+    R.template advance<false, InfBeam<AMR>>(a, 0x7fffffff, B);
+    const bool reached = R.status == MPATH_RAY_REACHED;
+    if (reached) {
+        // end-point sample: leaf level of the end point
+        double v[3];
+        grid_coords(a.grid, R.geo, R.y.eta, R.y.dx, v);
+        float ph, G[3];
+        int L, l;
+        B.P.eval(a.grid, v, ph, G, L, l);       // sets L (-1 outside a non-periodic box)
+        B.at_step(a, R.geo, R.y, L < 0 ? 0 : L);
+    }
+    B.write(A + 4 * r, reached);
+    R.finish(a);
+}
+
 __global__ void zero_u64(unsigned long long* p) { *p = 0ull; }
 
 __global__ void permute_values_kernel(float4* payload, const int64_t* perm, const float4* values, int64_t n)
@@ -305,6 +455,18 @@ hipError_t launch_cast_checkpointed(const CastArgs& a, hipStream_t s)
         hipLaunchKernelGGL(cast_ckpt_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
     else
         hipLaunchKernelGGL(cast_ckpt_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_infbeam(const CastArgs& a, float* A, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
+    const size_t lds = (size_t)64 * kBlock * sizeof(float);
+    if (a.grid.max_level > 0)
+        hipLaunchKernelGGL(cast_infbeam_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, A);
+    else
+        hipLaunchKernelGGL(cast_infbeam_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, A);
     return hipGetLastError();
 }
 

@@ -109,6 +109,8 @@ struct CastArgs {
     GeoState* ckpt;              // [slots][n_rays] state before steps 0, K, 2K, ... (adjoint)
     int32_t ckpt_every;          // K (0: no checkpoints)
     int32_t ckpt_slots;
+    const double2* ray_stop;     // [n_rays] (eta_s, a_s) of each ray's own stop surface, or
+                                 // NULL: the observer's (geodesic finder: one source per ray)
 };
 
 // Reverse-mode (adjoint) arguments.
@@ -134,6 +136,7 @@ hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s);
 hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipStream_t s);
 hipError_t launch_observables(const CastArgs& a, hipStream_t s);
 hipError_t launch_ray_dirs(const CastArgs& a, hipStream_t s);
+hipError_t launch_cast_infbeam(const CastArgs& a, float* A, hipStream_t s);
 hipError_t launch_permute_values(float4* payload, const int64_t* perm, const float4* values,
                                  int64_t n, hipStream_t s);
 // Derived tables (defined in grid.hip); cellpos[c] = (i, j, k, level).
@@ -150,6 +153,24 @@ hipError_t launch_scatter_grad(const float* grad_lib, const int64_t* perm, float
 hipError_t launch_central_transpose(const float* g_lib, const int4* cellpos, const int64_t* perm, float* out,
                                     int n0, double h0, int64_t n, hipStream_t s);
 int cast_occupancy_blocks_per_cu(int block, bool amr);
+// Reference rays of one observer for the finite-beam casts.
+struct BeamObs {
+    int64_t ray_first;   // first reference ray of the observer
+    int64_t pix_first;   // first NESTED pixel (pixel-centre directions)
+    int64_t count;       // reference rays of the observer
+};
+hipError_t launch_lensing_maps(const float* A, int64_t n, float* out, hipStream_t s);
+hipError_t launch_beam_dirs(const BeamObs* obs, int n_obs, int nside, const double* user_dirs, double tan_eps,
+                            int64_t n_rays, double* dirs5, hipStream_t s);
+hipError_t launch_finite_beam(const BeamObs* obs, int n_obs, const RayEnd* ends, const double* dirs5,
+                              const int32_t* status5, double eta0, double tan_eps, int64_t n_rays, float* A,
+                              int32_t* status, hipStream_t s);
+hipError_t launch_finder_update(int64_t n, const RayEnd* ends, const double* target, const int32_t* status,
+                                const float* jac, double eta0, double tol, int it, double* theta, int32_t* n_iter,
+                                double* sep, unsigned int* active, hipStream_t s);
+hipError_t launch_finder_sep(int64_t n, const RayEnd* ends, const double* target, const double* theta,
+                             const int32_t* status, double eta0, double* sep, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gather_probe(const void* table, size_t table_bytes, int record_bytes, int in_flight,
                                int64_t n_waves, int iters, uint32_t seed, float* out, hipStream_t s);
 

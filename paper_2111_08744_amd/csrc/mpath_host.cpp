@@ -449,7 +449,7 @@ int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_ra
     if (d->n_obs < 1) return fail(MPATH_ERR_INVALID_ARG, "n_obs must be >= 1");
     if (!d->obs_pos || !d->stop_value) return fail(MPATH_ERR_INVALID_ARG, "obs_pos or stop_value is NULL");
     if (d->nside < 1 || d->nside > 8192) return fail(MPATH_ERR_INVALID_ARG, "nside must be in [1, 8192]");
-    if ((d->pix_first == nullptr) != (d->pix_count == nullptr))
+    if (!d->dirs && (d->pix_first == nullptr) != (d->pix_count == nullptr))
         return fail(MPATH_ERR_INVALID_ARG, "pix_first and pix_count must both be given or both NULL");
     if (d->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "only order = 1 (CIC) is implemented");
     if (d->steps_per_cell < 1) return fail(MPATH_ERR_INVALID_ARG, "steps_per_cell must be >= 1");
@@ -465,9 +465,10 @@ int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_ra
     const int64_t npix = 12ll * d->nside * d->nside;
     int64_t total = 0;
     for (int j = 0; j < d->n_obs; ++j) {
-        const int64_t f = d->pix_first ? d->pix_first[j] : 0;
+        const int64_t f = (d->pix_first && !d->dirs) ? d->pix_first[j] : 0;
         const int64_t c = d->pix_count ? d->pix_count[j] : npix;
-        if (f < 0 || c < 0 || f + c > npix) return fail(MPATH_ERR_INVALID_ARG, "pixel range outside the sky");
+        if (d->dirs ? c < 0 : (f < 0 || c < 0 || f + c > npix))
+            return fail(MPATH_ERR_INVALID_ARG, d->dirs ? "negative ray count" : "pixel range outside the sky");
         total += c;
     }
     *n_rays = total;
@@ -620,8 +621,14 @@ int mpath_cast_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, si
     return MPATH_OK;
 }
 
-int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* dev_ws,
-               size_t ws_bytes, void* stream)
+}  // extern "C"
+
+namespace {
+
+// mpath_cast, or with inf set the cast that also integrates the
+// infinitesimal-beam distortion matrix into inf_A (static schedule).
+int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* dev_ws,
+              size_t ws_bytes, void* stream, bool inf, float* inf_A, const double2* ray_stop = nullptr)
 {
     int64_t n_rays;
     std::vector<ObsDev> obs;
@@ -640,6 +647,7 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
     if (e) return hip_fail(e, "observer table upload");
 
     CastArgs a = make_cast_args(g, d, lay, ws, n_rays);
+    a.ray_stop = ray_stop;
     a.out.beta = out->beta;
     a.out.alpha = out->alpha;
     a.out.z5 = out->z5;
@@ -650,9 +658,16 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
     a.out.hash = out->hash;
     a.out.chi = out->chi;
 
-    e = launch_ray_dirs(a, s);
-    if (e) return hip_fail(e, "ray directions launch");
-    if (d->checkpoint_every > 0) {
+    if (d->dirs) {
+        e = n_rays ? hipMemcpyAsync(a.dirs, d->dirs, (size_t)n_rays * 24, hipMemcpyDeviceToDevice, s) : hipSuccess;
+        if (e) return hip_fail(e, "ray directions copy");
+    } else {
+        e = launch_ray_dirs(a, s);
+        if (e) return hip_fail(e, "ray directions launch");
+    }
+    if (inf) {
+        e = launch_cast_infbeam(a, inf_A, s);
+    } else if (d->checkpoint_every > 0) {
         e = launch_cast_checkpointed(a, s);
     } else {
         int sched = d->schedule;
@@ -674,6 +689,28 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
     return MPATH_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* dev_ws,
+               size_t ws_bytes, void* stream)
+{
+    return cast_impl(g, d, out, dev_ws, ws_bytes, stream, false, nullptr);
+}
+
+int mpath_infinitesimal_beam(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, float* A,
+                             void* dev_ws, size_t ws_bytes, void* stream)
+{
+    int64_t n_rays;
+    int rc = check_cast_desc(g, d, &n_rays);
+    if (rc) return rc;
+    if (n_rays > 0 && !A) return fail(MPATH_ERR_INVALID_ARG, "A is NULL");
+    if (d->checkpoint_every != 0)
+        return fail(MPATH_ERR_INVALID_ARG, "the infinitesimal-beam cast stores no checkpoints (checkpoint_every 0)");
+    return cast_impl(g, d, out, dev_ws, ws_bytes, stream, true, A);
+}
+
 int mpath_adjoint_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, size_t* bytes)
 {
     if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
@@ -687,9 +724,13 @@ int mpath_adjoint_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d,
     return MPATH_OK;
 }
 
-int mpath_adjoint(const mpath_grid* g, const mpath_cast_desc* d, const mpath_observables* fwd,
-                  const void* cast_ws, size_t cast_ws_bytes, const mpath_adjoint_desc* ad, void* dev_ws,
-                  size_t ws_bytes, void* stream)
+}  // extern "C"
+
+namespace {
+
+int adjoint_impl(const mpath_grid* g, const mpath_cast_desc* d, const mpath_observables* fwd,
+                 const void* cast_ws, size_t cast_ws_bytes, const mpath_adjoint_desc* ad, void* dev_ws,
+                 size_t ws_bytes, void* stream, const double2* ray_stop)
 {
     int64_t n_rays;
     std::vector<ObsDev> obs;
@@ -715,6 +756,7 @@ int mpath_adjoint(const mpath_grid* g, const mpath_cast_desc* d, const mpath_obs
     AdjointArgs A;
     std::memset(&A, 0, sizeof A);
     A.c = make_cast_args(g, d, lay, (char*)cast_ws, n_rays);
+    A.c.ray_stop = ray_stop;
     A.tape = (GeoState*)(ws + al.off_tape);
     A.n_steps = fwd->n_steps;
     A.status = fwd->status;
@@ -736,6 +778,17 @@ int mpath_adjoint(const mpath_grid* g, const mpath_cast_desc* d, const mpath_obs
                                      g->box / g->n0, g->n_cells, s);
     if (e) return hip_fail(e, "adjoint launch");
     return MPATH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpath_adjoint(const mpath_grid* g, const mpath_cast_desc* d, const mpath_observables* fwd,
+                  const void* cast_ws, size_t cast_ws_bytes, const mpath_adjoint_desc* ad, void* dev_ws,
+                  size_t ws_bytes, void* stream)
+{
+    return adjoint_impl(g, d, fwd, cast_ws, cast_ws_bytes, ad, dev_ws, ws_bytes, stream, nullptr);
 }
 
 }  // extern "C"
@@ -861,6 +914,292 @@ int mpath_gather_probe(const void* table, size_t table_bytes, int32_t record_byt
     const hipError_t e = launch_gather_probe(table, table_bytes, record_bytes, in_flight, n_waves, iters, seed, out,
                                              static_cast<hipStream_t>(stream));
     return e ? hip_fail(e, "gather probe launch") : MPATH_OK;
+}
+
+
+int mpath_lensing_maps(const float* A, int64_t n, float* out, void* stream)
+{
+    if (n < 0) return fail(MPATH_ERR_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && (!A || !out)) return fail(MPATH_ERR_INVALID_ARG, "A and out must be device pointers");
+    const hipError_t e = launch_lensing_maps(A, n, out, static_cast<hipStream_t>(stream));
+    return e ? hip_fail(e, "lensing maps launch") : MPATH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The five-rays-per-beam cast behind mpath_finite_beam: workspace layout and
+// the inner cast descriptor (caller's directions, 5 c_j rays per observer).
+struct BeamPlan {
+    int64_t n_rays = 0;
+    std::vector<BeamObs> obs;
+    std::vector<int64_t> count5;
+    mpath_cast_desc desc5;
+    size_t off_obs = 0, off_dirs5 = 0, off_status5 = 0, off_cast = 0, cast_bytes = 0, total = 0;
+    CastLayout lay5;
+};
+
+int beam_plan(const mpath_grid* g, const mpath_cast_desc* d, BeamPlan& P)
+{
+    int rc = check_cast_desc(g, d, &P.n_rays);
+    if (rc) return rc;
+    const int64_t npix = 12ll * d->nside * d->nside;
+    P.obs.resize(d->n_obs);
+    P.count5.resize(d->n_obs);
+    int64_t first = 0;
+    for (int j = 0; j < d->n_obs; ++j) {
+        P.obs[j].ray_first = first;
+        P.obs[j].pix_first = (d->pix_first && !d->dirs) ? d->pix_first[j] : 0;
+        P.obs[j].count = d->pix_count ? d->pix_count[j] : npix;
+        P.count5[j] = 5 * P.obs[j].count;
+        first += P.obs[j].count;
+    }
+    P.desc5 = *d;
+    P.desc5.pix_first = nullptr;
+    P.desc5.pix_count = P.count5.data();
+    P.desc5.checkpoint_every = 0;
+    P.desc5.dirs = reinterpret_cast<const double*>(16);   // placeholder until the workspace is known
+    int64_t n5;
+    std::vector<ObsDev> obs5;
+    rc = cast_plan(g, &P.desc5, &n5, obs5, &P.lay5);
+    if (rc) return rc;
+    P.off_obs = 0;
+    P.off_dirs5 = align_up((size_t)d->n_obs * sizeof(BeamObs), 256);
+    P.off_status5 = align_up(P.off_dirs5 + (size_t)n5 * 24, 256);
+    P.off_cast = align_up(P.off_status5 + (size_t)n5 * 4, 256);
+    P.cast_bytes = P.lay5.total;
+    P.total = P.off_cast + P.cast_bytes;
+    return MPATH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpath_finite_beam_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, size_t* bytes)
+{
+    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
+    BeamPlan P;
+    const int rc = beam_plan(g, d, P);
+    if (rc) return rc;
+    *bytes = P.total;
+    return MPATH_OK;
+}
+
+int mpath_finite_beam(const mpath_grid* g, const mpath_cast_desc* d, double eps, float* A, int32_t* status,
+                      void* dev_ws, size_t ws_bytes, void* stream)
+{
+    if (!(eps > 0.0 && eps <= 0.1)) return fail(MPATH_ERR_INVALID_ARG, "eps must be in (0, 0.1] rad");
+    BeamPlan P;
+    int rc = beam_plan(g, d, P);
+    if (rc) return rc;
+    if (P.n_rays > 0 && !A) return fail(MPATH_ERR_INVALID_ARG, "A is NULL");
+    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
+    if (ws_bytes < P.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "finite-beam workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dev_ws;
+    BeamObs* obs_d = reinterpret_cast<BeamObs*>(ws + P.off_obs);
+    double* dirs5 = reinterpret_cast<double*>(ws + P.off_dirs5);
+    int32_t* status5 = reinterpret_cast<int32_t*>(ws + P.off_status5);
+    hipError_t e = hipMemcpyAsync(obs_d, P.obs.data(), P.obs.size() * sizeof(BeamObs), hipMemcpyHostToDevice, s);
+    if (!e) e = hipStreamSynchronize(s);   // the host table is released on return
+    if (e) return hip_fail(e, "beam table upload");
+    const double te = std::tan(eps);
+    e = launch_beam_dirs(obs_d, d->n_obs, d->nside, d->dirs, te, P.n_rays, dirs5, s);
+    if (e) return hip_fail(e, "beam directions launch");
+    P.desc5.dirs = dirs5;
+    mpath_observables out5;
+    std::memset(&out5, 0, sizeof out5);
+    out5.status = status5;
+    rc = mpath_cast(g, &P.desc5, &out5, ws + P.off_cast, P.cast_bytes, stream);
+    if (rc) return rc;
+    const RayEnd* ends = reinterpret_cast<const RayEnd*>(ws + P.off_cast + P.lay5.off_ends);
+    e = launch_finite_beam(obs_d, d->n_obs, ends, dirs5, status5, g->eta0, te, P.n_rays, A, status, s);
+    return e ? hip_fail(e, "finite-beam launch") : MPATH_OK;
+}
+
+
+}  // extern "C"
+
+namespace {
+
+// Host side of the geodesic finder: per-source stop surfaces and targets,
+// the cast descriptor of the iterations, and the workspace layout.
+struct FinderPlan {
+    int64_t n = 0;
+    std::vector<double2> stop;          // (eta_s, a_s)
+    std::vector<double> target;         // beta, [n][3]
+    double chi_max = 0.0;
+    int64_t count = 0;
+    mpath_cast_desc cd;
+    size_t off_stop = 0, off_target = 0, off_iter = 0, off_status = 0, off_sep = 0, off_jac = 0, off_nsteps = 0,
+           off_active = 0, off_cast = 0, off_adj = 0, cast_bytes = 0, adj_bytes = 0, total = 0;
+    CastLayout lay;
+};
+
+int finder_plan(const mpath_grid* g, const mpath_finder_desc* f, FinderPlan& P, bool tables)
+{
+    if (!g) return fail(MPATH_ERR_INVALID_ARG, "grid is NULL");
+    if (!f) return fail(MPATH_ERR_INVALID_ARG, "finder desc is NULL");
+    if (!f->obs_pos) return fail(MPATH_ERR_INVALID_ARG, "obs_pos is NULL");
+    if (f->n_src < 0 || (f->n_src > 0 && !f->src_pos)) return fail(MPATH_ERR_INVALID_ARG, "bad n_src or src_pos");
+    if (f->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "only order = 1 (CIC) is implemented");
+    if (!(f->tol > 0.0)) return fail(MPATH_ERR_INVALID_ARG, "tol must be > 0");
+    if (f->max_iter < 1) return fail(MPATH_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (f->identity_iters < 0) return fail(MPATH_ERR_INVALID_ARG, "identity_iters must be >= 0");
+    if (f->checkpoint_every < 1) return fail(MPATH_ERR_INVALID_ARG, "checkpoint_every must be >= 1");
+    P.n = f->n_src;
+    const double amin = 1.0 / (1.0 + kZMaxTable);
+    const double eta_min = g->bg.is_static ? -INFINITY : g->bg.eta_of_a(amin);
+    if (tables) {
+        P.stop.resize(P.n);
+        P.target.resize(3 * P.n);
+    }
+    P.chi_max = 0.0;
+    for (int64_t i = 0; i < P.n; ++i) {
+        double r[3];
+        for (int k = 0; k < 3; ++k) r[k] = f->src_pos[3 * i + k] - f->obs_pos[k];
+        const double chi = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        if (!(chi > 0.0) || !std::isfinite(chi)) return fail(MPATH_ERR_INVALID_ARG, "a source sits at the observer");
+        const double eta_s = g->eta0 - chi;
+        if (eta_s < eta_min) return fail(MPATH_ERR_UNSUPPORTED, "a source lies beyond the background table (z > 20)");
+        P.chi_max = std::max(P.chi_max, chi);
+        if (tables) {
+            P.stop[i] = make_double2(eta_s, g->bg.a_of_eta(eta_s));
+            for (int k = 0; k < 3; ++k) P.target[3 * i + k] = r[k] / chi;
+        }
+    }
+    P.count = P.n;
+    std::memset(&P.cd, 0, sizeof P.cd);
+    P.cd.n_obs = 1;
+    P.cd.obs_pos = f->obs_pos;
+    P.cd.stop_value = &P.chi_max;     // bounds every source's surface (checkpoint sizing)
+    P.cd.stop_kind = MPATH_STOP_CHI;
+    P.cd.nside = 1;
+    P.cd.pix_count = &P.count;
+    P.cd.order = 1;
+    P.cd.steps_per_cell = f->steps_per_cell;
+    P.cd.adaptive = f->adaptive;
+    P.cd.max_steps = f->max_steps;
+    P.cd.schedule = MPATH_SCHED_STATIC;
+    P.cd.checkpoint_every = f->checkpoint_every;
+    P.cd.dirs = reinterpret_cast<const double*>(16);   // the working theta once the workspace is known
+    int64_t nr;
+    std::vector<ObsDev> obs;
+    int rc = cast_plan(g, &P.cd, &nr, obs, &P.lay);
+    if (rc) return rc;
+    const size_t n = (size_t)P.n;
+    P.off_stop = 0;
+    P.off_target = align_up(P.off_stop + n * 16, 256);
+    P.off_iter = align_up(P.off_target + n * 24, 256);
+    P.off_status = align_up(P.off_iter + n * 4, 256);
+    P.off_sep = align_up(P.off_status + n * 4, 256);
+    P.off_jac = align_up(P.off_sep + n * 8, 256);
+    P.off_nsteps = align_up(P.off_jac + n * 16, 256);
+    P.off_active = align_up(P.off_nsteps + n * 4, 256);
+    P.off_cast = align_up(P.off_active + 256, 256);
+    P.cast_bytes = P.lay.total;
+    P.off_adj = align_up(P.off_cast + P.cast_bytes, 256);
+    P.adj_bytes = adjoint_layout(g, &P.cd, P.n).total;
+    P.total = P.off_adj + P.adj_bytes;
+    return MPATH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpath_find_geodesics_workspace_bytes(const mpath_grid* g, const mpath_finder_desc* f, size_t* bytes)
+{
+    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
+    FinderPlan P;
+    const int rc = finder_plan(g, f, P, false);
+    if (rc) return rc;
+    *bytes = P.total;
+    return MPATH_OK;
+}
+
+int mpath_find_geodesics(const mpath_grid* g, const mpath_finder_desc* f, mpath_finder_out* out, void* dev_ws,
+                         size_t ws_bytes, void* stream)
+{
+    FinderPlan P;
+    int rc = finder_plan(g, f, P, true);
+    if (rc) return rc;
+    if (!out || (P.n > 0 && !out->theta)) return fail(MPATH_ERR_INVALID_ARG, "out or out->theta is NULL");
+    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
+    if (ws_bytes < P.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "finder workspace too small");
+    if (P.n == 0) return MPATH_OK;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dev_ws;
+    const double2* stop = reinterpret_cast<const double2*>(ws + P.off_stop);
+    const double* target = reinterpret_cast<const double*>(ws + P.off_target);
+    int32_t* n_iter = reinterpret_cast<int32_t*>(ws + P.off_iter);
+    int32_t* status = reinterpret_cast<int32_t*>(ws + P.off_status);
+    double* sep = reinterpret_cast<double*>(ws + P.off_sep);
+    float* jac = reinterpret_cast<float*>(ws + P.off_jac);
+    int32_t* nsteps = reinterpret_cast<int32_t*>(ws + P.off_nsteps);
+    unsigned int* active = reinterpret_cast<unsigned int*>(ws + P.off_active);
+    char* cws = ws + P.off_cast;
+    char* aws = ws + P.off_adj;
+    double* theta = out->theta;
+    const size_t n = (size_t)P.n;
+    hipError_t e = hipMemcpyAsync(ws + P.off_stop, P.stop.data(), n * 16, hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemcpyAsync(ws + P.off_target, P.target.data(), n * 24, hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemcpyAsync(theta, ws + P.off_target, n * 24, hipMemcpyDeviceToDevice, s);   // theta_0 = beta
+    if (!e) e = hipStreamSynchronize(s);   // host tables are released on return
+    if (!e) e = launch_fill_i32(n_iter, P.n, -1, s);
+    if (e) return hip_fail(e, "finder set-up");
+    P.cd.dirs = theta;
+    const RayEnd* ends = reinterpret_cast<const RayEnd*>(cws + P.lay.off_ends);
+    const int K = f->checkpoint_every;
+    for (int it = 0; it < f->max_iter; ++it) {
+        const bool exact = it >= f->identity_iters;
+        P.cd.checkpoint_every = exact ? K : 0;
+        mpath_observables fo;
+        std::memset(&fo, 0, sizeof fo);
+        fo.status = status;
+        fo.n_steps = nsteps;
+        rc = cast_impl(g, &P.cd, &fo, cws, P.cast_bytes, stream, false, nullptr, stop);
+        if (rc) return rc;
+        if (exact) {
+            mpath_adjoint_desc ad;
+            std::memset(&ad, 0, sizeof ad);
+            ad.jac = jac;
+            rc = adjoint_impl(g, &P.cd, &fo, cws, P.cast_bytes, &ad, aws, P.adj_bytes, stream, stop);
+            if (rc) return rc;
+        }
+        e = launch_finder_update(P.n, ends, target, status, exact ? jac : nullptr, g->eta0, f->tol, it, theta,
+                                 n_iter, sep, active, s);
+        unsigned int left = 0;
+        if (!e) e = hipMemcpyAsync(&left, active, sizeof left, hipMemcpyDeviceToHost, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (e) return hip_fail(e, "finder iteration");
+        if (left == 0) break;
+    }
+    // final cast along theta, checkpointed for the distortion matrix there
+    P.cd.checkpoint_every = K;
+    mpath_observables fo;
+    std::memset(&fo, 0, sizeof fo);
+    fo.status = status;
+    fo.n_steps = nsteps;
+    fo.z5 = out->z5;
+    fo.z0 = out->z0;
+    fo.phi_src = out->phi_src;
+    rc = cast_impl(g, &P.cd, &fo, cws, P.cast_bytes, stream, false, nullptr, stop);
+    if (rc) return rc;
+    if (out->A || out->dz_dtheta) {
+        mpath_adjoint_desc ad;
+        std::memset(&ad, 0, sizeof ad);
+        ad.jac = out->A;
+        ad.dz_dtheta = out->dz_dtheta;
+        rc = adjoint_impl(g, &P.cd, &fo, cws, P.cast_bytes, &ad, aws, P.adj_bytes, stream, stop);
+        if (rc) return rc;
+    }
+    e = launch_finder_sep(P.n, ends, target, theta, status, g->eta0, out->sep ? out->sep : sep, s);
+    if (!e && out->n_iter) e = hipMemcpyAsync(out->n_iter, n_iter, n * 4, hipMemcpyDeviceToDevice, s);
+    if (!e && out->status) e = hipMemcpyAsync(out->status, status, n * 4, hipMemcpyDeviceToDevice, s);
+    return e ? hip_fail(e, "finder output") : MPATH_OK;
 }
 
 }  // extern "C"

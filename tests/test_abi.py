@@ -120,3 +120,41 @@ def test_gather_probe_argument_checks(abi):
         rc = L.mpath_gather_probe(a["table"], a["nbytes"], a["rec"], a["u"], a["waves"], a["iters"], 1, out, None)
         assert rc == abi.MPATH_ERR_INVALID_ARG, (bad, L.mpath_last_error())
     assert L.mpath_gather_probe(fake, 1 << 16, 64, 4, 8, 2, 1, None, None) == abi.MPATH_ERR_INVALID_ARG
+
+
+def test_lensing_entry_points_reject_bad_arguments(abi):
+    """Checked before any device work (no grid or device memory is touched)."""
+    L = abi.lib()
+    fake = C.c_void_p(1 << 20)
+    assert L.mpath_lensing_maps(fake, -1, fake, None) == abi.MPATH_ERR_INVALID_ARG
+    assert L.mpath_lensing_maps(None, 4, fake, None) == abi.MPATH_ERR_INVALID_ARG
+    assert L.mpath_lensing_maps(None, 0, None, None) == abi.MPATH_OK
+    from paper_2111_08744_amd import CastConfig
+    d = CastConfig([0, 0, 0], 0.5, 4).desc()
+    n = C.c_size_t()
+    assert L.mpath_finite_beam_workspace_bytes(None, C.byref(d), C.byref(n)) == abi.MPATH_ERR_INVALID_ARG
+    for eps in (0.0, -1e-3, 0.2, float("nan")):
+        assert L.mpath_finite_beam(fake, C.byref(d), eps, fake, None, fake, 1 << 30, None) == \
+            abi.MPATH_ERR_INVALID_ARG
+
+
+def test_caller_directions_ray_count(abi):
+    """With caller directions pix_count alone sets the rays per observer."""
+    import torch
+    from paper_2111_08744_amd import CastConfig
+    cfg = CastConfig([[0, 0, 0], [1, 1, 1]], [0.5, 1.0], 4, pix_count=[500, 7])
+    cfg.dirs = torch.zeros((507, 3), dtype=torch.float64)   # any non-NULL pointer: only counted here
+    d = cfg.desc()
+    assert d.dirs and not d.pix_first
+    assert cfg.n_rays() == 507
+
+
+def test_finder_rejects_missing_arguments(abi):
+    L = abi.lib()
+    d = abi.mpath_finder_desc()
+    n = C.c_size_t()
+    assert L.mpath_find_geodesics_workspace_bytes(None, C.byref(d), C.byref(n)) == abi.MPATH_ERR_INVALID_ARG
+    assert L.mpath_find_geodesics_workspace_bytes(C.c_void_p(1 << 20), None, C.byref(n)) == \
+        abi.MPATH_ERR_INVALID_ARG
+    o = abi.mpath_finder_out()
+    assert L.mpath_find_geodesics(None, C.byref(d), C.byref(o), None, 0, None) == abi.MPATH_ERR_INVALID_ARG

@@ -1,0 +1,131 @@
+"""GPU geodesic finder (Sect. 2.5) against the oracle: the roots it finds
+land on the sources under the oracle's own integration, agree with the
+oracle's Newton roots, and carry the exact distortion matrix and redshift
+there."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from oracle import catalog
+from oracle.lensing import angular_separation, jacobian_cs
+from parity import ARCSEC, TOL_ARCSEC, TOL_Z
+
+pytestmark = pytest.mark.gpu
+
+COSMO = (0.3, 0.7, 0.7)
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2111_08744_amd as M
+    return M
+
+
+@pytest.fixture(scope="module")
+def gauss64():
+    return synth.make_cells("gauss64")
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _sources(obs, n, seed, lo, hi):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return np.asarray(obs) + v * rng.uniform(lo, hi, n)[:, None]
+
+
+def _check_against_oracle(cells, obs, src, res, spc, adaptive, flip_frac=0.0):
+    field = O.Field.grid(cells)
+    c = O.cosmo(*COSMO)
+    theta = res["theta"].cpu().numpy()
+    A = res["A"].cpu().numpy().astype(np.float64)
+    z5 = res["z5"].cpu().numpy()
+    r = src - obs
+    chi = np.linalg.norm(r, axis=1)
+    beta = r / chi[:, None]
+    land = np.empty(len(src))
+    dA = np.empty(len(src))
+    dz = np.empty(len(src))
+    for i in range(len(src)):
+        p = O.params(obs, chi=chi[i], steps_per_cell=spc, adaptive=adaptive)
+        Ao, _, out = jacobian_cs(lambda d, dt: O.cast_cs(field, c, p, d, dtheta=dt), theta[i][None])
+        land[i] = angular_separation(out["r"][0], beta[i]) / ARCSEC
+        dA[i] = np.abs(A[i] - Ao[0]).max()
+        dz[i] = abs(z5[i] - out["z5"][0]) / abs(out["z5"][0])
+    good = land <= TOL_ARCSEC
+    _print(f"oracle landing of the GPU roots: max {land.max():.2e} arcsec, median {np.median(land):.2e}; "
+           f"max |A - A_oracle| {dA.max():.2e}; max rel z5 {dz.max():.2e}")
+    assert (~good).sum() <= flip_frac * len(src)
+    assert dA[good].max() < 5e-6
+    assert dz[good].max() < TOL_Z
+    return beta
+
+
+def test_finder_uniform_matches_oracle(M, gauss64):
+    """48 sources at 300-1500 Mpc/h around the box centre on the 64^3 grid."""
+    obs = np.array([250.0, 250.0, 250.0])
+    src = _sources(obs, 48, 21, 300.0, 1500.0)
+    _print("finder: 48 sources, uniform 64^3")
+    grid = M.Grid(gauss64, COSMO)
+    res = M.find_geodesics(grid, obs, src, steps_per_cell=10, tol=2e-10)
+    it = res["n_iter"].cpu().numpy()
+    _print("iterations:", np.bincount(it[it >= 0]))
+    assert (it >= 0).all() and (res["status"].cpu().numpy() == 0).all()
+    assert res["sep"].cpu().numpy().max() < 2e-10
+    beta = _check_against_oracle(gauss64, obs, src, res, 10, False)
+    theta = res["theta"].cpu().numpy()
+    assert angular_separation(theta, beta).max() > 1e-6          # the sources are lensed
+    # the oracle's own Newton roots for a subset
+    t_o, it_o, _ = catalog.find_geodesics(O.Field.grid(gauss64), O.cosmo(*COSMO), obs, src[:12], tol=1e-11)
+    assert (it_o >= 0).all()
+    d = angular_separation(theta[:12], t_o) / ARCSEC
+    _print(f"GPU vs oracle roots: max {d.max():.2e} arcsec")
+    assert d.max() < 2 * TOL_ARCSEC
+
+
+def test_finder_schedules_find_the_same_roots(M, gauss64):
+    """Exact Newton from the first iteration, or the identity first: the same
+    roots; one iteration is not enough for lensed sources."""
+    obs = np.array([120.0, 300.0, 410.0])
+    src = _sources(obs, 32, 22, 400.0, 900.0)
+    grid = M.Grid(gauss64, COSMO)
+    a = M.find_geodesics(grid, obs, src, tol=2e-10)
+    b = M.find_geodesics(grid, obs, src, tol=2e-10, identity_iters=0)
+    ta, tb = a["theta"].cpu().numpy(), b["theta"].cpu().numpy()
+    assert angular_separation(ta, tb).max() < 1e-9
+    one = M.find_geodesics(grid, obs, src, tol=2e-10, max_iter=1)
+    it1 = one["n_iter"].cpu().numpy()
+    assert (it1 == -1).any() and set(np.unique(it1)) <= {-1, 0}
+
+
+def test_finder_amr(M):
+    """Refined grid, adaptive steps: roots land on the sources under the
+    oracle; a source whose path grazes an AMR boundary within rounding may
+    take the other branch there, which must stay rare."""
+    cells = synth.make_cells("amr_halo_small")
+    obs = np.array([125.0, 125.0, 125.0])
+    src = _sources(obs, 24, 23, 200.0, 800.0)
+    grid = M.Grid(cells, COSMO)
+    res = M.find_geodesics(grid, obs, src, steps_per_cell=4, adaptive=True, tol=2e-10)
+    assert (res["n_iter"].cpu().numpy() >= 0).all()
+    _check_against_oracle(cells, obs, src, res, 4, True, flip_frac=0.1)
+
+
+def test_finder_edge_cases(M, gauss64):
+    grid = M.Grid(gauss64, COSMO)
+    obs = np.array([250.0, 250.0, 250.0])
+    empty = M.find_geodesics(grid, obs, np.zeros((0, 3)))
+    assert empty["theta"].shape == (0, 3)
+    with pytest.raises(RuntimeError):
+        M.find_geodesics(grid, obs, obs[None, :])             # a source at the observer
+    with pytest.raises(RuntimeError):
+        M.find_geodesics(grid, obs, obs[None, :] + 1e5)       # beyond z = 20
+    with pytest.raises(RuntimeError):
+        M.find_geodesics(grid, obs, obs[None, :] + 100.0, tol=0.0)
