@@ -239,6 +239,53 @@ def measure_lensing(M, torch, dev):
             "infinitesimal_beam_rays_per_s": n / (t_inf / 1e3), "finite_beam_rays_per_s": n / (t_fb / 1e3)}
 
 
+def measure_finder(M, torch, dev):
+    """Geodesic finder on the 64^3 uniform grid: 16,384 sources at seeded
+    positions around the box centre, comoving distances uniform in
+    [200, 2300] Mpc/h (z up to about 1), tolerance 1e-9 rad; identity
+    Newton steps first, then the exact Jacobian."""
+    import synth
+    grid = M.Grid(synth.make_cells("gauss64"), (0.3, 0.7, 0.7), device=dev)
+    rng = np.random.default_rng(31)
+    obs = np.array([250.0, 250.0, 250.0])
+    v = rng.standard_normal((16384, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    src = obs + v * rng.uniform(200.0, 2300.0, len(v))[:, None]
+    res = {}
+    t = _time_ms(torch, lambda: res.update(M.find_geodesics(grid, obs, src, tol=1e-9, ws=res.get("_ws"))), reps=1)
+    it = res["n_iter"].cpu().numpy()
+    hist = np.bincount(it[it >= 0]).tolist()
+    log(f"[bench] finder: {len(src)} sources in {t:.1f} ms, converged {int((it >= 0).sum())}, "
+        f"iterations {hist}, max sep {float(res['sep'].max()):.2e} rad")
+    return {"workload": "16384 sources, chi U[200, 2300] Mpc/h, uniform 64^3 grid, tol 1e-9 rad",
+            "sources": len(src), "ms": t, "sources_per_s": len(src) / (t / 1e3),
+            "converged": int((it >= 0).sum()), "iterations_histogram": hist}
+
+
+def measure_orders(M, torch, dev):
+    """The three interpolation orders (Sect. 2.2) on the same rays: 196,608
+    rays (nside 128) to z = 1 on the uniform 64^3 grid and 49,152 rays
+    (nside 64) to z = 1 on the AMR 128^3 + 3 levels grid; time per ray-step."""
+    import synth
+    res = {}
+    for name, grid_name, nside, spc, adaptive in (("uniform", "gauss64", 128, 10, False),
+                                                  ("amr", "amr128", 64, 4, True)):
+        grid = M.Grid(synth.make_cells(grid_name), (0.3, 0.7, 0.7), device=dev)
+        obs = [250.0, 250.0, 250.0]
+        row = {}
+        for order, label in ((0, "ngp"), (1, "cic"), (2, "tsc")):
+            cfg = M.CastConfig(obs, 1.0, nside, steps_per_cell=spc, adaptive=adaptive, schedule=1, order=order)
+            out = M.alloc_outputs(cfg.n_rays(), dev)
+            t = _time_ms(torch, lambda: M.cast(grid, cfg, out, out.get("_ws")))
+            steps = int(out["n_steps"].to(torch.int64).sum())
+            row[label] = {"ms": t, "ray_steps": steps, "ray_steps_per_s": steps / (t / 1e3)}
+        res[name] = row
+        del grid
+        log(f"[bench] orders ({name}): " + ", ".join(
+            f"{k} {v['ms']:.2f} ms ({v['ray_steps_per_s'] / 1e9:.2f} G ray-steps/s)" for k, v in row.items()))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,7 +420,8 @@ def main():
         }
     if not args.no_secondary:
         sec = {"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev),
-               "lensing": measure_lensing(M, torch, dev)}
+               "lensing": measure_lensing(M, torch, dev), "finder": measure_finder(M, torch, dev),
+               "orders": measure_orders(M, torch, dev)}
         res["secondary"] = sec
         res["adjoint_forward_ratio"] = sec["adjoint"]["adjoint_forward_ratio"]
     if not args.no_cpu_baseline:

@@ -155,7 +155,9 @@ typedef struct {
     const int64_t* pix_first;
     const int64_t* pix_count;
     /* integration (Sect. 2.2) */
-    int32_t order;              /* 1 = CIC; 0 (NGP) and 2 (TSC): MPATH_ERR_UNSUPPORTED */
+    int32_t order;              /* interpolation (Sect. 2.2): 0 NGP, 1 CIC, 2 TSC; NGP and
+                                   TSC run the static schedule and support neither
+                                   checkpoints (the adjoint) nor the infinitesimal beam */
     int32_t steps_per_cell;     /* N >= 1: comoving step length h / N                   */
     int32_t adaptive;           /* 1: h of the leaf cell at the step start; 0: coarse h */
     int64_t max_steps;          /* per ray, including the landing step (at most 2^31-1)  */

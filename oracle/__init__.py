@@ -92,6 +92,8 @@ def lib():
         L.or_field_analytic.restype = vp
         L.or_field_analytic.argtypes = [C.c_int, dp]
         L.or_field_free.argtypes = [vp]
+        L.or_field_set_order.restype = C.c_int
+        L.or_field_set_order.argtypes = [vp, C.c_int]
         L.or_field_probe.restype = C.c_int
         L.or_field_probe.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         for name in ("or_eta_of_a", "or_a_of_eta", "or_conformal_hubble"):
@@ -132,7 +134,8 @@ class Field:
         self._keep = keep
 
     @classmethod
-    def grid(cls, cells) -> "Field":
+    def grid(cls, cells, order: int = 1) -> "Field":
+        """Grid field; order 0 NGP, 1 CIC, 2 TSC (Sect. 2.2)."""
         level = np.ascontiguousarray(cells.level, np.uint8)
         ijk = np.ascontiguousarray(cells.ijk, np.int32)
         phi = np.ascontiguousarray(cells.phi, np.float64)
@@ -143,6 +146,9 @@ class Field:
                                 _ptr(phi), _ptr(grad), err, 256)
         if not h:
             raise ValueError("oracle rejected the grid: " + err.value.decode())
+        if lib().or_field_set_order(h, int(order)):
+            lib().or_field_free(h)
+            raise ValueError(f"bad interpolation order {order}")
         return cls(h)
 
     @classmethod

@@ -24,6 +24,7 @@
 
 struct or_field {
     int kind;
+    int order;            /* grid interpolation: 0 NGP, 1 CIC, 2 TSC (Sect. 2.2) */
     /* grid */
     double box, h0;
     int n0, max_level, periodic;
@@ -122,6 +123,25 @@ static int stencil_cells(const or_field* f, int l, const int64_t b[3], int64_t i
     return 1;
 }
 
+/* The 27 cells c + {-1,0,1}^3 at level l (index (ox+1) + 3 (oy+1) + 9 (oz+1));
+ * returns 0 if any of them is missing. */
+static int tsc_cells(const or_field* f, int l, const int64_t c[3], int64_t ids[27])
+{
+    for (int q = 0; q < 27; ++q) {
+        const int64_t cidx[3] = {c[0] + q % 3 - 1, c[1] + (q / 3) % 3 - 1, c[2] + q / 9 - 1};
+        ids[q] = find_cell(f, l, cidx);
+        if (ids[q] < 0) return 0;
+    }
+    return 1;
+}
+
+int or_field_set_order(or_field* f, int order)
+{
+    if (!f || f->kind != OR_FIELD_GRID || order < 0 || order > 2) return -1;
+    f->order = order;
+    return 0;
+}
+
 static void set_err(char* err, int errlen, const char* msg)
 {
     if (err && errlen > 0) { strncpy(err, msg, (size_t)errlen - 1); err[errlen - 1] = 0; }
@@ -137,6 +157,7 @@ or_field* or_field_grid(double box, int n0, int max_level, int periodic, int64_t
     }
     or_field* f = (or_field*)calloc(1, sizeof(or_field));
     f->kind = OR_FIELD_GRID;
+    f->order = 1;
     f->box = box; f->n0 = n0; f->max_level = max_level; f->periodic = periodic;
     f->h0 = box / n0;
     f->n_cells = n_cells;

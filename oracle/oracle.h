@@ -41,9 +41,14 @@ or_field* or_field_grid(double box, int n0, int max_level, int periodic, int64_t
  *   POINT     params = {m, cx,cy,cz, soft}                      Phi = -m / sqrt(|x-c|^2 + soft^2) */
 or_field* or_field_analytic(int kind, const double* params);
 void or_field_free(or_field* f);
+/* Interpolation scheme of a grid field (Sect. 2.2, weights W_NGP, W_CIC,
+ * W_TSC): 0 NGP (the deepest cell containing x), 1 CIC (default, 8 cells),
+ * 2 TSC (27 cells centred on the cell containing x), CIC and TSC with the
+ * level fallback.  Returns 0, or -1 for a bad order or a closed-form field. */
+int or_field_set_order(or_field* f, int order);
 
 /* Interpolation probe at a point: Phi, grad Phi, the leaf level (deepest
- * existing cell containing x) and the level the CIC stencil was taken at.
+ * existing cell containing x) and the level the stencil was taken at.
  * Returns 0, or 1 when no complete stencil exists even at the coarse level. */
 int or_field_probe(const or_field* f, const double x[3], double* phi, double grad[3],
                    int* leaf_level, int* stencil_level);

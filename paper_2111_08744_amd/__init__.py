@@ -130,7 +130,7 @@ class CastConfig:
 
     def __init__(self, obs, stop, nside, pix_first=None, pix_count=None, stop_kind="z",
                  steps_per_cell=10, adaptive=False, max_steps=1 << 40, schedule=0,
-                 block_size=0, waves_per_cu=0, batch=0, checkpoint_every=0, dirs=None):
+                 block_size=0, waves_per_cu=0, batch=0, checkpoint_every=0, dirs=None, order=1):
         self.obs = np.ascontiguousarray(np.atleast_2d(obs), np.float64)
         self.stop = np.ascontiguousarray(np.atleast_1d(stop), np.float64)
         self.nside = int(nside)
@@ -146,6 +146,7 @@ class CastConfig:
         self.waves_per_cu = int(waves_per_cu)
         self.batch = int(batch)
         self.checkpoint_every = int(checkpoint_every)
+        self.order = int(order)          # 0 NGP, 1 CIC, 2 TSC
         # initial directions: None = NESTED pixel centres; else a float64 CUDA
         # tensor [n_rays, 3] of unit vectors (pix_count gives the rays per observer)
         if dirs is not None:
@@ -163,7 +164,7 @@ class CastConfig:
         d.nside = self.nside
         d.pix_first = self.pix_first.ctypes.data if self.pix_first is not None else None
         d.pix_count = self.pix_count.ctypes.data if self.pix_count is not None else None
-        d.order = 1
+        d.order = self.order
         d.steps_per_cell = self.steps_per_cell
         d.adaptive = int(self.adaptive)
         d.max_steps = self.max_steps

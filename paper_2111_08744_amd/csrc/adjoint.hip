@@ -562,7 +562,7 @@ __device__ __forceinline__ bool forward_step(const CastArgs& a, FieldCache<AMR>&
     // landing: two Newton passes for the step length, then the step
     const int passes = landing ? 3 : 1;
     for (int k = 0; k < passes; ++k) {
-        if (rk4_step<AMR, Rec>(a.grid, a.cosmo, F, geo, y, dlx, yn, h, rec, record && k + 1 == passes))
+        if (rk4_step<FieldCache<AMR>, Rec>(a.grid, a.cosmo, F, geo, y, dlx, yn, h, rec, record && k + 1 == passes))
             return false;
         if (k + 1 < passes) dlx = dlx + (yn.eta - eta_s) / yn.K;
     }

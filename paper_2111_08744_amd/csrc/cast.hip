@@ -12,6 +12,8 @@
 //               redshifts, AMR) do not leave lanes idle.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.h"
 
 namespace mpath {
@@ -31,7 +33,7 @@ struct NoSample {
 };
 
 // Everything one lane carries for its current ray.
-template <bool AMR>
+template <bool AMR, class FC = FieldCache<AMR>>
 struct RayRun {
     int64_t ray;          // -1: no ray
     RayGeom geo;
@@ -41,7 +43,7 @@ struct RayRun {
     int32_t n_steps;
     uint32_t hash;
     int status;           // -1 while running
-    FieldCache<AMR> F;
+    FC F;
 
     template <bool CKPT = false>
     __device__ __forceinline__ bool advance(const CastArgs& a, int max_iter)
@@ -117,7 +119,7 @@ struct RayRun {
             const int passes = landing ? 3 : 1;
             GeoState yn;
             for (int k = 0; k < passes; ++k) {
-                if (rk4_step<AMR>(g, a.cosmo, F, geo, y, dlx, yn, hash)) {
+                if (rk4_step<FC>(g, a.cosmo, F, geo, y, dlx, yn, hash)) {
                     status = MPATH_RAY_LEFT_DOMAIN;
                     return true;
                 }
@@ -424,6 +426,21 @@ __global__ __launch_bounds__(kBlock, 2) void cast_infbeam_kernel(CastArgs a, flo
     R.finish(a);
 }
 
+// Static schedule with the NGP (ORDER 0) or TSC (ORDER 2) field evaluator.
+template <bool AMR, int ORDER>
+__global__ __launch_bounds__(kBlock, 2) void cast_order_kernel(CastArgs a)
+{
+    extern __shared__ float order_lds[];
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    using FC = typename std::conditional<ORDER == 0, NgpCache<AMR>, TscCache<AMR>>::type;
+    RayRun<AMR, FC> R;
+    R.F.bind(order_lds + threadIdx.x);
+    R.start(a, r);
+    R.advance(a, 0x7fffffff);
+    R.finish(a);
+}
+
 __global__ void zero_u64(unsigned long long* p) { *p = 0ull; }
 
 __global__ void permute_values_kernel(float4* payload, const int64_t* perm, const float4* values, int64_t n)
@@ -467,6 +484,23 @@ hipError_t launch_cast_infbeam(const CastArgs& a, float* A, hipStream_t s)
         hipLaunchKernelGGL(cast_infbeam_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, A);
     else
         hipLaunchKernelGGL(cast_infbeam_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_order(const CastArgs& a, int order, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
+    const size_t lds = order == 2 ? (size_t)27 * kBlock * sizeof(int) : 0;
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    const bool amr = a.grid.max_level > 0;
+    if (order == 0) {
+        if (amr) hipLaunchKernelGGL((cast_order_kernel<true, 0>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((cast_order_kernel<false, 0>), grid, block, lds, s, a);
+    } else {
+        if (amr) hipLaunchKernelGGL((cast_order_kernel<true, 2>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((cast_order_kernel<false, 2>), grid, block, lds, s, a);
+    }
     return hipGetLastError();
 }
 

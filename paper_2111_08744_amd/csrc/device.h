@@ -363,6 +363,189 @@ struct FieldCache {
     }
 };
 
+// Leaf containing the point with unwrapped coordinates I at level
+// max_level + 1 (a walk from its coarse cell); its id in id.  Returns its
+// level, or -1 outside a non-periodic box.
+template <bool AMR>
+__device__ __forceinline__ int walk_to_leaf(const GridDev& g, const int I[3], int& id)
+{
+    const int Lm = AMR ? g.max_level : 0;
+    int J0 = I[0] >> 1, J1 = I[1] >> 1, J2 = I[2] >> 1;   // level max_level
+    const int M = g.n0 << Lm;
+    if (g.periodic) {
+        J0 &= M - 1; J1 &= M - 1; J2 &= M - 1;
+    } else if ((unsigned)J0 >= (unsigned)M || (unsigned)J1 >= (unsigned)M || (unsigned)J2 >= (unsigned)M) {
+        return -1;
+    }
+    id = (int)morton3((uint32_t)(J0 >> Lm), (uint32_t)(J1 >> Lm), (uint32_t)(J2 >> Lm));
+    int L = 0;
+    if (AMR) {
+        for (int m = Lm - 1; m >= 0; --m) {
+            const int ch = g.child[id];
+            if (ch < 0) break;
+            id = ch + (((J0 >> m) & 1) | (((J1 >> m) & 1) << 1) | (((J2 >> m) & 1) << 2));
+            ++L;
+        }
+    }
+    return L;
+}
+
+// Field by nearest grid point (Sect. 2.2, W_NGP): the values of the deepest
+// cell containing the point.  The lane keeps the last leaf and its values.
+template <bool AMR>
+struct NgpCache {
+    static constexpr int kNoKey = 0x40000000;
+    int keyL;           // level of the cached leaf
+    int key[3];         // its unwrapped coordinates at that level
+    float val[4];       // its (phi, gx, gy, gz)
+
+    __device__ __forceinline__ void bind(float*) {}
+    __device__ __forceinline__ void reset()
+    {
+        keyL = 0;
+        key[0] = key[1] = key[2] = kNoKey;
+    }
+
+    // Leaf level at the point with fine coordinates I (-1 outside a
+    // non-periodic box); loads the leaf's values when it changes.
+    __device__ __forceinline__ int leaf(const GridDev& g, const int I[3])
+    {
+        const int Lm = AMR ? g.max_level : 0;
+        const int sh = Lm + 1 - keyL;
+        if ((I[0] >> sh) == key[0] && (I[1] >> sh) == key[1] && (I[2] >> sh) == key[2]) return keyL;
+        int id;
+        const int L = walk_to_leaf<AMR>(g, I, id);
+        if (L < 0) return -1;
+        const float4 q = g.payload[id];
+        val[0] = q.x; val[1] = q.y; val[2] = q.z; val[3] = q.w;
+        const int s2 = Lm + 1 - L;
+        keyL = L;
+        key[0] = I[0] >> s2; key[1] = I[1] >> s2; key[2] = I[2] >> s2;
+        return L;
+    }
+
+    __device__ __forceinline__ int eval(const GridDev& g, const double v[3], float& phi, float G[3],
+                                        int& leaf_level, int& stencil_level)
+    {
+        int I[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
+        const int L = leaf(g, I);
+        leaf_level = L;
+        if (L < 0) return 1;
+        stencil_level = L;
+        phi = val[0];
+        G[0] = val[1]; G[1] = val[2]; G[2] = val[3];
+        return 0;
+    }
+};
+
+// Field by triangular-shaped cloud (Sect. 2.2, W_TSC): the 27 cells around
+// the cell containing the point at the leaf level, falling back one level at
+// a time while any of them is missing.  The stencil depends only on the leaf
+// cell (the cell containing the point at every coarser level is its
+// ancestor), so the lane keeps the 27 ids of its leaf's stencil in LDS and
+// resolves them again only when the leaf changes.  Per axis, with f the
+// position in the centre cell (in [0, 1)), the weights of the cells at
+// -1, 0, +1 are (1 - f)^2 / 2, 3/4 - (f - 1/2)^2 and f^2 / 2.
+template <bool AMR>
+struct TscCache {
+    static constexpr int kNoKey = 0x40000000;
+    int keyL;           // level of the leaf whose stencil is cached
+    int key[3];         // its unwrapped coordinates at that level
+    int lvl;            // level of the stencil (-1: not resolved for this leaf)
+    int c[3];           // centre cell of the stencil, unwrapped, at level lvl
+    int* ids;           // LDS: id of stencil cell q at ids[q * kBlock]
+
+    __device__ __forceinline__ void bind(float* lds) { ids = reinterpret_cast<int*>(lds); }
+    __device__ __forceinline__ void reset()
+    {
+        keyL = 0;
+        key[0] = key[1] = key[2] = kNoKey;
+        lvl = -1;
+    }
+
+    __device__ __forceinline__ int leaf(const GridDev& g, const int I[3])
+    {
+        const int Lm = AMR ? g.max_level : 0;
+        const int sh = Lm + 1 - keyL;
+        if ((I[0] >> sh) == key[0] && (I[1] >> sh) == key[1] && (I[2] >> sh) == key[2]) return keyL;
+        int id;
+        const int L = walk_to_leaf<AMR>(g, I, id);
+        if (L < 0) return -1;
+        const int s2 = Lm + 1 - L;
+        keyL = L;
+        key[0] = I[0] >> s2; key[1] = I[1] >> s2; key[2] = I[2] >> s2;
+        lvl = -1;
+        return L;
+    }
+
+    __device__ __forceinline__ bool resolve(const GridDev& g, int L, const int I[3])
+    {
+        const int Lm = AMR ? g.max_level : 0;
+        for (int l = L; l >= 0; --l) {
+            const int s = Lm + 1 - l;
+            const int c0 = I[0] >> s, c1 = I[1] >> s, c2 = I[2] >> s;
+            bool all = true;
+            for (int q = 0; q < 27 && all; ++q) {
+                const int id = lookup_cell(g, l, c0 + q % 3 - 1, c1 + (q / 3) % 3 - 1, c2 + q / 9 - 1);
+                ids[q * kBlock] = id;
+                all = id >= 0;
+            }
+            if (all) {
+                lvl = l;
+                c[0] = c0; c[1] = c1; c[2] = c2;
+                return true;
+            }
+        }
+        return false;
+    }
+
+    __device__ __forceinline__ int eval(const GridDev& g, const double v[3], float& phi, float G[3],
+                                        int& leaf_level, int& stencil_level)
+    {
+        const int Lm = AMR ? g.max_level : 0;
+        int I[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
+        const int L = leaf(g, I);
+        leaf_level = L;
+        if (L < 0) return 1;
+        if (lvl < 0 && !resolve(g, L, I)) return 1;
+        stencil_level = lvl;
+        // position in the centre cell: v 2^(lvl - Lm - 1) - c, exact in FP64
+        const double sc = ldexp(1.0, lvl - Lm - 1);
+        float w[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float f = (float)(v[d] * sc - (double)c[d]);
+            const float h = f - 0.5f;
+            w[d][0] = 0.5f * (1.0f - f) * (1.0f - f);
+            w[d][1] = 0.75f - h * h;
+            w[d][2] = 0.5f * f * f;
+        }
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int z = 0; z < 3; ++z)
+#pragma unroll
+            for (int y = 0; y < 3; ++y) {
+                const float wyz = w[1][y] * w[2][z];
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    const float wq = w[0][x] * wyz;
+                    const float4 p = g.payload[ids[(x + 3 * y + 9 * z) * kBlock]];
+                    acc[0] = fmaf(wq, p.x, acc[0]);
+                    acc[1] = fmaf(wq, p.y, acc[1]);
+                    acc[2] = fmaf(wq, p.z, acc[2]);
+                    acc[3] = fmaf(wq, p.w, acc[3]);
+                }
+            }
+        phi = acc[0];
+        G[0] = acc[1]; G[1] = acc[2]; G[2] = acc[3];
+        return 0;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Geodesic state in the split representation.  With K = -k0 > 0,
 // k = K (n + d) and x = x_obs + s n + dx, the null geodesic equations of
@@ -399,16 +582,17 @@ __device__ __forceinline__ void grid_coords(const GridDev& g, const RayGeom& r, 
 
 // No-op stage recorder of the forward kernels.
 struct NoRecord {
-    __device__ __forceinline__ void stage(int, const GeoState&, const FieldCache<true>&, const float*) {}
-    __device__ __forceinline__ void stage(int, const GeoState&, const FieldCache<false>&, const float*) {}
+    template <class FC>
+    __device__ __forceinline__ void stage(int, const GeoState&, const FC&, const float*) {}
 };
 
-// One RK4 step of affine length dl from y into out.  The four stencil levels
+// One RK4 step of affine length dl from y into out (F: the lane's field
+// evaluator, any interpolation order).  The four stencil levels
 // are appended to hash only when all four stages succeed (return 0).  When
 // record is set, the recorder receives every stage's state and stencil (base
 // id, level); the reverse sweep uses it to replay the forward stages exactly.
-template <bool AMR, class Rec>
-__device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FieldCache<AMR>& F,
+template <class FC, class Rec>
+__device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
                                         uint32_t& hash, Rec& rec, bool record)
 {
@@ -493,13 +677,13 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, Fi
     return 0;
 }
 
-template <bool AMR>
-__device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FieldCache<AMR>& F,
+template <class FC>
+__device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
                                         uint32_t& hash)
 {
     NoRecord none;
-    return rk4_step<AMR, NoRecord>(g, cz, F, r, y, dl, out, hash, none, false);
+    return rk4_step<FC, NoRecord>(g, cz, F, r, y, dl, out, hash, none, false);
 }
 
 // NaN or infinity anywhere in the state (a sum of the small FP32 parts is

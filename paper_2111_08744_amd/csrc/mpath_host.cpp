@@ -451,7 +451,9 @@ int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_ra
     if (d->nside < 1 || d->nside > 8192) return fail(MPATH_ERR_INVALID_ARG, "nside must be in [1, 8192]");
     if (!d->dirs && (d->pix_first == nullptr) != (d->pix_count == nullptr))
         return fail(MPATH_ERR_INVALID_ARG, "pix_first and pix_count must both be given or both NULL");
-    if (d->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "only order = 1 (CIC) is implemented");
+    if (d->order < 0 || d->order > 2) return fail(MPATH_ERR_INVALID_ARG, "order must be 0 (NGP), 1 (CIC) or 2 (TSC)");
+    if (d->order != 1 && d->checkpoint_every > 0)
+        return fail(MPATH_ERR_UNSUPPORTED, "checkpoints (the adjoint) need order = 1 (CIC)");
     if (d->steps_per_cell < 1) return fail(MPATH_ERR_INVALID_ARG, "steps_per_cell must be >= 1");
     if (d->max_steps < 1) return fail(MPATH_ERR_INVALID_ARG, "max_steps must be >= 1");
     if (d->stop_kind != MPATH_STOP_REDSHIFT && d->stop_kind != MPATH_STOP_CHI)
@@ -667,6 +669,8 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
     }
     if (inf) {
         e = launch_cast_infbeam(a, inf_A, s);
+    } else if (d->order != 1) {
+        e = launch_cast_order(a, d->order, s);
     } else if (d->checkpoint_every > 0) {
         e = launch_cast_checkpointed(a, s);
     } else {
@@ -708,6 +712,7 @@ int mpath_infinitesimal_beam(const mpath_grid* g, const mpath_cast_desc* d, mpat
     if (n_rays > 0 && !A) return fail(MPATH_ERR_INVALID_ARG, "A is NULL");
     if (d->checkpoint_every != 0)
         return fail(MPATH_ERR_INVALID_ARG, "the infinitesimal-beam cast stores no checkpoints (checkpoint_every 0)");
+    if (d->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "the infinitesimal beam is implemented for order = 1 (CIC)");
     return cast_impl(g, d, out, dev_ws, ws_bytes, stream, true, A);
 }
 
