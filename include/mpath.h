@@ -181,10 +181,21 @@ typedef struct {
        observer j.  The array is read during the call (copied to the
        workspace before the integration starts). */
     const double* dirs;
+    /* intermediate stop surfaces (the maps at several source redshifts of one
+       run): 0 = none; else n_surfaces (<= 64) more surfaces per observer,
+       HOST surface_stops[n_obs][n_surfaces] of stop_kind, nearest first and
+       each nearer than stop_value[j].  Every photon lands exactly on each
+       surface in turn (as on its final stop) and continues from there; the
+       outputs then hold n_surfaces + 1 blocks of n_rays entries, block k
+       for surface k and the last block for stop_value (steps and hash
+       cumulative).  Static schedule; order 1 and checkpoint_every 0 only. */
+    int32_t n_surfaces;
+    const double* surface_stops;
 } mpath_cast_desc;
 
 /* Per-ray outputs: caller-allocated DEVICE arrays of length n_rays
- * (= sum pix_count).  Any pointer may be NULL (not written).
+ * (= sum pix_count; (n_surfaces + 1) n_rays with intermediate surfaces).
+ * Any pointer may be NULL (not written).
  *   beta[2]     (polar, azimuth) of x_s - x_obs (lens equation, Sect. 2.3)
  *   alpha[2]    deflection theta - beta as a tangent vector at theta of length
  *               the great-circle angle, on e1 = e_phi(theta), e2 = -e_theta(theta)
@@ -407,6 +418,22 @@ int mpath_find_geodesics_workspace_bytes(const mpath_grid* grid, const mpath_fin
  * background table, z > 20), WORKSPACE_TOO_SMALL, DEVICE. */
 int mpath_find_geodesics(const mpath_grid* grid, const mpath_finder_desc* desc, mpath_finder_out* out,
                          void* dev_ws, size_t ws_bytes, void* stream);
+
+/* mpath_born_beam: the Born approximation of the infinitesimal-beam matrix
+ * (Sect. 2.3.1 and the comparison of Sect. 3.6): the same line-of-sight
+ * integral taken along the straight line x_obs + chi n from the observer to
+ * the stop surface's comoving distance chi_s = eta_0 - eta_s, with n the
+ * ray's initial direction (pixel centre or desc->dirs: pass the source
+ * directions beta there for the Born approximation in the direction of the
+ * sources).  Samples at chi_{i+1} = min(chi_i + ds_i, chi_s), ds_i the
+ * integration's step length (h / N) at x(chi_i); trapezoid rule in chi.
+ *   A:      DEVICE float[n_rays][2][2], written (NaN if the line leaves a
+ *           non-periodic box or exceeds max_steps samples).
+ *   status: DEVICE int32[n_rays] or NULL (MPATH_RAY_*).
+ *   dev_ws: mpath_cast_workspace_bytes of desc (checkpoint_every 0).
+ * Errors: as mpath_cast; UNSUPPORTED for order != 1. */
+int mpath_born_beam(const mpath_grid* grid, const mpath_cast_desc* desc, float* A, int32_t* status, void* dev_ws,
+                    size_t ws_bytes, void* stream);
 
 /* ---- measurement utility (not a step of the method) ----
  *

@@ -110,6 +110,10 @@ def lib():
         L.or_cast_cs.argtypes = [vp, C.POINTER(Cosmo), C.POINTER(CastParams), i64, vp, vp, vp, vp, vp, vp, C.c_int]
         L.or_infinitesimal.restype = C.c_int
         L.or_infinitesimal.argtypes = [vp, C.POINTER(Cosmo), C.POINTER(CastParams), i64, vp, C.c_double, vp, vp, C.c_int]
+        L.or_cast_surfaces.restype = C.c_int
+        L.or_cast_surfaces.argtypes = [vp, C.POINTER(Cosmo), C.POINTER(CastParams), C.c_int, vp, i64, vp, vp, C.c_int]
+        L.or_born.restype = C.c_int
+        L.or_born.argtypes = [vp, C.POINTER(Cosmo), C.POINTER(CastParams), i64, vp, C.c_double, vp, vp, C.c_int]
         L.or_integrate_steps.restype = C.c_int
         L.or_integrate_steps.argtypes = [vp, C.POINTER(Cosmo), dp, i64, vp]
         _lib = L
@@ -254,6 +258,33 @@ def infinitesimal(field: Field, c: Cosmo, p: CastParams, dirs, h_deriv: float = 
                                 _ptr(A), _ptr(out), threads or default_threads())
     if rc:
         raise ValueError("or_infinitesimal rejected its arguments")
+    return A, out
+
+
+def cast_surfaces(field: Field, c: Cosmo, p: CastParams, stops, dirs, threads: int | None = None) -> np.ndarray:
+    """Records [n_surf, n_rays] of one cast through several stop surfaces
+    (stops of p's stop kind, nearest first)."""
+    stops = np.ascontiguousarray(np.atleast_1d(stops), np.float64)
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    out = np.zeros((len(stops), len(dirs)), RAY_DTYPE)
+    rc = lib().or_cast_surfaces(field._h, C.byref(c), C.byref(p), len(stops), _ptr(stops), len(dirs), _ptr(dirs),
+                                _ptr(out), threads or default_threads())
+    if rc:
+        raise ValueError("or_cast_surfaces rejected its arguments")
+    return out
+
+
+def born(field: Field, c: Cosmo, p: CastParams, dirs, h_deriv: float = 0.0, threads: int | None = None):
+    """Born-approximation distortion matrices along the straight lines x_obs +
+    chi n to the stop surface (or_born); returns (A [n, 2, 2], records with
+    status and n_steps)."""
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    A = np.zeros((len(dirs), 2, 2))
+    out = np.zeros(len(dirs), RAY_DTYPE)
+    rc = lib().or_born(field._h, C.byref(c), C.byref(p), len(dirs), _ptr(dirs), h_deriv,
+                       _ptr(A), _ptr(out), threads or default_threads())
+    if rc:
+        raise ValueError("or_born rejected its arguments")
     return A, out
 
 

@@ -461,7 +461,9 @@ typedef struct {
     or_ray_tan* tan;
     double* A;            /* infinitesimal-beam output */
     double h_deriv;
-    int mode;             /* 0 values, 1 complex step, 2 infinitesimal beam */
+    int mode;             /* 0 values, 1 complex step, 2 infinitesimal beam, 3 Born beam, 4 surfaces */
+    int n_surf;           /* mode 4: stop surfaces, nearest first, and their outputs [n_surf][n_rays] */
+    const derived_t* dvs;
     int64_t next;
     pthread_mutex_t lock;
 } job_t;
@@ -579,6 +581,64 @@ static void* worker(void* arg)
                     I22 += dc * (w0 * s0[3] + w1 * s1[3]);
                 }
                 A[0] = 1.0 - 2.0 * I11; A[1] = -2.0 * I12; A[2] = -2.0 * I12; A[3] = 1.0 - 2.0 * I22;
+            } else if (J->mode == 4) {
+                /* one photon through several stop surfaces: land on each in turn
+                 * (the landing step ends exactly on it), record the observables
+                 * there, and continue from the landed state to the next */
+                trace_t_r R;
+                const int bad = trace_start_r(J->f, &J->ctx, J->p, &J->dvs[0], n, &R);
+                for (int k = 0; k < J->n_surf; ++k) {
+                    if (!bad && (k == 0 || R.status == OR_REACHED)) {
+                        R.status = -1;
+                        trace_run_r(J->f, &J->ctx, J->c, J->p, &J->dvs[k], &R, NULL, NULL);
+                        trace_end_r(J->f, &J->ctx, &R, NULL, NULL);
+                    }
+                    observe_r(J->p, &J->dvs[k], n, &R, J->out + (int64_t)k * J->n_rays + r, NULL);
+                }
+            } else if (J->mode == 3) {
+                /* Born approximation: the same line-of-sight integral along the
+                 * straight line x = x_obs + chi n, sampled with the step rule of
+                 * the integration (h_leaf / N, or ds for closed-form fields) from
+                 * chi = 0 to the stop surface's comoving distance */
+                acc.f = J->f; acc.obs = J->p->obs; acc.n = n; acc.h_deriv = J->h_deriv;
+                acc.len = 0; acc.bad = 0;
+                const double chis = J->dv.eta0 - J->dv.eta_s;
+                double chi = 0.0;
+                int status = OR_MAX_STEPS;
+                int64_t steps = 0;
+                for (;;) {
+                    double y[S_N] = {0};
+                    for (int i = 0; i < 3; ++i) y[S_X + i] = J->p->obs[i] + chi * n[i];
+                    double ds = J->p->ds_analytic;
+                    if (J->f->kind == OR_FIELD_GRID) {
+                        double u[3] = {y[S_X] / J->f->h0, y[S_X + 1] / J->f->h0, y[S_X + 2] / J->f->h0};
+                        const int leaf = leaf_level(J->f, u);
+                        if (leaf < 0) { status = OR_LEFT_DOMAIN; break; }
+                        const int lstep = J->p->adaptive ? leaf : 0;
+                        ds = J->f->h0 / ldexp(1.0, lstep) / (double)J->p->steps_per_cell;
+                    }
+                    inf_sample(&acc, y);
+                    if (chi >= chis) { status = OR_REACHED; break; }
+                    if (steps >= J->p->max_steps) break;
+                    chi = chi + ds < chis ? chi + ds : chis;
+                    ++steps;
+                }
+                if (J->out) { memset(J->out + r, 0, sizeof(or_ray_out)); J->out[r].status = status; J->out[r].n_steps = steps; }
+                double* A = J->A + 4 * r;
+                A[0] = 1.0; A[1] = 0.0; A[2] = 0.0; A[3] = 1.0;
+                if (status != OR_REACHED || acc.len < 2) continue;
+                const double cs = acc.s[4 * (acc.len - 1)];
+                double I11 = 0.0, I12 = 0.0, I22 = 0.0;
+                for (int64_t i = 0; i + 1 < acc.len; ++i) {
+                    const double* s0 = acc.s + 4 * i;
+                    const double* s1 = acc.s + 4 * (i + 1);
+                    const double w0 = (cs - s0[0]) * s0[0] / cs, w1 = (cs - s1[0]) * s1[0] / cs;
+                    const double dc = 0.5 * (s1[0] - s0[0]);
+                    I11 += dc * (w0 * s0[1] + w1 * s1[1]);
+                    I12 += dc * (w0 * s0[2] + w1 * s1[2]);
+                    I22 += dc * (w0 * s0[3] + w1 * s1[3]);
+                }
+                A[0] = 1.0 - 2.0 * I11; A[1] = -2.0 * I12; A[2] = -2.0 * I12; A[3] = 1.0 - 2.0 * I22;
             } else {
                 trace_t_r R;
                 trace_r(J->f, &J->ctx, J->c, J->p, &J->dv, n, &R, NULL, NULL);
@@ -644,6 +704,35 @@ int or_infinitesimal(const or_field* f, const or_cosmo* c, const or_cast_params*
     if (setup(&J, f, c, p, n_rays, dirs) || !A) return -1;
     J.A = A; J.out = out; J.h_deriv = h_deriv;
     J.mode = 2;
+    return run_job(&J, n_threads);
+}
+
+int or_cast_surfaces(const or_field* f, const or_cosmo* c, const or_cast_params* p, int n_surf,
+                     const double* stops, int64_t n_rays, const double* dirs, or_ray_out* out, int n_threads)
+{
+    job_t J;
+    if (n_surf < 1 || n_surf > 64 || !stops || setup(&J, f, c, p, n_rays, dirs) || !out) return -1;
+    derived_t dvs[64];
+    for (int k = 0; k < n_surf; ++k) {
+        or_cast_params q = *p;
+        q.stop_value = stops[k];
+        if (derive(c, &q, &dvs[k])) return -1;
+        if (k > 0 && !(dvs[k].eta_s < dvs[k - 1].eta_s)) return -1;   /* nearest first */
+    }
+    J.out = out;
+    J.n_surf = n_surf;
+    J.dvs = dvs;
+    J.mode = 4;
+    return run_job(&J, n_threads);
+}
+
+int or_born(const or_field* f, const or_cosmo* c, const or_cast_params* p, int64_t n_rays,
+            const double* dirs, double h_deriv, double* A, or_ray_out* out, int n_threads)
+{
+    job_t J;
+    if (setup(&J, f, c, p, n_rays, dirs) || !A) return -1;
+    J.A = A; J.out = out; J.h_deriv = h_deriv;
+    J.mode = 3;
     return run_job(&J, n_threads);
 }
 

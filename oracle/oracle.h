@@ -117,6 +117,19 @@ int or_infinitesimal(const or_field* f, const or_cosmo* c, const or_cast_params*
 
 /* Plain RK4 over given affine steps from state y[8] = (eta, x, k0, k); used
  * by the time-reversal pin.  Returns 0 or the status of a failed stage. */
+/* One cast through several stop surfaces (stops[k], nearest first, of
+ * p->stop_kind; p->stop_value is not used): each photon lands on every
+ * surface in turn and continues from there.  out[k * n_rays + r] holds the
+ * observables of ray r on surface k (steps and hash cumulative). */
+int or_cast_surfaces(const or_field* f, const or_cosmo* c, const or_cast_params* p, int n_surf,
+                     const double* stops, int64_t n_rays, const double* dirs, or_ray_out* out, int n_threads);
+/* Born approximation of the same matrix: the line-of-sight integral of
+ * or_infinitesimal taken along the straight line x_obs + chi n (n = dirs[r])
+ * from chi = 0 to the stop surface's comoving distance eta_0 - eta_s, sampled
+ * at chi_{i+1} = min(chi_i + ds_i, chi_s) with ds_i the integration's step
+ * rule at x(chi_i).  out (optional) receives status and the sample count. */
+int or_born(const or_field* f, const or_cosmo* c, const or_cast_params* p, int64_t n_rays,
+            const double* dirs, double h_deriv, double* A, or_ray_out* out, int n_threads);
 int or_integrate_steps(const or_field* f, const or_cosmo* c, double* y, int64_t n, const double* dl);
 
 #ifdef __cplusplus

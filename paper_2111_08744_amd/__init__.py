@@ -25,7 +25,7 @@ from ._abi import (MPATH_RAY_LEFT_DOMAIN, MPATH_RAY_MAX_STEPS, MPATH_RAY_NONFINI
                    MPATH_SCHED_STATIC, MPATH_STOP_CHI, MPATH_STOP_REDSHIFT, MpathError)
 
 __all__ = ["Grid", "cast", "CastConfig", "adjoint", "autotune", "cast_differentiable", "library_path",
-           "lensing_maps", "finite_beam", "infinitesimal_beam", "find_geodesics",
+           "lensing_maps", "finite_beam", "infinitesimal_beam", "born_beam", "find_geodesics",
            "MpathError"]
 
 
@@ -130,7 +130,7 @@ class CastConfig:
 
     def __init__(self, obs, stop, nside, pix_first=None, pix_count=None, stop_kind="z",
                  steps_per_cell=10, adaptive=False, max_steps=1 << 40, schedule=0,
-                 block_size=0, waves_per_cu=0, batch=0, checkpoint_every=0, dirs=None, order=1):
+                 block_size=0, waves_per_cu=0, batch=0, checkpoint_every=0, dirs=None, order=1, surfaces=None):
         self.obs = np.ascontiguousarray(np.atleast_2d(obs), np.float64)
         self.stop = np.ascontiguousarray(np.atleast_1d(stop), np.float64)
         self.nside = int(nside)
@@ -147,6 +147,14 @@ class CastConfig:
         self.batch = int(batch)
         self.checkpoint_every = int(checkpoint_every)
         self.order = int(order)          # 0 NGP, 1 CIC, 2 TSC
+        # intermediate stop surfaces [n_obs, n_s] (or [n_s] for every observer),
+        # nearest first, each nearer than the observer's stop
+        if surfaces is not None:
+            sf = np.atleast_1d(np.asarray(surfaces, np.float64))
+            if sf.ndim == 1:
+                sf = np.tile(sf, (self.obs.shape[0], 1))
+            surfaces = np.ascontiguousarray(sf)
+        self.surfaces = surfaces
         # initial directions: None = NESTED pixel centres; else a float64 CUDA
         # tensor [n_rays, 3] of unit vectors (pix_count gives the rays per observer)
         if dirs is not None:
@@ -174,7 +182,13 @@ class CastConfig:
         d.batch = self.batch
         d.checkpoint_every = self.checkpoint_every
         d.dirs = self.dirs.data_ptr() if self.dirs is not None else None
+        d.n_surfaces = 0 if self.surfaces is None else self.surfaces.shape[1]
+        d.surface_stops = None if self.surfaces is None else self.surfaces.ctypes.data
         return d
+
+    def n_blocks(self) -> int:
+        """Output blocks of n_rays: one per stop surface."""
+        return 1 if self.surfaces is None else self.surfaces.shape[1] + 1
 
     def n_rays(self) -> int:
         n = C.c_int64()
@@ -218,7 +232,7 @@ def cast(grid: Grid, cfg: CastConfig, out=None, ws=None):
     if cfg.dirs is not None and cfg.dirs.shape[0] != n:
         raise ValueError(f"dirs has {cfg.dirs.shape[0]} rows for {n} rays")
     if out is None:
-        out = alloc_outputs(n, grid.device)
+        out = alloc_outputs(n * cfg.n_blocks(), grid.device)
     nbytes = C.c_size_t()
     _abi.check(L.mpath_cast_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)), "mpath_cast_workspace_bytes")
     if ws is None or ws.numel() < nbytes.value:
@@ -463,3 +477,24 @@ def find_geodesics(grid: Grid, obs, src, steps_per_cell=10, adaptive=False, tol=
                                           _stream_ptr(dev)), "mpath_find_geodesics")
     res["_ws"] = ws
     return res
+
+
+def born_beam(grid: Grid, cfg: CastConfig, ws=None):
+    """mpath_born_beam: Born-approximation distortion matrices [n_rays, 2, 2]
+    along the straight lines of cfg's initial directions, and the status."""
+    torch = _torch()
+    L = _abi.lib()
+    d = cfg.desc()
+    n = cfg.n_rays()
+    if cfg.dirs is not None and cfg.dirs.shape[0] != n:
+        raise ValueError(f"dirs has {cfg.dirs.shape[0]} rows for {n} rays")
+    nbytes = C.c_size_t()
+    _abi.check(L.mpath_cast_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)), "mpath_cast_workspace_bytes")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=grid.device)
+    A = torch.empty((n, 2, 2), dtype=torch.float32, device=grid.device)
+    st = torch.empty((n,), dtype=torch.int32, device=grid.device)
+    with torch.cuda.device(grid.device):
+        _abi.check(L.mpath_born_beam(grid.handle, C.byref(d), _ptr(A), _ptr(st), _ptr(ws), ws.numel(),
+                                     _stream_ptr(grid.device)), "mpath_born_beam")
+    return {"A": A, "status": st, "_ws": ws}

@@ -55,7 +55,8 @@ class mpath_cast_desc(C.Structure):
                 ("pix_count", C.c_void_p), ("order", C.c_int32), ("steps_per_cell", C.c_int32),
                 ("adaptive", C.c_int32), ("max_steps", C.c_int64), ("schedule", C.c_int32),
                 ("block_size", C.c_int32), ("waves_per_cu", C.c_int32), ("batch", C.c_int32),
-                ("checkpoint_every", C.c_int32), ("dirs", C.c_void_p)]
+                ("checkpoint_every", C.c_int32), ("dirs", C.c_void_p), ("n_surfaces", C.c_int32),
+                ("surface_stops", C.c_void_p)]
 
 
 class mpath_observables(C.Structure):
@@ -114,6 +115,7 @@ def lib():
         L.mpath_infinitesimal_beam.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp, vp, sz, vp]
         L.mpath_find_geodesics_workspace_bytes.argtypes = [vp, P(mpath_finder_desc), P(sz)]
         L.mpath_find_geodesics.argtypes = [vp, P(mpath_finder_desc), P(mpath_finder_out), vp, sz, vp]
+        L.mpath_born_beam.argtypes = [vp, P(mpath_cast_desc), vp, vp, vp, sz, vp]
         L.mpath_gather_probe.argtypes = [vp, sz, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_uint32, vp, vp]
         L.mpath_status_string.restype = C.c_char_p
         L.mpath_status_string.argtypes = [C.c_int]
@@ -124,7 +126,8 @@ def lib():
                      "mpath_cast", "mpath_cast_count_rays", "mpath_adjoint_workspace_bytes",
                      "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune", "mpath_gather_probe",
                      "mpath_lensing_maps", "mpath_finite_beam_workspace_bytes", "mpath_finite_beam",
-                     "mpath_infinitesimal_beam", "mpath_find_geodesics_workspace_bytes", "mpath_find_geodesics"):
+                     "mpath_infinitesimal_beam", "mpath_find_geodesics_workspace_bytes", "mpath_find_geodesics",
+                     "mpath_born_beam"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

@@ -30,6 +30,8 @@ constexpr int kMinWavesPerSimd = 4;
 // Step-start hook of RayRun::advance that does nothing (plain casts).
 struct NoSample {
     __device__ __forceinline__ void at_step(const CastArgs&, const RayGeom&, const GeoState&, int) {}
+    template <class Run>
+    __device__ __forceinline__ bool at_surface(const CastArgs&, Run&) { return false; }
 };
 
 // Everything one lane carries for its current ray.
@@ -129,6 +131,8 @@ struct RayRun {
             if (landing) {
                 y = yn;
                 ++n_steps;
+                if constexpr (!std::is_same<Smp, NoSample>::value)
+                    if (fin && smp.at_surface(a, *this)) continue;   // on to the next stop surface
                 status = fin ? MPATH_RAY_REACHED : MPATH_RAY_NONFINITE;
                 return true;
             }
@@ -147,26 +151,35 @@ struct RayRun {
         int j = a.n_obs - 1;
         while (j > 0 && a.obs[j].ray_first > ray) --j;
         const ObsDev& ob = a.obs[j];
+        const double a_s = a.ray_stop ? a.ray_stop[ray].y : ob.a_s;
+        write_outputs(a, ray, j, a_s, a.ray_stop ? 1.0 / a_s - 1.0 : ob.z0, status);
+    }
+
+    // Outputs of the current state at output slot `slot` (observer j, stop
+    // surface with scale factor a_s and FLRW redshift z0) with ray status st
+    // (MPATH_RAY_REACHED: the ray is on that surface).
+    __device__ __forceinline__ void write_outputs(const CastArgs& a, int64_t slot, int j, double a_s, double z0,
+                                                  int st)
+    {
+        const bool ok = st == MPATH_RAY_REACHED;
         double v[3];
         grid_coords(a.grid, geo, y.eta, y.dx, v);
         float phi_s = __builtin_nanf(""), G[3];
         int leafl, l;
         if (F.eval(a.grid, v, phi_s, G, leafl, l)) phi_s = __builtin_nanf("");
         const OutDev& o = a.out;
-        const bool ok = status == MPATH_RAY_REACHED;
-        const double a_s = a.ray_stop ? a.ray_stop[ray].y : ob.a_s;
         if (o.z5)
-            o.z5[ray] = ok ? a_s * y.K * (1.0 + (double)phi_s) / (1.0 + (double)phi_o) - 1.0 : __builtin_nan("");
-        if (o.z0) o.z0[ray] = ok ? (a.ray_stop ? 1.0 / a_s - 1.0 : ob.z0) : __builtin_nan("");
-        if (o.phi_src) o.phi_src[ray] = phi_s;
-        if (o.n_steps) o.n_steps[ray] = (int32_t)n_steps;
-        if (o.status) o.status[ray] = status;
-        if (o.hash) o.hash[ray] = hash;
+            o.z5[slot] = ok ? a_s * y.K * (1.0 + (double)phi_s) / (1.0 + (double)phi_o) - 1.0 : __builtin_nan("");
+        if (o.z0) o.z0[slot] = ok ? z0 : __builtin_nan("");
+        if (o.phi_src) o.phi_src[slot] = phi_s;
+        if (o.n_steps) o.n_steps[slot] = (int32_t)n_steps;
+        if (o.status) o.status[slot] = st;
+        if (o.hash) o.hash[slot] = hash;
         RayEnd e;
         e.eta = y.eta;
         e.dx[0] = y.dx[0]; e.dx[1] = y.dx[1]; e.dx[2] = y.dx[2];
         e.obs = j;
-        a.ends[ray] = e;
+        a.ends[slot] = e;
     }
 };
 
@@ -381,6 +394,9 @@ struct InfBeam {
         ++n;
     }
 
+    template <class Run>
+    __device__ __forceinline__ bool at_surface(const CastArgs&, Run&) { return false; }
+
     // A at the end of a ray that reached the source (after the end-point
     // sample); NaN otherwise or without two samples.
     __device__ __forceinline__ void write(float* A, bool reached) const
@@ -424,6 +440,106 @@ __global__ __launch_bounds__(kBlock, 2) void cast_infbeam_kernel(CastArgs a, flo
     }
     B.write(A + 4 * r, reached);
     R.finish(a);
+}
+
+// Intermediate stop surfaces of a cast (the paper's maps at several source
+// redshifts from one run): landing on surface k < n_extra writes the ray's
+// observables there to output block k and sends the ray on to surface k + 1;
+// the observer's own stop is the last surface (block n_extra).
+struct Surfaces {
+    const double2* surf;    // [n_obs][n_extra] (eta_s, a_s), nearest first
+    int n_extra;
+    int k;
+
+    __device__ __forceinline__ void at_step(const CastArgs&, const RayGeom&, const GeoState&, int) {}
+
+    template <class Run>
+    __device__ __forceinline__ bool at_surface(const CastArgs& a, Run& R)
+    {
+        if (k >= n_extra) return false;
+        int j = a.n_obs - 1;
+        while (j > 0 && a.obs[j].ray_first > R.ray) --j;
+        const double a_s = surf[j * n_extra + k].y;
+        R.write_outputs(a, (int64_t)k * a.n_rays + R.ray, j, a_s, 1.0 / a_s - 1.0, MPATH_RAY_REACHED);
+        ++k;
+        R.eta_s = k < n_extra ? surf[j * n_extra + k].x : a.obs[j].eta_s;
+        return true;
+    }
+};
+
+template <bool AMR>
+__global__ __launch_bounds__(kBlock, 2) void cast_surfaces_kernel(CastArgs a, Surfaces S)
+{
+    extern __shared__ float coef_lds[];
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    RayRun<AMR> R;
+    R.F.bind(coef_lds + threadIdx.x);
+    R.start(a, r);
+    int j = a.n_obs - 1;
+    while (j > 0 && a.obs[j].ray_first > r) --j;
+    R.eta_s = S.surf[j * S.n_extra].x;
+    S.k = 0;
+    R.template advance<false, Surfaces>(a, 0x7fffffff, S);
+    // a ray that stopped before some surface: those slots get its status
+    for (int k = S.k; k < S.n_extra; ++k) {
+        const double a_s = S.surf[j * S.n_extra + k].y;
+        R.write_outputs(a, (int64_t)k * a.n_rays + r, j, a_s, 1.0 / a_s - 1.0, R.status);
+    }
+    const ObsDev& ob = a.obs[j];
+    R.write_outputs(a, (int64_t)S.n_extra * a.n_rays + r, j, ob.a_s, ob.z0, R.status);
+}
+
+// Born approximation of the infinitesimal-beam matrix: the same
+// line-of-sight integral taken along the straight line x_obs + chi n from the
+// observer to the stop surface's comoving distance chi_s = eta_0 - eta_s,
+// sampled at chi_{i+1} = min(chi_i + ds_i, chi_s), ds_i the integration's
+// step length at x(chi_i) (N steps per leaf or coarse cell).
+template <bool AMR>
+__global__ __launch_bounds__(kBlock, 2) void born_beam_kernel(CastArgs a, float* A, int32_t* status_out)
+{
+    extern __shared__ float born_lds[];
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    const GridDev& g = a.grid;
+    int j = a.n_obs - 1;
+    while (j > 0 && a.obs[j].ray_first > r) --j;
+    const ObsDev& ob = a.obs[j];
+    RayGeom geo;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        geo.vo[i] = ldexp(ob.x[i] / g.h0, g.max_level + 1);
+        geo.n[i] = a.dirs[3 * r + i];
+    }
+    const double eta_s = a.ray_stop ? a.ray_stop[r].x : ob.eta_s;
+    const double chis = a.cosmo_eta0 - eta_s;
+    InfBeam<AMR> B;
+    B.init(born_lds + threadIdx.x);
+    FieldCache<AMR> F;          // leaf lookups only (no stencil, no LDS)
+    F.reset();
+    GeoState y;
+    y.K = 1.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { y.d[i] = 0.0f; y.dx[i] = 0.0f; }
+    double chi = 0.0;
+    int status = MPATH_RAY_MAX_STEPS;
+    for (int64_t steps = 0;; ++steps) {
+        y.eta = a.cosmo_eta0 - chi;
+        double v[3];
+        grid_coords(g, geo, y.eta, y.dx, v);
+        int I[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
+        const int L = F.leaf(g, I);
+        if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; break; }
+        B.at_step(a, geo, y, L);
+        if (chi >= chis) { status = MPATH_RAY_REACHED; break; }
+        if (steps >= a.max_steps) break;
+        const double ds = a.ds_level[L];
+        chi = chi + ds < chis ? chi + ds : chis;
+    }
+    B.write(A + 4 * r, status == MPATH_RAY_REACHED);
+    if (status_out) status_out[r] = status;
 }
 
 // Static schedule with the NGP (ORDER 0) or TSC (ORDER 2) field evaluator.
@@ -501,6 +617,34 @@ hipError_t launch_cast_order(const CastArgs& a, int order, hipStream_t s)
         if (amr) hipLaunchKernelGGL((cast_order_kernel<true, 2>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((cast_order_kernel<false, 2>), grid, block, lds, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_born_beam(const CastArgs& a, float* A, int32_t* status, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
+    const size_t lds = (size_t)32 * kBlock * sizeof(float);
+    if (a.grid.max_level > 0)
+        hipLaunchKernelGGL(born_beam_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, A, status);
+    else
+        hipLaunchKernelGGL(born_beam_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, A, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_surfaces(const CastArgs& a, const double2* surf, int n_extra, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
+    const size_t lds = (size_t)32 * kBlock * sizeof(float);
+    Surfaces S;
+    S.surf = surf;
+    S.n_extra = n_extra;
+    S.k = 0;
+    if (a.grid.max_level > 0)
+        hipLaunchKernelGGL(cast_surfaces_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, S);
+    else
+        hipLaunchKernelGGL(cast_surfaces_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, S);
     return hipGetLastError();
 }
 

@@ -138,6 +138,8 @@ hipError_t launch_observables(const CastArgs& a, hipStream_t s);
 hipError_t launch_ray_dirs(const CastArgs& a, hipStream_t s);
 hipError_t launch_cast_infbeam(const CastArgs& a, float* A, hipStream_t s);
 hipError_t launch_cast_order(const CastArgs& a, int order, hipStream_t s);
+hipError_t launch_born_beam(const CastArgs& a, float* A, int32_t* status, hipStream_t s);
+hipError_t launch_cast_surfaces(const CastArgs& a, const double2* surf, int n_extra, hipStream_t s);
 hipError_t launch_permute_values(float4* payload, const int64_t* perm, const float4* values,
                                  int64_t n, hipStream_t s);
 // Derived tables (defined in grid.hip); cellpos[c] = (i, j, k, level).

@@ -423,19 +423,20 @@ int mpath_grid_set_values(mpath_grid* g, const float* values, void* stream)
 namespace {
 
 struct CastLayout {
-    size_t off_obs, off_queue, off_ends, off_dirs, off_ckpt, total;
+    size_t off_obs, off_surf, off_queue, off_ends, off_dirs, off_ckpt, total;
     int64_t ckpt_slots;
 };
 
 // Cast workspace: observer table, queue counter, per-ray end states, initial
 // directions and, for a checkpointed cast, ckpt_slots states per ray.
-CastLayout cast_layout(int64_t n_obs, int64_t n_rays, int64_t ckpt_slots)
+CastLayout cast_layout(int64_t n_obs, int64_t n_rays, int64_t ckpt_slots, int n_surf = 0)
 {
     CastLayout L;
     L.off_obs = 0;
-    L.off_queue = align_up((size_t)n_obs * sizeof(ObsDev), 256);
+    L.off_surf = align_up((size_t)n_obs * sizeof(ObsDev), 256);
+    L.off_queue = align_up(L.off_surf + (size_t)n_obs * n_surf * sizeof(double2), 256);
     L.off_ends = align_up(L.off_queue + 256, 256);
-    L.off_dirs = align_up(L.off_ends + (size_t)n_rays * sizeof(RayEnd), 256);
+    L.off_dirs = align_up(L.off_ends + (size_t)(n_surf + 1) * n_rays * sizeof(RayEnd), 256);
     L.off_ckpt = align_up(L.off_dirs + (size_t)n_rays * 24, 256);
     L.ckpt_slots = ckpt_slots;
     L.total = align_up(L.off_ckpt + (size_t)ckpt_slots * (size_t)n_rays * sizeof(GeoState), 256);
@@ -454,6 +455,12 @@ int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_ra
     if (d->order < 0 || d->order > 2) return fail(MPATH_ERR_INVALID_ARG, "order must be 0 (NGP), 1 (CIC) or 2 (TSC)");
     if (d->order != 1 && d->checkpoint_every > 0)
         return fail(MPATH_ERR_UNSUPPORTED, "checkpoints (the adjoint) need order = 1 (CIC)");
+    if (d->n_surfaces < 0 || d->n_surfaces > 64) return fail(MPATH_ERR_INVALID_ARG, "n_surfaces must be in [0, 64]");
+    if (d->n_surfaces > 0) {
+        if (!d->surface_stops) return fail(MPATH_ERR_INVALID_ARG, "surface_stops is NULL");
+        if (d->checkpoint_every > 0 || d->order != 1)
+            return fail(MPATH_ERR_UNSUPPORTED, "several stop surfaces need order = 1 and no checkpoints");
+    }
     if (d->steps_per_cell < 1) return fail(MPATH_ERR_INVALID_ARG, "steps_per_cell must be >= 1");
     if (d->max_steps < 1) return fail(MPATH_ERR_INVALID_ARG, "max_steps must be >= 1");
     if (d->stop_kind != MPATH_STOP_REDSHIFT && d->stop_kind != MPATH_STOP_CHI)
@@ -577,7 +584,38 @@ int cast_plan(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_rays, st
     if (rc) return rc;
     const int64_t slots = checkpoint_slots(g, d, obs);
     if (slots > (int64_t)1 << 30) return fail(MPATH_ERR_INVALID_ARG, "too many checkpoints: lower max_steps");
-    *lay = cast_layout(d->n_obs, *n_rays, slots);
+    *lay = cast_layout(d->n_obs, *n_rays, slots, d->n_surfaces);
+    return MPATH_OK;
+}
+
+// (eta_s, a_s) of the intermediate stop surfaces, [n_obs][n_surfaces],
+// nearest first and each nearer than the observer's own stop.
+int make_surface_table(const mpath_grid* g, const mpath_cast_desc* d, const std::vector<ObsDev>& obs,
+                       std::vector<double2>& surf)
+{
+    const int n = d->n_surfaces;
+    surf.assign((size_t)d->n_obs * n, make_double2(0.0, 0.0));
+    for (int j = 0; j < d->n_obs; ++j) {
+        double prev = g->eta0;
+        for (int k = 0; k < n; ++k) {
+            const double v = d->surface_stops[(size_t)j * n + k];
+            double eta_s, a_s;
+            if (d->stop_kind == MPATH_STOP_REDSHIFT) {
+                if (!(v > 0.0)) return fail(MPATH_ERR_INVALID_ARG, "surface redshifts must be > 0");
+                a_s = 1.0 / (1.0 + v);
+                eta_s = g->bg.eta_of_a(a_s);
+            } else {
+                if (!(v > 0.0)) return fail(MPATH_ERR_INVALID_ARG, "surface distances must be > 0");
+                eta_s = g->eta0 - v;
+                a_s = g->bg.a_of_eta(eta_s);
+            }
+            if (!(eta_s < prev) || !(eta_s > obs[j].eta_s))
+                return fail(MPATH_ERR_INVALID_ARG,
+                            "surfaces must increase in distance and lie nearer than the observer's stop");
+            surf[(size_t)j * n + k] = make_double2(eta_s, a_s);
+            prev = eta_s;
+        }
+    }
     return MPATH_OK;
 }
 
@@ -667,6 +705,27 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
         e = launch_ray_dirs(a, s);
         if (e) return hip_fail(e, "ray directions launch");
     }
+    if (d->n_surfaces > 0) {
+        if (inf || ray_stop) return fail(MPATH_ERR_UNSUPPORTED, "several stop surfaces in a plain cast only");
+        std::vector<double2> surf;
+        rc = make_surface_table(g, d, obs, surf);
+        if (rc) return rc;
+        e = hipMemcpyAsync(ws + lay.off_surf, surf.data(), surf.size() * sizeof(double2), hipMemcpyHostToDevice, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (!e) e = launch_cast_surfaces(a, (const double2*)(ws + lay.off_surf), d->n_surfaces, s);
+        // the observables of each surface block
+        for (int k = 0; !e && k <= d->n_surfaces; ++k) {
+            CastArgs ak = a;
+            const int64_t o = (int64_t)k * n_rays;
+            ak.ends = a.ends + o;
+            if (ak.out.beta) ak.out.beta += 2 * o;
+            if (ak.out.alpha) ak.out.alpha += 2 * o;
+            if (ak.out.chi) ak.out.chi += o;
+            e = launch_observables(ak, s);
+        }
+        if (e) return hip_fail(e, "cast launch");
+        return MPATH_OK;
+    }
     if (inf) {
         e = launch_cast_infbeam(a, inf_A, s);
     } else if (d->order != 1) {
@@ -701,6 +760,34 @@ int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables*
                size_t ws_bytes, void* stream)
 {
     return cast_impl(g, d, out, dev_ws, ws_bytes, stream, false, nullptr);
+}
+
+int mpath_born_beam(const mpath_grid* g, const mpath_cast_desc* d, float* A, int32_t* status, void* dev_ws,
+                    size_t ws_bytes, void* stream)
+{
+    int64_t n_rays;
+    std::vector<ObsDev> obs;
+    CastLayout lay;
+    int rc = cast_plan(g, d, &n_rays, obs, &lay);
+    if (rc) return rc;
+    if (d->checkpoint_every != 0) return fail(MPATH_ERR_INVALID_ARG, "the Born beam takes checkpoint_every 0");
+    if (d->n_surfaces) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam takes one stop surface");
+    if (d->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam is implemented for order = 1 (CIC)");
+    if (n_rays > 0 && !A) return fail(MPATH_ERR_INVALID_ARG, "A is NULL");
+    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
+    if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "cast workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dev_ws;
+    hipError_t e = hipMemcpyAsync(ws + lay.off_obs, obs.data(), obs.size() * sizeof(ObsDev), hipMemcpyHostToDevice, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return hip_fail(e, "observer table upload");
+    CastArgs a = make_cast_args(g, d, lay, ws, n_rays);
+    if (d->dirs)
+        e = n_rays ? hipMemcpyAsync(a.dirs, d->dirs, (size_t)n_rays * 24, hipMemcpyDeviceToDevice, s) : hipSuccess;
+    else
+        e = launch_ray_dirs(a, s);
+    if (!e) e = launch_born_beam(a, A, status, s);
+    return e ? hip_fail(e, "Born beam launch") : MPATH_OK;
 }
 
 int mpath_infinitesimal_beam(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, float* A,
@@ -949,6 +1036,7 @@ int beam_plan(const mpath_grid* g, const mpath_cast_desc* d, BeamPlan& P)
 {
     int rc = check_cast_desc(g, d, &P.n_rays);
     if (rc) return rc;
+    if (d->n_surfaces) return fail(MPATH_ERR_UNSUPPORTED, "the finite beam takes one stop surface");
     const int64_t npix = 12ll * d->nside * d->nside;
     P.obs.resize(d->n_obs);
     P.count5.resize(d->n_obs);

@@ -158,3 +158,10 @@ def test_finder_rejects_missing_arguments(abi):
         abi.MPATH_ERR_INVALID_ARG
     o = abi.mpath_finder_out()
     assert L.mpath_find_geodesics(None, C.byref(d), C.byref(o), None, 0, None) == abi.MPATH_ERR_INVALID_ARG
+
+
+def test_born_beam_rejects_missing_grid(abi):
+    L = abi.lib()
+    from paper_2111_08744_amd import CastConfig
+    d = CastConfig([0, 0, 0], 0.5, 4).desc()
+    assert L.mpath_born_beam(None, C.byref(d), None, None, None, 0, None) == abi.MPATH_ERR_INVALID_ARG

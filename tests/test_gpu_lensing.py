@@ -192,3 +192,34 @@ def test_infinitesimal_beam_amr(M):
     cells = synth.make_cells("amr_halo_small")
     _print("infinitesimal beam, amr halo small, nside 4, z = 0.4")
     _inf_compare(M, cells, [125.0, 125.0, 125.0], 0.4, 4, 4, True, max_bad_frac=0.02)
+
+
+@pytest.mark.parametrize("grid_name,obs,z,spc,adaptive", [
+    ("gauss64", [250.3, 249.6, 250.9], 0.5, 10, False),
+    ("amr_halo_small", [125.3, 124.6, 125.9], 0.4, 4, True)])
+def test_born_beam_matches_oracle(M, grid_name, obs, z, spc, adaptive):
+    """Born approximation along the straight lines of 192 pixel directions:
+    the same samples as the oracle (the step rule along the line), so the
+    matrices agree to the float32 field arithmetic; close to the
+    infinitesimal beam along the actual geodesics (weak lensing).  The
+    observer sits off the cell faces: from a point on a face, the lines of
+    the equatorial pixels run inside that face for their whole length, where
+    rounding alone picks the leaf cell (and, on a refined grid, the step)."""
+    cells = synth.make_cells(grid_name)
+    grid = M.Grid(cells, COSMO)
+    cfg = M.CastConfig(obs, z, 4, steps_per_cell=spc, adaptive=adaptive)
+    res = M.born_beam(grid, cfg)
+    A = res["A"].cpu().numpy().astype(np.float64)
+    assert (res["status"].cpu().numpy() == 0).all()
+    dirs = O.pix2vec_nest(4, np.arange(192))
+    p = O.params(obs, z_src=z, steps_per_cell=spc, adaptive=adaptive)
+    Ao, rec = O.born(O.Field.grid(cells), O.cosmo(*COSMO), p, dirs)
+    assert (rec["status"] == O.REACHED).all()
+    d = np.abs(A - Ao).max(axis=(1, 2))
+    lens = np.abs(Ao - np.eye(2)).max(axis=(1, 2))
+    _print(f"Born beam ({grid_name}): max |A - A_oracle| {d.max():.3e}, max |A_oracle - I| {lens.max():.3e}, "
+           f"{(d > 1e-6).sum()} of {len(d)} above 1e-6")
+    assert lens.max() > 1e-3
+    assert (d > 1e-6).sum() <= (0.02 * len(d) if adaptive else 0)
+    inf = M.infinitesimal_beam(grid, cfg)["A"].cpu().numpy().astype(np.float64)
+    assert np.abs(inf - A).max() < 0.2 * lens.max()

@@ -161,6 +161,27 @@ def test_p5_quadratic_jacobian(O):
         assert np.allclose(A_fb[i], A_cs[i], rtol=0, atol=5e-9)
 
 
+def test_p5_born_quadratic(O):
+    """Born approximation along the straight line of a constant Hessian:
+    int_0^chi_s (chi_s - chi) chi / chi_s dchi = chi_s^2 / 6 gives
+    A = I - chi_s^2/3 H_perp exactly up to the trapezoid error of a quadratic
+    integrand, (ds/chi_s)^2 relative; Phi = 0 gives the identity."""
+    c = O.cosmo()
+    H, dirs, chis = _quadratic_setup(O)
+    f = O.Field.quadratic(H, OBS)
+    p = O.params(OBS, z_src=0.25, ds=1.0)
+    A, rec = O.born(f, c, p, dirs, h_deriv=1.0)
+    assert (rec["status"] == O.REACHED).all()
+    for i, n in enumerate(dirs):
+        e1, e2 = O.screen_basis(n)
+        E = np.stack([e1, e2])
+        lens = chis ** 2 / 3.0 * (E @ H @ E.T)
+        assert np.abs(lens).max() > 1e-5
+        assert np.allclose(A[i], np.eye(2) - lens, rtol=0, atol=10 * np.abs(lens).max() / chis ** 2)
+    A0, _ = O.born(O.Field.linear([0.0, 0.0, 0.0]), c, p, dirs, h_deriv=1.0)
+    assert np.abs(A0 - np.eye(2)).max() < 1e-15
+
+
 def test_p6_time_reversal(O):
     c = O.cosmo()
     f = O.Field.point(3e-4, OBS + [150.0, 30.0, -20.0], soft=3.0)
