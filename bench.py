@@ -308,8 +308,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(rays would be sharded by sky pixel with the grid replicated; see DESIGN.md)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(rays would be sharded by sky pixel with the grid replicated on every GPU)",
               file=sys.stderr)
         sys.exit(2)
 
