@@ -178,11 +178,14 @@ def test_invalid_arguments_raise(M, gauss64):
     with pytest.raises(M.MpathError):
         M.cast(grid, M.CastConfig([250.0, 250.0, 250.0], 0.5, 4, pix_first=[40], pix_count=[200]))
     cfg = M.CastConfig([250.0, 250.0, 250.0], 0.5, 4)
-    d = cfg.desc()
-    d.order = 2
     import ctypes as C
     from paper_2111_08744_amd import _abi
     n = C.c_size_t()
+    d = cfg.desc()
+    d.order = 3                                  # no such interpolation order
+    assert _abi.lib().mpath_cast_workspace_bytes(grid.handle, C.byref(d), C.byref(n)) == _abi.MPATH_ERR_INVALID_ARG
+    d = cfg.desc()
+    d.order, d.checkpoint_every = 2, 32          # TSC has no adjoint
     assert _abi.lib().mpath_cast_workspace_bytes(grid.handle, C.byref(d), C.byref(n)) == _abi.MPATH_ERR_UNSUPPORTED
 
 
