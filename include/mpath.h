@@ -206,7 +206,10 @@ typedef struct {
  *   status      MPATH_RAY_*
  *   hash        FNV-1a over the discrete decisions (leaf level of every step,
  *               stencil level of every sub-step) for comparing with a reference
- *   chi         |x_s - x_obs| */
+ *   chi         |x_s - x_obs|
+ *   z1          FLRW redshift plus the potential term, z0 + (1 + z0)(Phi_o - Phi_s)
+ *               (Sect. 2.5; with v = 0 and a static Phi the Doppler, transverse
+ *               Doppler and ISW terms vanish, so z2 = z3 = z4 = z1) */
 typedef struct {
     double* beta;
     float* alpha;
@@ -217,6 +220,7 @@ typedef struct {
     int32_t* status;
     uint32_t* hash;
     double* chi;
+    double* z1;
 } mpath_observables;
 
 /* Device workspace for a cast (observer table, queue counter, end states,
@@ -406,6 +410,7 @@ typedef struct {
     int32_t* n_iter;            /* iteration of convergence (0: the first cast); -1 not converged
                                    within max_iter; -2 a cast did not reach the source              */
     int32_t* status;            /* MPATH_RAY_* of the final cast                                    */
+    double* z1;                 /* z0 + (1 + z0)(Phi_o - Phi_s)                                      */
 } mpath_finder_out;
 
 /* Workspace: the checkpointed cast and Jacobian sweep of n_src rays plus

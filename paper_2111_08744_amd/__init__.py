@@ -200,7 +200,7 @@ class CastConfig:
 _OUT_FIELDS = {
     "beta": ("float64", 2), "alpha": ("float32", 2), "z5": ("float64", 1), "z0": ("float64", 1),
     "phi_src": ("float32", 1), "n_steps": ("int32", 1), "status": ("int32", 1), "hash": ("int32", 1),
-    "chi": ("float64", 1),
+    "chi": ("float64", 1), "z1": ("float64", 1),
 }
 
 
@@ -465,6 +465,7 @@ def find_geodesics(grid: Grid, obs, src, steps_per_cell=10, adaptive=False, tol=
            "dz_dtheta": torch.empty((n, 2), dtype=torch.float32, device=dev),
            "z5": torch.empty((n,), dtype=torch.float64, device=dev),
            "z0": torch.empty((n,), dtype=torch.float64, device=dev),
+           "z1": torch.empty((n,), dtype=torch.float64, device=dev),
            "phi_src": torch.empty((n,), dtype=torch.float32, device=dev),
            "sep": torch.empty((n,), dtype=torch.float64, device=dev),
            "n_iter": torch.empty((n,), dtype=torch.int32, device=dev),

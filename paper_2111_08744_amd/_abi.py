@@ -62,7 +62,7 @@ class mpath_cast_desc(C.Structure):
 class mpath_observables(C.Structure):
     _fields_ = [("beta", C.c_void_p), ("alpha", C.c_void_p), ("z5", C.c_void_p), ("z0", C.c_void_p),
                 ("phi_src", C.c_void_p), ("n_steps", C.c_void_p), ("status", C.c_void_p),
-                ("hash", C.c_void_p), ("chi", C.c_void_p)]
+                ("hash", C.c_void_p), ("chi", C.c_void_p), ("z1", C.c_void_p)]
 
 
 class mpath_adjoint_desc(C.Structure):
@@ -81,7 +81,7 @@ class mpath_finder_desc(C.Structure):
 class mpath_finder_out(C.Structure):
     _fields_ = [("theta", C.c_void_p), ("A", C.c_void_p), ("dz_dtheta", C.c_void_p), ("z5", C.c_void_p),
                 ("z0", C.c_void_p), ("phi_src", C.c_void_p), ("sep", C.c_void_p), ("n_iter", C.c_void_p),
-                ("status", C.c_void_p)]
+                ("status", C.c_void_p), ("z1", C.c_void_p)]
 
 
 _lib = None

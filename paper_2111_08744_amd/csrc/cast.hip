@@ -171,6 +171,7 @@ struct RayRun {
         if (o.z5)
             o.z5[slot] = ok ? a_s * y.K * (1.0 + (double)phi_s) / (1.0 + (double)phi_o) - 1.0 : __builtin_nan("");
         if (o.z0) o.z0[slot] = ok ? z0 : __builtin_nan("");
+        if (o.z1) o.z1[slot] = ok ? z0 + (1.0 + z0) * ((double)phi_o - (double)phi_s) : __builtin_nan("");
         if (o.phi_src) o.phi_src[slot] = phi_s;
         if (o.n_steps) o.n_steps[slot] = (int32_t)n_steps;
         if (o.status) o.status[slot] = st;

@@ -87,6 +87,7 @@ struct OutDev {
     int32_t* status;
     uint32_t* hash;
     double* chi;
+    double* z1;
 };
 
 struct CastArgs {

@@ -697,6 +697,7 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
     a.out.status = out->status;
     a.out.hash = out->hash;
     a.out.chi = out->chi;
+    a.out.z1 = out->z1;
 
     if (d->dirs) {
         e = n_rays ? hipMemcpyAsync(a.dirs, d->dirs, (size_t)n_rays * 24, hipMemcpyDeviceToDevice, s) : hipSuccess;
@@ -1278,6 +1279,7 @@ int mpath_find_geodesics(const mpath_grid* g, const mpath_finder_desc* f, mpath_
     fo.n_steps = nsteps;
     fo.z5 = out->z5;
     fo.z0 = out->z0;
+    fo.z1 = out->z1;
     fo.phi_src = out->phi_src;
     rc = cast_impl(g, &P.cd, &fo, cws, P.cast_bytes, stream, false, nullptr, stop);
     if (rc) return rc;

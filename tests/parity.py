@@ -94,6 +94,13 @@ def compare(gpu, ora, idx=None, max_flip_frac=0.0, flip_tol_arcsec=None):
         summary["max_dphi"] = float(dphi)
         assert dphi <= 1e-6 * max(np.abs(ora["phi_s"]).max(), 1e-12), summary
         assert np.all(g["z0"][ok] == ora["z0"][ok])
+        if "z1" in g:
+            # z0 plus the potential term (Sect. 2.5): relative bar, with an
+            # absolute floor at the level of float32 cell values (the term is
+            # all of z1 in a static background, where z0 = 0)
+            dz1 = np.abs(g["z1"][ok] - ora["z1"][ok])
+            summary["max_dz1"] = float(dz1.max())
+            assert np.all(dz1 <= TOL_Z * np.abs(ora["z1"][ok]) + 1e-11), summary
     if flip_tol_arcsec is not None and n_flip:
         summary["flip_max_sep_arcsec"] = float(sep[~same].max())
         assert summary["flip_max_sep_arcsec"] <= flip_tol_arcsec, summary
