@@ -101,6 +101,35 @@ def cpu_baseline(w, cells, sample_stride, threads):
             "rays_per_s": len(pix) / dt}
 
 
+def cpu_table1(w, cells):
+    """The oracle's single-thread time per ray-step for the interpolation
+    modes of the paper's timing table (FLRW without lookups, NGP, CIC, TSC on
+    the uniform 64^3 grid; CIC on the AMR grid), on a few rays each."""
+    import oracle as O
+    import synth
+    c = O.cosmo(0.3, 0.7, 0.7)
+    obs = [250.0, 250.0, 250.0]
+    dirs = O.pix2vec_nest(4, np.arange(0, 192, 6))          # 32 rays
+    g64 = synth.make_cells("gauss64")
+    h0 = 500.0 / 64
+
+    def per_step(field, p, d):
+        t0 = time.perf_counter()
+        rec = O.cast(field, c, p, d, threads=1)
+        dt = time.perf_counter() - t0
+        return dt / int(rec["n_steps"].sum()) * 1e6
+
+    res = {"flrw": per_step(O.Field.linear([0.0, 0.0, 0.0]), O.params(obs, z_src=0.5, ds=h0 / 10), dirs)}
+    for order, name in ((0, "ngp"), (1, "cic"), (2, "tsc")):
+        res[f"uniform_{name}"] = per_step(O.Field.grid(g64, order=order),
+                                          O.params(obs, z_src=0.5, steps_per_cell=10), dirs)
+    res["amr_cic"] = per_step(O.Field.grid(cells), O.params(w.obs[0], z_src=float(w.z_src[0]), steps_per_cell=4,
+                                                            adaptive=True), dirs[:8])
+    return {"us_per_ray_step": res, "threads": 1,
+            "paper_table1_us_per_step": {"flrw": 0.55, "ngp": 1.10, "cic": 6.0, "tsc": 14.6},
+            "paper_hardware": "one core of an Intel Xeon Platinum 8168"}
+
+
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -431,6 +460,9 @@ def main():
             threads = min(threads, int(env))
         log(f"[bench] CPU baseline: oracle on every {args.cpu_stride}th ray with {threads} threads")
         res["cpu_baseline"] = cpu_baseline(w, cells, args.cpu_stride, threads)
+        if w.name == "amr":
+            res["cpu_baseline"]["single_thread"] = cpu_table1(w, cells)
+            log(f"[bench] oracle single-thread us/step: {res['cpu_baseline']['single_thread']['us_per_ray_step']}")
     print(json.dumps(res), flush=True)
 
 
