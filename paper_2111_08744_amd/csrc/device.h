@@ -275,7 +275,10 @@ struct FieldCache {
         const int k0 = I[0] >> sh, k1 = I[1] >> sh, k2 = I[2] >> sh;
         if (keyL == L && k0 == key[0] && k1 == key[1] && k2 == key[2]) return true;
         int base, l;
-        if (AMR) {
+        // a point in a leaf of level 0 takes the level-0 stencil (or none at
+        // the edge of a non-periodic box), whose base follows from the Morton
+        // order without the per-half-cell table
+        if (AMR && L > 0) {
             base = g.leafinfo[8 * leafId + ((k0 & 1) | ((k1 & 1) << 1) | ((k2 & 1) << 2))];
             if (base < 0) return false;
             l = level_of(g, base);
