@@ -382,6 +382,11 @@ def make_cells(grid: str) -> Cells:
         return random_amr_cells(16, 125.0, 3, seed=5)
     if grid == "amr_halo_small":
         return amr_halo_cells(32, 250.0, 3, seed=12, n_halo=40, dens_norm=1.0)
+    if grid == "amr_deep":
+        # 64^3 coarse, box 500 Mpc/h, 5 levels (finest 0.24 Mpc/h) in 60
+        # haloes: the depth of the 512^3 + 5 levels configuration on a grid
+        # small enough for full oracle comparisons (about 1.2e6 cells)
+        return amr_halo_cells(64, 500.0, 5, seed=5, n_halo=60, dens_norm=3000.0, threshold=30.0)
     if grid == "amr128":
         # 128^3 coarse, box 500 Mpc/h, 3 levels, 200 haloes, ~1e7 cells
         return amr_halo_cells(128, 500.0, 3, seed=2, n_halo=200, dens_norm=AMR128_DENS_NORM)

@@ -322,3 +322,28 @@ def test_rays_without_derivative(M):
     assert (_np(res["ray_status"]) == 1).all()
     assert np.isnan(_np(res["jac"])).all() and np.isnan(_np(res["dz_dtheta"])).all()
     assert (_np(res["dL_dvalues"]) == 0).all()
+
+
+def test_amr_deep_jacobian_vs_oracle(M):
+    """Adjoint distortion matrix on the five-level grid (a few rays through
+    the refined haloes) against the oracle's complex-step Jacobian."""
+    import torch
+    cells = synth.make_cells("amr_deep")
+    grid = M.Grid(cells, COSMO)
+    obs = OBS
+    cfg = M.CastConfig(obs, 0.3, 4, pix_first=[0], pix_count=[48], steps_per_cell=4, adaptive=True,
+                       checkpoint_every=16)
+    fwd = M.cast(grid, cfg)
+    res = M.adjoint(grid, cfg, fwd, jacobian=True)
+    torch.cuda.synchronize()
+    jac = res["jac"].cpu().numpy().astype(np.float64)
+    st = res["ray_status"].cpu().numpy()
+    dirs = O.pix2vec_nest(4, np.arange(48))
+    p = O.params(obs, z_src=0.3, steps_per_cell=4, adaptive=True)
+    field = O.Field.grid(cells)
+    A, dz, out = O.jacobian_cs(lambda d, t: O.cast_cs(field, O.cosmo(*COSMO), p, d, dtheta=t), dirs)
+    ok = (st == 0) & (out["status"] == O.REACHED)
+    assert ok.sum() >= 44
+    d = np.abs(jac[ok] - A[ok]).max(axis=(1, 2))
+    print("deep adjoint: max |dA|", d.max(), "median", np.median(d), flush=True)
+    assert np.median(d) < 2e-7 and (d > 5e-6).sum() <= 1

@@ -225,3 +225,21 @@ def test_empty_and_ragged_ray_lists(M, gauss64):
         g = run_gpu(grid, cfg)
         o = run_oracle(O.Field.grid(gauss64), O.cosmo(*COSMO), obs, z, 4, first, count, 10, False)
         _print(compare(g, o))
+
+
+def test_amr_deep_five_levels(M):
+    """Five refinement levels (the depth of the largest configuration): 64^3
+    coarse cells, finest 0.24 Mpc/h, adaptive steps, 768 rays (nside 8) to
+    z = 0.5 against the oracle, and the level mix of the decisions."""
+    cells = synth.make_cells("amr_deep")
+    counts = cells.counts_per_level()
+    _print("amr deep cells", cells.n_cells, counts)
+    assert cells.max_level == 5 and counts[5] > 0
+    grid = M.Grid(cells, COSMO)
+    obs = [250.0, 250.0, 250.0]
+    cfg = M.CastConfig(obs, 0.5, 8, steps_per_cell=4, adaptive=True)
+    g = run_gpu(grid, cfg)
+    o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), obs, 0.5, 8, [0], [768], 4, True)
+    _print(compare(g, o, max_flip_frac=0.02, flip_tol_arcsec=1.0))
+    coarse_only = 1322.038 / (500.0 / 64) * 4
+    assert g["n_steps"].max() > 1.2 * coarse_only        # some rays cross the refined haloes
