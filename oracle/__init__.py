@@ -36,7 +36,7 @@ STOP_REDSHIFT, STOP_CHI = 0, 1
 
 RAY_DTYPE = np.dtype([
     ("theta", "f8", 2), ("beta", "f8", 2), ("alpha", "f8", 2), ("sep2", "f8"),
-    ("z5", "f8"), ("z0", "f8"), ("z1", "f8"), ("phi_o", "f8"), ("phi_s", "f8"),
+    ("z5", "f8"), ("z0", "f8"), ("z1", "f8"), ("z4", "f8"), ("isw", "f8"), ("phi_o", "f8"), ("phi_s", "f8"),
     ("chi", "f8"), ("r", "f8", 3), ("k", "f8", 4), ("eta", "f8"), ("max_null", "f8"),
     ("n_steps", "i8"), ("status", "i4"), ("hash", "u4"),
 ], align=True)
@@ -94,6 +94,8 @@ def lib():
         L.or_field_free.argtypes = [vp]
         L.or_field_set_order.restype = C.c_int
         L.or_field_set_order.argtypes = [vp, C.c_int]
+        L.or_field_set_tdot.restype = C.c_int
+        L.or_field_set_tdot.argtypes = [vp, vp]
         L.or_field_probe.restype = C.c_int
         L.or_field_probe.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         for name in ("or_eta_of_a", "or_a_of_eta", "or_conformal_hubble"):
@@ -139,7 +141,8 @@ class Field:
 
     @classmethod
     def grid(cls, cells, order: int = 1) -> "Field":
-        """Grid field; order 0 NGP, 1 CIC, 2 TSC (Sect. 2.2)."""
+        """Grid field; order 0 NGP, 1 CIC, 2 TSC (Sect. 2.2).  A dphi_deta
+        attribute of the cells (not None) makes the potential time-dependent."""
         level = np.ascontiguousarray(cells.level, np.uint8)
         ijk = np.ascontiguousarray(cells.ijk, np.int32)
         phi = np.ascontiguousarray(cells.phi, np.float64)
@@ -153,6 +156,13 @@ class Field:
         if lib().or_field_set_order(h, int(order)):
             lib().or_field_free(h)
             raise ValueError(f"bad interpolation order {order}")
+        td = getattr(cells, "dphi_deta", None)
+        if td is not None:
+            td = np.ascontiguousarray(td, np.float64)
+            if td.shape != phi.shape:
+                lib().or_field_free(h)
+                raise ValueError("dphi_deta must have one value per cell")
+            lib().or_field_set_tdot(h, _ptr(td))
         return cls(h)
 
     @classmethod
@@ -205,6 +215,21 @@ def conformal_hubble(c: Cosmo, eta: float) -> float:
 
 def eta0(c: Cosmo) -> float:
     return lib().or_eta0(C.byref(c))
+
+
+def double_layer(phi1, phi2, a1, a2, c: Cosmo):
+    """dPhi/deta per cell from the potential on two light cones slightly
+    shifted in time (Sect. 2.2, the double-layer equation): the difference
+    quotient in a times da/deta, the latter at the midpoint a_m = (a1 + a2)/2
+    of the two layers, a' = a (a'/a) at eta(a_m) from the background."""
+    phi1 = np.asarray(phi1, np.float64)
+    phi2 = np.asarray(phi2, np.float64)
+    a1 = np.broadcast_to(np.asarray(a1, np.float64), phi1.shape)
+    a2 = np.broadcast_to(np.asarray(a2, np.float64), phi1.shape)
+    am = 0.5 * (a1 + a2)
+    u, inv = np.unique(am, return_inverse=True)
+    adot = np.array([a * conformal_hubble(c, eta_of_a(c, a)) for a in u])[inv.reshape(am.shape)]
+    return (phi2 - phi1) / (a2 - a1) * adot
 
 
 def chi_of_z(c: Cosmo, z: float) -> float:

@@ -31,6 +31,7 @@ struct or_field {
     int64_t n_cells;
     double* phi;
     double* grad;
+    double* tdot;         /* dPhi/deta per cell, or NULL (static potential) */
     int64_t* coarse;      /* [n0^3] cell index of coarse cell (i + n0 (j + n0 k)) */
     uint64_t* hkeys;      /* open-addressing table for levels >= 1 */
     int64_t* hvals;
@@ -218,8 +219,19 @@ or_field* or_field_analytic(int kind, const double* params)
 void or_field_free(or_field* f)
 {
     if (!f) return;
-    free(f->phi); free(f->grad); free(f->coarse); free(f->hkeys); free(f->hvals);
+    free(f->phi); free(f->grad); free(f->tdot); free(f->coarse); free(f->hkeys); free(f->hvals);
     free(f);
+}
+
+int or_field_set_tdot(or_field* f, const double* tdot)
+{
+    if (!f || f->kind != OR_FIELD_GRID) return -1;
+    free(f->tdot);
+    f->tdot = NULL;
+    if (!tdot) return 0;
+    f->tdot = (double*)malloc(sizeof(double) * (size_t)f->n_cells);
+    memcpy(f->tdot, tdot, sizeof(double) * (size_t)f->n_cells);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -428,7 +440,7 @@ int or_field_probe(const or_field* f, const double x[3], double* phi, double gra
                    int* leaf_level_out, int* stencil_level)
 {
     cs_ctx ctx = {NULL, NULL};
-    return eval_r(f, &ctx, x, phi, grad, leaf_level_out, stencil_level);
+    return eval_r(f, &ctx, x, phi, grad, NULL, leaf_level_out, stencil_level);
 }
 
 static int derive(const or_cosmo* c, const or_cast_params* p, derived_t* dv)
@@ -739,11 +751,13 @@ int or_born(const or_field* f, const or_cosmo* c, const or_cast_params* p, int64
 int or_integrate_steps(const or_field* f, const or_cosmo* c, double* y, int64_t n, const double* dl)
 {
     cs_ctx ctx = {NULL, NULL};
-    double out[S_N];
+    double s[S_N] = {0}, out[S_N];
+    memcpy(s, y, 8 * sizeof(double));
     for (int64_t i = 0; i < n; ++i) {
-        const int st = rk4_r(f, &ctx, c, y, dl[i], out, NULL, NULL);
+        const int st = rk4_r(f, &ctx, c, s, dl[i], out, NULL, NULL);
         if (st) return st;
-        memcpy(y, out, sizeof out);
+        memcpy(s, out, sizeof out);
     }
+    memcpy(y, s, 8 * sizeof(double));
     return 0;
 }

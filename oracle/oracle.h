@@ -46,6 +46,11 @@ void or_field_free(or_field* f);
  * 2 TSC (27 cells centred on the cell containing x), CIC and TSC with the
  * level fallback.  Returns 0, or -1 for a bad order or a closed-form field. */
 int or_field_set_order(or_field* f, int order);
+/* Time derivative of the potential per cell (a grid field; NULL: static).
+ * With it the geodesic equations take their dPhi/deta terms and each ray
+ * carries the ISW integral (Sect. 2.2, Sect. 2.5 z4).  The values are
+ * copied; they are interpolated with the weights of the potential. */
+int or_field_set_tdot(or_field* f, const double* tdot);
 
 /* Interpolation probe at a point: Phi, grad Phi, the leaf level (deepest
  * existing cell containing x) and the level the stencil was taken at.
@@ -83,6 +88,8 @@ typedef struct {
     double alpha[2];      /* deflection theta - beta, components on e1 = e_phi(theta), e2 = -e_theta(theta) */
     double sep2;          /* squared great-circle angle between theta and beta */
     double z5, z0, z1;    /* observed redshift (Eq. z5, v = 0), FLRW redshift, FLRW + potential */
+    double z4;            /* z1 + ISW term (Eq. z4 with v = 0) */
+    double isw;           /* integral of dPhi/deta d eta from eta_s to eta_0 along the ray */
     double phi_o, phi_s;  /* potential at the observer and at the end point */
     double chi;           /* |x_s - x_obs| */
     double r[3];          /* x_s - x_obs (unwrapped) */

@@ -20,13 +20,14 @@ from __future__ import annotations
 
 import dataclasses
 import math
+from typing import Optional
 
 import numpy as np
 
 __all__ = [
     "Cells", "gaussian_potential", "central_gradient", "uniform_cells",
     "fourier_field", "random_amr_cells", "amr_halo_cells", "Workload",
-    "WORKLOADS", "make_cells", "batched_cones",
+    "WORKLOADS", "make_cells", "batched_cones", "second_layer", "ISW_LAYER_A",
 ]
 
 
@@ -39,6 +40,8 @@ class Cells:
               [0, n0 * 2**level)
     phi[i]    potential sampled at the centre of cell i
     grad[i]   gradient of the potential at the centre of cell i
+    dphi_deta optional time derivative of the potential per cell (None: a
+              static potential)
     """
     box: float
     n0: int
@@ -48,6 +51,7 @@ class Cells:
     ijk: np.ndarray     # int32 [n, 3]
     phi: np.ndarray     # float64 [n]
     grad: np.ndarray    # float64 [n, 3]
+    dphi_deta: Optional[np.ndarray] = None
 
     @property
     def n_cells(self) -> int:
@@ -368,12 +372,33 @@ class Workload:
         return int(self.pix_count.sum())
 
 
+# Two light-cone layers of the uniform 64^3 potential, slightly shifted in
+# time: the second is the first decayed as in linear LCDM near z = 0.5
+# (d ln Phi / d ln a = -0.3) plus an independent Gaussian field of the same
+# spectrum at a fifth of that change (a non-linear, uncorrelated part).
+ISW_LAYER_A = (0.66, 0.68)
+
+
+def second_layer(phi1: np.ndarray, n: int, box: float, seed: int, a1: float, a2: float,
+                 slope: float = -0.3, noise: float = 0.2) -> np.ndarray:
+    """Potential of the second layer at a2 of a uniform n^3 grid whose first
+    layer (at a1, cell order of uniform_cells) is phi1."""
+    d = slope * (a2 - a1) / a1
+    g2 = gaussian_potential(n, box, seed=seed).ravel()
+    return phi1 * (1.0 + d) + noise * d * g2
+
+
 def make_cells(grid: str) -> Cells:
     """Build a named grid (deterministic)."""
     if grid == "gauss64":
         # uniform 64^3 grid, box 500 Mpc/h, P(k) ~ k^-3, rms 1e-5, seed 1
         phi = gaussian_potential(64, 500.0, seed=1)
         return uniform_cells(phi, central_gradient(phi, 500.0), 500.0)
+    if grid == "gauss64_layer2":
+        # the second layer of gauss64 at ISW_LAYER_A[1] (phi only; seed 21)
+        c = make_cells("gauss64")
+        c.phi = second_layer(c.phi, 64, 500.0, 21, *ISW_LAYER_A)
+        return c
     if grid == "gauss32":
         phi = gaussian_potential(32, 250.0, seed=11)
         return uniform_cells(phi, central_gradient(phi, 250.0), 250.0)
