@@ -80,7 +80,12 @@ typedef struct {
  *   phi[i]      potential at the cell centre (each cell, internal or leaf,
  *               carries its own value: used when interpolating at its level)
  *   grad[i][3]  gradient of the potential at the cell centre
- * value_dtype says whether phi and grad are double or float.  Cell (l, i)
+ *   dphi_deta[i] optional (NULL: a static potential): the time derivative of
+ *               the potential at the cell centre (Sect. 2.2; from two light
+ *               cones shifted in time, see mpath_double_layer).  A grid that
+ *               carries it is integrated with the dPhi/deta terms of the
+ *               geodesic equations and yields the ISW integral and z4.
+ * value_dtype says whether phi, grad and dphi_deta are double or float.  Cell (l, i)
  * covers [i h_l, (i+1) h_l) per axis with h_l = box / (n0 2^l); n0 must be a
  * power of two (<= 1024) and max_level <= 10.  periodic != 0 replicates the
  * box (rays may travel further than the box size); otherwise cells outside
@@ -96,6 +101,7 @@ typedef struct {
     const int32_t* ijk;
     const void* phi;
     const void* grad;
+    const void* dphi_deta;
 } mpath_grid_desc;
 
 typedef struct mpath_grid mpath_grid;   /* opaque host handle */
@@ -113,6 +119,19 @@ int mpath_grid_workspace_bytes(const mpath_grid_desc* desc, size_t* bytes);
  * outlive the handle. */
 int mpath_grid_build(const mpath_grid_desc* desc, const mpath_cosmo* cosmo, void* dev_ws,
                      size_t ws_bytes, void* stream, mpath_grid** out);
+
+/* dPhi/deta of every cell from a double-layer light cone (Sect. 2.2, the
+ * equation for dPhi/deta from two light cones slightly shifted in time):
+ *   dphi_deta[i] = (phi2[i] - phi1[i]) / (a2[i] - a1[i]) * a'(a_m),
+ * where phi1, phi2 are the potential of cell i on the two cones, a1, a2 the
+ * scale factors of the cell on them, and the conformal-time derivative
+ * a' = da/deta = a (a'/a) of the background is taken at a_m = (a1 + a2)/2
+ * (the centre of the difference quotient).  All arrays are HOST arrays of n
+ * doubles; dphi_deta may alias neither input.  MPATH_ERR_INVALID_ARG when a
+ * cell has a1 == a2 or a non-positive scale factor; MPATH_ERR_UNSUPPORTED
+ * for the static background.  Runs on the host (grid ingest). */
+int mpath_double_layer(int64_t n, const double* phi1, const double* phi2, const double* a1, const double* a2,
+                       const mpath_cosmo* cosmo, double* dphi_deta);
 
 /* Release the handle (not dev_ws, which the caller owns). */
 int mpath_grid_free(mpath_grid* grid);
@@ -208,8 +227,12 @@ typedef struct {
  *               stencil level of every sub-step) for comparing with a reference
  *   chi         |x_s - x_obs|
  *   z1          FLRW redshift plus the potential term, z0 + (1 + z0)(Phi_o - Phi_s)
- *               (Sect. 2.5; with v = 0 and a static Phi the Doppler, transverse
- *               Doppler and ISW terms vanish, so z2 = z3 = z4 = z1) */
+ *               (Sect. 2.5; with v = 0 the Doppler and transverse Doppler
+ *               terms vanish, so z2 = z3 = z1)
+ *   z4          z1 plus the ISW term, z1 - 2 (1 + z0) isw (Sect. 2.5; equal to
+ *               z1 for a static potential)
+ *   isw         integral of dPhi/deta over conformal time from the stop surface
+ *               to the observer along the ray (0 for a static potential) */
 typedef struct {
     double* beta;
     float* alpha;
@@ -221,6 +244,8 @@ typedef struct {
     uint32_t* hash;
     double* chi;
     double* z1;
+    double* z4;
+    double* isw;
 } mpath_observables;
 
 /* Device workspace for a cast (observer table, queue counter, end states,
@@ -229,7 +254,11 @@ typedef struct {
 int mpath_cast_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* desc, size_t* bytes);
 
 /* Cast all rays; asynchronous on the stream except for the upload of the
- * observer table (a few bytes per observer), which completes before return. */
+ * observer table (a few bytes per observer), which completes before return.
+ * A grid with dphi_deta is cast with order 1, one stop surface and
+ * checkpoint_every 0 (MPATH_ERR_UNSUPPORTED otherwise); the reverse mode,
+ * the infinitesimal and Born beams and the finder take static potentials
+ * only. */
 int mpath_cast(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observables* out,
                void* dev_ws, size_t ws_bytes, void* stream);
 

@@ -51,7 +51,8 @@ class Grid:
     """An octree of Phi and grad Phi resident on the GPU (mpath_grid_build).
 
     cells: an object with box, n0, max_level, periodic, level[n] (uint8),
-    ijk[n,3] (int32), phi[n], grad[n,3] (float64 or float32 numpy arrays).
+    ijk[n,3] (int32), phi[n], grad[n,3] (float64 or float32 numpy arrays)
+    and optionally dphi_deta[n] (a time-dependent potential, Sect. 2.2).
     cosmo: (omega_m, omega_l, h); (0, 0, h) is a static background.
     """
 
@@ -67,7 +68,12 @@ class Grid:
         vt = np.float32 if f32 else np.float64
         phi = np.ascontiguousarray(cells.phi, vt)
         grad = np.ascontiguousarray(cells.grad, vt)
-        self._keep = (level, ijk, phi, grad)
+        td = getattr(cells, "dphi_deta", None)
+        td = None if td is None else np.ascontiguousarray(td, vt)
+        if td is not None and td.shape != phi.shape:
+            raise ValueError("dphi_deta must have one value per cell")
+        self.time_dependent = td is not None
+        self._keep = (level, ijk, phi, grad, td)
         d = _abi.mpath_grid_desc()
         d.box = float(cells.box)
         d.n0 = int(cells.n0)
@@ -79,6 +85,7 @@ class Grid:
         d.ijk = ijk.ctypes.data
         d.phi = phi.ctypes.data
         d.grad = grad.ctypes.data
+        d.dphi_deta = None if td is None else td.ctypes.data
         nbytes = C.c_size_t()
         _abi.check(L.mpath_grid_workspace_bytes(C.byref(d), C.byref(nbytes)), "mpath_grid_workspace_bytes")
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
@@ -200,7 +207,7 @@ class CastConfig:
 _OUT_FIELDS = {
     "beta": ("float64", 2), "alpha": ("float32", 2), "z5": ("float64", 1), "z0": ("float64", 1),
     "phi_src": ("float32", 1), "n_steps": ("int32", 1), "status": ("int32", 1), "hash": ("int32", 1),
-    "chi": ("float64", 1), "z1": ("float64", 1),
+    "chi": ("float64", 1), "z1": ("float64", 1), "z4": ("float64", 1), "isw": ("float64", 1),
 }
 
 
@@ -499,3 +506,22 @@ def born_beam(grid: Grid, cfg: CastConfig, ws=None):
         _abi.check(L.mpath_born_beam(grid.handle, C.byref(d), _ptr(A), _ptr(st), _ptr(ws), ws.numel(),
                                      _stream_ptr(grid.device)), "mpath_born_beam")
     return {"A": A, "status": st, "_ws": ws}
+
+
+def double_layer(phi1, phi2, a1, a2, cosmo=(0.3, 0.7, 0.7)):
+    """mpath_double_layer: dPhi/deta of every cell from the potential on two
+    light cones slightly shifted in time (Sect. 2.2), phi1 at scale factors
+    a1 and phi2 at a2 (arrays, or scalars for the whole grid); returns a
+    float64 numpy array, for the dphi_deta field of a grid's cells."""
+    phi1 = np.ascontiguousarray(phi1, np.float64)
+    phi2 = np.ascontiguousarray(phi2, np.float64)
+    if phi1.shape != phi2.shape or phi1.ndim != 1:
+        raise ValueError("phi1 and phi2 must be 1-d arrays of equal length")
+    n = phi1.shape[0]
+    a1 = np.ascontiguousarray(np.broadcast_to(np.asarray(a1, np.float64), (n,)))
+    a2 = np.ascontiguousarray(np.broadcast_to(np.asarray(a2, np.float64), (n,)))
+    out = np.empty(n, np.float64)
+    cz = _abi.mpath_cosmo(*map(float, cosmo))
+    _abi.check(_abi.lib().mpath_double_layer(n, phi1.ctypes.data, phi2.ctypes.data, a1.ctypes.data, a2.ctypes.data,
+                                             C.byref(cz), out.ctypes.data), "mpath_double_layer")
+    return out

@@ -40,7 +40,8 @@ class mpath_cosmo(C.Structure):
 class mpath_grid_desc(C.Structure):
     _fields_ = [("box", C.c_double), ("n0", C.c_int32), ("max_level", C.c_int32),
                 ("periodic", C.c_int32), ("value_dtype", C.c_int32), ("n_cells", C.c_int64),
-                ("level", C.c_void_p), ("ijk", C.c_void_p), ("phi", C.c_void_p), ("grad", C.c_void_p)]
+                ("level", C.c_void_p), ("ijk", C.c_void_p), ("phi", C.c_void_p), ("grad", C.c_void_p),
+                ("dphi_deta", C.c_void_p)]
 
 
 class mpath_grid_info(C.Structure):
@@ -62,7 +63,8 @@ class mpath_cast_desc(C.Structure):
 class mpath_observables(C.Structure):
     _fields_ = [("beta", C.c_void_p), ("alpha", C.c_void_p), ("z5", C.c_void_p), ("z0", C.c_void_p),
                 ("phi_src", C.c_void_p), ("n_steps", C.c_void_p), ("status", C.c_void_p),
-                ("hash", C.c_void_p), ("chi", C.c_void_p), ("z1", C.c_void_p)]
+                ("hash", C.c_void_p), ("chi", C.c_void_p), ("z1", C.c_void_p), ("z4", C.c_void_p),
+                ("isw", C.c_void_p)]
 
 
 class mpath_adjoint_desc(C.Structure):
@@ -117,6 +119,7 @@ def lib():
         L.mpath_find_geodesics.argtypes = [vp, P(mpath_finder_desc), P(mpath_finder_out), vp, sz, vp]
         L.mpath_born_beam.argtypes = [vp, P(mpath_cast_desc), vp, vp, vp, sz, vp]
         L.mpath_gather_probe.argtypes = [vp, sz, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_uint32, vp, vp]
+        L.mpath_double_layer.argtypes = [C.c_int64, vp, vp, vp, vp, P(mpath_cosmo), vp]
         L.mpath_status_string.restype = C.c_char_p
         L.mpath_status_string.argtypes = [C.c_int]
         L.mpath_last_error.restype = C.c_char_p
@@ -127,7 +130,7 @@ def lib():
                      "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune", "mpath_gather_probe",
                      "mpath_lensing_maps", "mpath_finite_beam_workspace_bytes", "mpath_finite_beam",
                      "mpath_infinitesimal_beam", "mpath_find_geodesics_workspace_bytes", "mpath_find_geodesics",
-                     "mpath_born_beam"):
+                     "mpath_born_beam", "mpath_double_layer"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

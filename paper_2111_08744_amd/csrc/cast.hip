@@ -45,6 +45,7 @@ struct RayRun {
     int32_t n_steps;
     uint32_t hash;
     int status;           // -1 while running
+    double isw;           // int dPhi/deta |d eta| so far (time-dependent potential; else 0)
     FC F;
 
     template <bool CKPT = false>
@@ -71,6 +72,7 @@ struct RayRun {
         n_steps = 0;
         hash = kFnvOffset;
         status = -1;
+        isw = 0.0;
         float G[3];
         int leafl, l;
         if (F.eval(a.grid, geo.vo, phi_o, G, leafl, l)) {
@@ -128,6 +130,7 @@ struct RayRun {
                 if (k + 1 < passes) dlx = dlx + (yn.eta - eta_s) / yn.K;
             }
             const bool fin = finite_state(yn);
+            if constexpr (FC::kTime) isw += (double)F.isw_step;
             if (landing) {
                 y = yn;
                 ++n_steps;
@@ -171,7 +174,11 @@ struct RayRun {
         if (o.z5)
             o.z5[slot] = ok ? a_s * y.K * (1.0 + (double)phi_s) / (1.0 + (double)phi_o) - 1.0 : __builtin_nan("");
         if (o.z0) o.z0[slot] = ok ? z0 : __builtin_nan("");
-        if (o.z1) o.z1[slot] = ok ? z0 + (1.0 + z0) * ((double)phi_o - (double)phi_s) : __builtin_nan("");
+        const double z1 = z0 + (1.0 + z0) * ((double)phi_o - (double)phi_s);
+        if (o.z1) o.z1[slot] = ok ? z1 : __builtin_nan("");
+        // z4 = z1 - 2 (a0 / a_s) int_{eta_s}^{eta_0} dPhi/deta d eta (Sect. 2.5, v = 0)
+        if (o.z4) o.z4[slot] = ok ? z1 - 2.0 * (1.0 + z0) * isw : __builtin_nan("");
+        if (o.isw) o.isw[slot] = ok ? isw : __builtin_nan("");
         if (o.phi_src) o.phi_src[slot] = phi_s;
         if (o.n_steps) o.n_steps[slot] = (int32_t)n_steps;
         if (o.status) o.status[slot] = st;
@@ -245,13 +252,14 @@ __global__ __launch_bounds__(256) void observables_kernel(CastArgs a)
     }
 }
 
-template <bool AMR>
+// TIME: the grid carries dPhi/deta (time-dependent potential).
+template <bool AMR, bool TIME>
 __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_static_kernel(CastArgs a)
 {
     extern __shared__ float coef_lds[];
     const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (r >= a.n_rays) return;
-    RayRun<AMR> R;
+    RayRun<AMR, FieldCache<AMR, TIME>> R;
     R.F.bind(coef_lds + threadIdx.x);
     R.start(a, r);
     R.advance(a, 0x7fffffff);
@@ -272,12 +280,12 @@ __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_ckpt_kernel(Cas
     R.finish(a);
 }
 
-template <bool AMR>
+template <bool AMR, bool TIME>
 __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_persistent_kernel(CastArgs a)
 {
     extern __shared__ float coef_lds[];
     const int lane = threadIdx.x & (kWave - 1);
-    RayRun<AMR> R;
+    RayRun<AMR, FieldCache<AMR, TIME>> R;
     R.F.bind(coef_lds + threadIdx.x);
     R.ray = -1;
     bool exhausted = false;
@@ -572,11 +580,17 @@ hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s)
 {
     if (a.n_rays == 0) return hipSuccess;
     const int64_t blocks = (a.n_rays + block - 1) / block;
-    const size_t lds = (size_t)32 * block * sizeof(float);
-    if (a.grid.max_level > 0)
-        hipLaunchKernelGGL(cast_static_kernel<true>, dim3((unsigned)blocks), dim3(block), lds, s, a);
-    else
-        hipLaunchKernelGGL(cast_static_kernel<false>, dim3((unsigned)blocks), dim3(block), lds, s, a);
+    const bool amr = a.grid.max_level > 0, td = a.grid.tdual != nullptr;
+    const size_t lds = (size_t)(td ? FieldCache<true, true>::kFloats : FieldCache<true>::kFloats) * block *
+                       sizeof(float);
+    const dim3 grid((unsigned)blocks), blk(block);
+    if (td) {
+        if (amr) hipLaunchKernelGGL((cast_static_kernel<true, true>), grid, blk, lds, s, a);
+        else hipLaunchKernelGGL((cast_static_kernel<false, true>), grid, blk, lds, s, a);
+    } else {
+        if (amr) hipLaunchKernelGGL((cast_static_kernel<true, false>), grid, blk, lds, s, a);
+        else hipLaunchKernelGGL((cast_static_kernel<false, false>), grid, blk, lds, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -667,20 +681,32 @@ hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipS
 {
     if (a.n_rays == 0) return hipSuccess;
     hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, a.queue);
-    const size_t lds = (size_t)32 * block * sizeof(float);
-    if (a.grid.max_level > 0)
-        hipLaunchKernelGGL(cast_persistent_kernel<true>, dim3(blocks), dim3(block), lds, s, a);
-    else
-        hipLaunchKernelGGL(cast_persistent_kernel<false>, dim3(blocks), dim3(block), lds, s, a);
+    const bool amr = a.grid.max_level > 0, td = a.grid.tdual != nullptr;
+    const size_t lds = (size_t)(td ? FieldCache<true, true>::kFloats : FieldCache<true>::kFloats) * block *
+                       sizeof(float);
+    const dim3 grid(blocks), blk(block);
+    if (td) {
+        if (amr) hipLaunchKernelGGL((cast_persistent_kernel<true, true>), grid, blk, lds, s, a);
+        else hipLaunchKernelGGL((cast_persistent_kernel<false, true>), grid, blk, lds, s, a);
+    } else {
+        if (amr) hipLaunchKernelGGL((cast_persistent_kernel<true, false>), grid, blk, lds, s, a);
+        else hipLaunchKernelGGL((cast_persistent_kernel<false, false>), grid, blk, lds, s, a);
+    }
     return hipGetLastError();
 }
 
-int cast_occupancy_blocks_per_cu(int block, bool amr)
+int cast_occupancy_blocks_per_cu(int block, bool amr, bool time_dep)
 {
     int nb = 0;
-    const size_t lds = (size_t)32 * block * sizeof(float);
-    hipError_t e = amr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<true>, block, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<false>, block, lds);
+    const size_t lds = (size_t)(time_dep ? FieldCache<true, true>::kFloats : FieldCache<true>::kFloats) * block *
+                       sizeof(float);
+    hipError_t e;
+    if (time_dep)
+        e = amr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<true, true>, block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<false, true>, block, lds);
+    else
+        e = amr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<true, false>, block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cast_persistent_kernel<false, false>, block, lds);
     return e == hipSuccess ? nb : 0;
 }
 

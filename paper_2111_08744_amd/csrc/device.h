@@ -206,8 +206,13 @@ __device__ __forceinline__ float trilinear_eval(float c0, float c1, float c2, fl
 // level l <= L is a function of floor(x / h_{L+1}) alone (the half of the
 // leaf cell x lies in per axis), so the resolved stencil is a function of
 // (leaf cell, floor(x / h_{L+1})); the build precomputes it per half-cell.
-template <bool AMR>
+//
+// TIME: the grid also carries dPhi/deta (Sect. 2.2, from a double-layer
+// light cone); its 8 coefficients follow the 32 of (phi, grad) in LDS and
+// eval leaves the interpolated value in tv.
+template <bool AMR, bool TIME = false>
 struct FieldCache {
+    static constexpr bool kTime = TIME;
     int leafId;         // id of the leaf cell containing the cached half-cell
     int keyL;           // level of that leaf (-1: nothing cached)
     int key[3];         // unwrapped coordinates of the half-cell at level keyL + 1
@@ -215,8 +220,11 @@ struct FieldCache {
     int base;           // id of its lowest corner cell
     float t[3];         // offsets of the last evaluated point in that stencil
     float* c;           // trilinear coefficients in LDS: coefficient k of
-                        // component f (phi, gx, gy, gz) at c[(8 f + k) * kBlock]
+                        // component f (phi, gx, gy, gz[, dphi/deta]) at c[(8 f + k) * kBlock]
+    float tv;           // TIME: dPhi/deta at the last evaluated point
+    float isw_step;     // TIME: ISW increment of the last RK4 step (set by rk4_step)
     static constexpr int cstride = kBlock;
+    static constexpr int kFloats = TIME ? 40 : 32;   // LDS words per lane
 
     // lds: this lane's first slot; lanes of a block are kBlock words apart
     // per coefficient, so the 64 lanes of a wave touch 64 consecutive words
@@ -304,6 +312,11 @@ struct FieldCache {
             c[(16 + o) * cstride] = q.z;
             c[(24 + o) * cstride] = q.w;
         }
+        if constexpr (TIME) {
+            const float4 t0 = g.tdual[2 * (int64_t)base], t1 = g.tdual[2 * (int64_t)base + 1];
+            c[32 * cstride] = t0.x; c[33 * cstride] = t0.y; c[34 * cstride] = t0.z; c[35 * cstride] = t0.w;
+            c[36 * cstride] = t1.x; c[37 * cstride] = t1.y; c[38 * cstride] = t1.z; c[39 * cstride] = t1.w;
+        }
         lvl = l;
         keyL = L;
         key[0] = k0; key[1] = k1; key[2] = k2;
@@ -362,6 +375,11 @@ struct FieldCache {
         G[0] = f[1];
         G[1] = f[2];
         G[2] = f[3];
+        if constexpr (TIME) {
+            const float* k = c + 32 * cstride;
+            tv = trilinear_eval(k[0], k[cstride], k[2 * cstride], k[3 * cstride], k[4 * cstride], k[5 * cstride],
+                                k[6 * cstride], k[7 * cstride], tx, ty, tz);
+        }
         return 0;
     }
 };
@@ -397,6 +415,7 @@ __device__ __forceinline__ int walk_to_leaf(const GridDev& g, const int I[3], in
 // cell containing the point.  The lane keeps the last leaf and its values.
 template <bool AMR>
 struct NgpCache {
+    static constexpr bool kTime = false;
     static constexpr int kNoKey = 0x40000000;
     int keyL;           // level of the cached leaf
     int key[3];         // its unwrapped coordinates at that level
@@ -453,6 +472,7 @@ struct NgpCache {
 // -1, 0, +1 are (1 - f)^2 / 2, 3/4 - (f - 1/2)^2 and f^2 / 2.
 template <bool AMR>
 struct TscCache {
+    static constexpr bool kTime = false;
     static constexpr int kNoKey = 0x40000000;
     int keyL;           // level of the leaf whose stencil is cached
     int key[3];         // its unwrapped coordinates at that level
@@ -590,7 +610,11 @@ struct NoRecord {
 };
 
 // One RK4 step of affine length dl from y into out (F: the lane's field
-// evaluator, any interpolation order).  The four stencil levels
+// evaluator, any interpolation order).  With a time-dependent potential
+// (FC::kTime) the spatial equation takes dPhi/dl = grad Phi . k + T k0 with
+// T = dPhi/deta (in the time equation the two T terms cancel: 2 T k0^2 -
+// 2 T k0 k0), and the step's ISW increment int T K dl (= int T |d eta|) is
+// left in F.isw_step.  The four stencil levels
 // are appended to hash only when all four stages succeed (return 0).  When
 // record is set, the recorder receives every stage's state and stencil (base
 // id, level); the reverse sweep uses it to replay the forward stages exactly.
@@ -605,6 +629,7 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC
     float acc_dx[3] = {0.f, 0.f, 0.f}, acc_P[3] = {0.f, 0.f, 0.f};
     double f_K = 0.0, Kprev = y.K;
     float f_dx[3] = {0.f, 0.f, 0.f}, f_P[3] = {0.f, 0.f, 0.f};
+    float acc_I = 0.f;
     uint32_t h = hash;
     HubbleCubic Hc;
     Hc.init(cz, y.eta);
@@ -645,13 +670,18 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC
         const float Kf = (float)yi.K;
         const float K2 = Kf * Kf;
         const float hm = 2.0f * ((float)H - mG);
+        // dk/dl with k = K m: K^2 (2 H m + 2 (m.G - T) m - 2 G); the P form
+        // subtracts n dK/dl, dK/dl = K^2 (2 H - 2 m.G)
+        float cm = 4.0f * mG;
+        if constexpr (FC::kTime) cm = fmaf(-2.0f, F.tv, cm);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             f_dx[i] = Kf * yi.d[i];
-            f_P[i] = K2 * fmaf(hm, yi.d[i], fmaf(4.0f * mG, m[i], -2.0f * G[i]));
+            f_P[i] = K2 * fmaf(hm, yi.d[i], fmaf(cm, m[i], -2.0f * G[i]));
         }
         const double w = (st == 0 || st == 3) ? 1.0 : 2.0;
         const float wf = (float)w;
+        if constexpr (FC::kTime) acc_I = fmaf(wf, F.tv * Kf, acc_I);
         acc_eta = fma(-w, yi.K, acc_eta);
         acc_K = fma(w, f_K, acc_K);
 #pragma unroll
@@ -676,6 +706,7 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC
         out.dx[i] = fmaf(h6f, acc_dx[i], y.dx[i]);
         out.d[i] = fmaf(cK, acc_P[i], fmaf(rm1, y.d[i], y.d[i]));
     }
+    if constexpr (FC::kTime) F.isw_step = h6f * acc_I;
     hash = h;
     return 0;
 }

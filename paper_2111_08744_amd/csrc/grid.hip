@@ -27,6 +27,25 @@ __global__ void build_dual_kernel(GridDev g, const int4* __restrict__ cellpos, f
     for (int o = 0; o < 8; ++o) dual[8 * c + o] = coef[o];
 }
 
+// The same record for dPhi/deta (a time-dependent potential): the 8
+// trilinear coefficients of the stencil based at cell c, two float4.
+__global__ void build_tdual_kernel(GridDev g, const int4* __restrict__ cellpos, const float* __restrict__ tpay,
+                                   float4* __restrict__ tdual, int64_t n)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int4 p = cellpos[c];
+    float4 v[8], coef[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const int id = lookup_cell(g, p.w, p.x + (o & 1), p.y + ((o >> 1) & 1), p.z + (o >> 2));
+        v[o] = make_float4(id >= 0 ? tpay[id] : 0.f, 0.f, 0.f, 0.f);
+    }
+    trilinear_coefficients(v, coef);
+    tdual[2 * c] = make_float4(coef[0].x, coef[1].x, coef[2].x, coef[3].x);
+    tdual[2 * c + 1] = make_float4(coef[4].x, coef[5].x, coef[6].x, coef[7].x);
+}
+
 __global__ void build_leafinfo_kernel(GridDev g, const int4* __restrict__ cellpos, int32_t* __restrict__ info,
                                       int64_t n)
 {
@@ -79,6 +98,15 @@ hipError_t launch_build_dual(const GridDev& g, const int4* cellpos, float4* dual
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(build_dual_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, cellpos, dual, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_tdual(const GridDev& g, const int4* cellpos, const float* tpay, float4* tdual, int64_t n,
+                              hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(build_tdual_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, cellpos, tpay,
+                       tdual, n);
     return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ struct GridDev {
     const float4* dual;       // [n][8]
     const int32_t* leafinfo;  // [n][8]
     const int32_t* dual_ids;  // [n][8] ids of the 8 cells of dual[c] (-1: missing)
+    const float4* tdual;      // [n][2]: 8 trilinear coefficients of dPhi/deta, or null (static potential)
     double h0;                // coarse cell size
     double inv_h0;
     double inv_hf;            // 2^(max_level + 1) / h0: fine-grid coordinates
@@ -88,6 +89,8 @@ struct OutDev {
     uint32_t* hash;
     double* chi;
     double* z1;
+    double* z4;
+    double* isw;
 };
 
 struct CastArgs {
@@ -145,6 +148,8 @@ hipError_t launch_permute_values(float4* payload, const int64_t* perm, const flo
                                  int64_t n, hipStream_t s);
 // Derived tables (defined in grid.hip); cellpos[c] = (i, j, k, level).
 hipError_t launch_build_dual(const GridDev& g, const int4* cellpos, float4* dual, int64_t n, hipStream_t s);
+hipError_t launch_build_tdual(const GridDev& g, const int4* cellpos, const float* tpay, float4* tdual, int64_t n,
+                              hipStream_t s);
 hipError_t launch_build_leafinfo(const GridDev& g, const int4* cellpos, int32_t* leafinfo, int64_t n,
                                  hipStream_t s);
 hipError_t launch_build_dual_ids(const GridDev& g, const int4* cellpos, int32_t* ids, int64_t n, hipStream_t s);
@@ -156,7 +161,7 @@ hipError_t launch_scatter_grad(const float* grad_lib, const int64_t* perm, float
                                hipStream_t s);
 hipError_t launch_central_transpose(const float* g_lib, const int4* cellpos, const int64_t* perm, float* out,
                                     int n0, double h0, int64_t n, hipStream_t s);
-int cast_occupancy_blocks_per_cu(int block, bool amr);
+int cast_occupancy_blocks_per_cu(int block, bool amr, bool time_dep);
 // Reference rays of one observer for the finite-beam casts.
 struct BeamObs {
     int64_t ray_first;   // first reference ray of the observer

@@ -137,6 +137,8 @@ struct mpath_grid {
     int32_t* leafinfo = nullptr;
     int32_t* dual_ids = nullptr;
     double2* table = nullptr;
+    float* tpay = nullptr;        // dPhi/deta per cell (time-dependent potential), else null
+    float4* tdual = nullptr;      // its 8 trilinear coefficients per stencil base
     int32_t level_start[kMaxLevels + 1] = {0};
     int num_cus = 0;
 };
@@ -144,11 +146,14 @@ struct mpath_grid {
 namespace {
 
 struct GridLayout {
-    size_t off_payload, off_child, off_perm, off_cellpos, off_dual, off_leafinfo, off_dual_ids, off_table, total;
+    size_t off_payload, off_child, off_perm, off_cellpos, off_dual, off_leafinfo, off_dual_ids, off_table;
+    size_t off_tpay, off_tdual, total;
 };
 
-// Device workspace of a grid: 236 bytes per cell plus the background table.
-GridLayout grid_layout(int64_t n)
+// Device workspace of a grid: 236 bytes per cell plus the background table,
+// and 36 more per cell for a time-dependent potential (dPhi/deta and its
+// stencil coefficients).
+GridLayout grid_layout(int64_t n, bool time_dep)
 {
     GridLayout L;
     L.off_payload = 0;
@@ -159,7 +164,9 @@ GridLayout grid_layout(int64_t n)
     L.off_leafinfo = align_up(L.off_dual + (size_t)n * 128, 256);
     L.off_dual_ids = align_up(L.off_leafinfo + (size_t)n * 32, 256);
     L.off_table = align_up(L.off_dual_ids + (size_t)n * 32, 256);
-    L.total = align_up(L.off_table + (size_t)kTableN * 16, 256);
+    L.off_tpay = align_up(L.off_table + (size_t)kTableN * 16, 256);
+    L.off_tdual = align_up(L.off_tpay + (time_dep ? (size_t)n * 4 : 0), 256);
+    L.total = align_up(L.off_tdual + (time_dep ? (size_t)n * 32 : 0), 256);
     return L;
 }
 
@@ -172,6 +179,7 @@ GridDev make_griddev(const mpath_grid* g)
     d.dual = g->dual;
     d.leafinfo = g->leafinfo;
     d.dual_ids = g->dual_ids;
+    d.tdual = g->tdual;
     d.h0 = g->box / g->n0;
     d.inv_h0 = g->n0 / g->box;
     d.inv_hf = std::ldexp(d.inv_h0, g->max_level + 1);
@@ -243,7 +251,7 @@ int mpath_grid_workspace_bytes(const mpath_grid_desc* desc, size_t* bytes)
     if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
     const int rc = check_grid_desc(desc);
     if (rc) return rc;
-    *bytes = grid_layout(desc->n_cells).total;
+    *bytes = grid_layout(desc->n_cells, desc->dphi_deta != nullptr).total;
     return MPATH_OK;
 }
 
@@ -259,7 +267,8 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     if (!stat && !(cosmo->omega_m > 0.0 && cosmo->omega_l >= 0.0 &&
                    std::fabs(cosmo->omega_m + cosmo->omega_l - 1.0) < 1e-12))
         return fail(MPATH_ERR_UNSUPPORTED, "only flat LCDM (omega_m + omega_l = 1) or a static background");
-    const GridLayout lay = grid_layout(d->n_cells);
+    const bool time_dep = d->dphi_deta != nullptr;
+    const GridLayout lay = grid_layout(d->n_cells, time_dep);
     if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
     if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "grid workspace too small");
 
@@ -311,8 +320,12 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     // ---- pack (phi, grad) as float32 and the cell coordinates in library order ----
     std::vector<float4> payload(n);
     std::vector<int4> cellpos(n);
+    std::vector<float> tpay(time_dep ? n : 0);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t c = perm[i];
+        if (time_dep)
+            tpay[i] = d->value_dtype == MPATH_F64 ? (float)((const double*)d->dphi_deta)[c]
+                                                  : ((const float*)d->dphi_deta)[c];
         cellpos[i] = make_int4(d->ijk[3 * c], d->ijk[3 * c + 1], d->ijk[3 * c + 2], (int)d->level[c]);
         if (d->value_dtype == MPATH_F64) {
             const double* p = (const double*)d->phi;
@@ -364,6 +377,10 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     G->leafinfo = (int32_t*)(G->ws + lay.off_leafinfo);
     G->dual_ids = (int32_t*)(G->ws + lay.off_dual_ids);
     G->table = (double2*)(G->ws + lay.off_table);
+    if (time_dep) {
+        G->tpay = (float*)(G->ws + lay.off_tpay);
+        G->tdual = (float4*)(G->ws + lay.off_tdual);
+    }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     const GridDev gd = make_griddev(G);
@@ -375,6 +392,8 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
         (e = launch_build_dual(gd, G->cellpos, G->dual, n, s)) ||
         (e = launch_build_leafinfo(gd, G->cellpos, G->leafinfo, n, s)) ||
         (e = launch_build_dual_ids(gd, G->cellpos, G->dual_ids, n, s)) ||
+        (time_dep && (e = hipMemcpyAsync(G->tpay, tpay.data(), (size_t)n * 4, hipMemcpyHostToDevice, s))) ||
+        (time_dep && (e = launch_build_tdual(gd, G->cellpos, G->tpay, G->tdual, n, s))) ||
         (e = hipStreamSynchronize(s))) {
         delete G;
         return hip_fail(e, "grid upload");
@@ -384,6 +403,28 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
         hipDeviceGetAttribute(&G->num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         G->num_cus = 0;
     *out = G;
+    return MPATH_OK;
+}
+
+int mpath_double_layer(int64_t n, const double* phi1, const double* phi2, const double* a1, const double* a2,
+                       const mpath_cosmo* cosmo, double* dphi_deta)
+{
+    if (n < 0) return fail(MPATH_ERR_INVALID_ARG, "n must be >= 0");
+    if (!cosmo) return fail(MPATH_ERR_INVALID_ARG, "cosmo is NULL");
+    if (n > 0 && (!phi1 || !phi2 || !a1 || !a2 || !dphi_deta)) return fail(MPATH_ERR_INVALID_ARG, "an array is NULL");
+    if (!(cosmo->omega_m > 0.0 && cosmo->omega_l >= 0.0 && std::fabs(cosmo->omega_m + cosmo->omega_l - 1.0) < 1e-12))
+        return fail(MPATH_ERR_UNSUPPORTED, "the double layer needs an expanding flat LCDM background");
+    Background bg;
+    bg.init(cosmo->omega_m, cosmo->omega_l);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(a1[i] > 0.0 && a2[i] > 0.0 && a1[i] != a2[i]) || !std::isfinite(a1[i]) || !std::isfinite(a2[i]))
+            return fail(MPATH_ERR_INVALID_ARG, "cell " + std::to_string(i) + ": layers need 0 < a1 != a2");
+        // dPhi/da from the two layers, times da/deta = a (a'/a) at the midpoint
+        const double am = 0.5 * (a1[i] + a2[i]);
+        double H, dH;
+        bg.hubble(am, H, dH);
+        dphi_deta[i] = (phi2[i] - phi1[i]) / (a2[i] - a1[i]) * (am * H);
+    }
     return MPATH_OK;
 }
 
@@ -698,6 +739,11 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
     a.out.hash = out->hash;
     a.out.chi = out->chi;
     a.out.z1 = out->z1;
+    a.out.z4 = out->z4;
+    a.out.isw = out->isw;
+    if (g->tdual && (inf || d->order != 1 || d->checkpoint_every > 0 || d->n_surfaces > 0))
+        return fail(MPATH_ERR_UNSUPPORTED,
+                    "a time-dependent potential is cast with order 1, one stop surface and no checkpoints");
 
     if (d->dirs) {
         e = n_rays ? hipMemcpyAsync(a.dirs, d->dirs, (size_t)n_rays * 24, hipMemcpyDeviceToDevice, s) : hipSuccess;
@@ -741,7 +787,8 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
             e = launch_cast_static(a, block, s);
         } else {
             int wpc = d->waves_per_cu;
-            if (wpc <= 0) wpc = cast_occupancy_blocks_per_cu(block, g->max_level > 0) * (block / 64);
+            if (wpc <= 0)
+                wpc = cast_occupancy_blocks_per_cu(block, g->max_level > 0, g->tdual != nullptr) * (block / 64);
             if (wpc <= 0) wpc = 8;
             const int cus = g->num_cus > 0 ? g->num_cus : 256;
             const int blocks = std::max(1, cus * wpc / (block / 64));
@@ -772,6 +819,7 @@ int mpath_born_beam(const mpath_grid* g, const mpath_cast_desc* d, float* A, int
     int rc = cast_plan(g, d, &n_rays, obs, &lay);
     if (rc) return rc;
     if (d->checkpoint_every != 0) return fail(MPATH_ERR_INVALID_ARG, "the Born beam takes checkpoint_every 0");
+    if (g->tdual) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam of a time-dependent potential is not implemented");
     if (d->n_surfaces) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam takes one stop surface");
     if (d->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam is implemented for order = 1 (CIC)");
     if (n_rays > 0 && !A) return fail(MPATH_ERR_INVALID_ARG, "A is NULL");
@@ -813,6 +861,7 @@ int mpath_adjoint_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d,
     const int rc = cast_plan(g, d, &n_rays, obs, &lay);
     if (rc) return rc;
     if (d->checkpoint_every <= 0) return fail(MPATH_ERR_INVALID_ARG, "the adjoint needs checkpoint_every > 0");
+    if (g->tdual) return fail(MPATH_ERR_UNSUPPORTED, "the adjoint of a time-dependent potential is not implemented");
     *bytes = adjoint_layout(g, d, n_rays).total;
     return MPATH_OK;
 }
@@ -831,6 +880,7 @@ int adjoint_impl(const mpath_grid* g, const mpath_cast_desc* d, const mpath_obse
     int rc = cast_plan(g, d, &n_rays, obs, &lay);
     if (rc) return rc;
     if (d->checkpoint_every <= 0) return fail(MPATH_ERR_INVALID_ARG, "the adjoint needs checkpoint_every > 0");
+    if (g->tdual) return fail(MPATH_ERR_UNSUPPORTED, "the adjoint of a time-dependent potential is not implemented");
     if (!fwd || !fwd->n_steps || !fwd->status)
         return fail(MPATH_ERR_INVALID_ARG, "the forward n_steps and status arrays are required");
     if (!ad) return fail(MPATH_ERR_INVALID_ARG, "adjoint desc is NULL");
@@ -942,7 +992,7 @@ int mpath_autotune(const mpath_grid* g, const mpath_cast_desc* d, int32_t sample
     hipStream_t s = (hipStream_t)stream;
     // candidates: the static schedule, and the persistent one at the
     // resident occupancy, half and twice that, with refills every 8..128 steps
-    const int occ = std::max(1, cast_occupancy_blocks_per_cu(256, g->max_level > 0) * 4);
+    const int occ = std::max(1, cast_occupancy_blocks_per_cu(256, g->max_level > 0, g->tdual != nullptr) * 4);
     struct Cand { int32_t schedule, wpc, batch; };
     std::vector<Cand> cands = {{MPATH_SCHED_STATIC, 0, 0}};
     for (int w : {occ, std::max(1, occ / 2), 2 * occ})
@@ -1139,6 +1189,8 @@ int finder_plan(const mpath_grid* g, const mpath_finder_desc* f, FinderPlan& P, 
     if (!f->obs_pos) return fail(MPATH_ERR_INVALID_ARG, "obs_pos is NULL");
     if (f->n_src < 0 || (f->n_src > 0 && !f->src_pos)) return fail(MPATH_ERR_INVALID_ARG, "bad n_src or src_pos");
     if (f->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "only order = 1 (CIC) is implemented");
+    if (g->tdual)
+        return fail(MPATH_ERR_UNSUPPORTED, "the finder's exact Jacobian (the adjoint) needs a static potential");
     if (!(f->tol > 0.0)) return fail(MPATH_ERR_INVALID_ARG, "tol must be > 0");
     if (f->max_iter < 1) return fail(MPATH_ERR_INVALID_ARG, "max_iter must be >= 1");
     if (f->identity_iters < 0) return fail(MPATH_ERR_INVALID_ARG, "identity_iters must be >= 0");

@@ -65,8 +65,10 @@ def beta_to_vec(beta):
     return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1)
 
 
-def compare(gpu, ora, idx=None, max_flip_frac=0.0, flip_tol_arcsec=None):
-    """Element-by-element comparison; returns a summary dict.  Asserts."""
+def compare(gpu, ora, idx=None, max_flip_frac=0.0, flip_tol_arcsec=None, isw_tol=0.0):
+    """Element-by-element comparison; returns a summary dict.  Asserts.
+    isw_tol: absolute bar on the ISW integral (0 for a static potential,
+    where both sides must give exactly 0 and z4 = z1)."""
     g = {k: (v if idx is None else v[idx]) for k, v in gpu.items()}
     n = len(ora)
     assert np.array_equal(g["status"], ora["status"]), "status differs"
@@ -101,6 +103,15 @@ def compare(gpu, ora, idx=None, max_flip_frac=0.0, flip_tol_arcsec=None):
             dz1 = np.abs(g["z1"][ok] - ora["z1"][ok])
             summary["max_dz1"] = float(dz1.max())
             assert np.all(dz1 <= TOL_Z * np.abs(ora["z1"][ok]) + 1e-11), summary
+        if "isw" in g:
+            # ISW integral (Sect. 2.5): float32 dPhi/deta samples and
+            # per-step sums; z4 = z1 - 2 (1 + z0) isw inherits both bars
+            disw = np.abs(g["isw"][ok] - ora["isw"][ok])
+            summary["max_disw"] = float(disw.max())
+            assert np.all(disw <= isw_tol), summary
+            dz4 = np.abs(g["z4"][ok] - ora["z4"][ok])
+            summary["max_dz4"] = float(dz4.max())
+            assert np.all(dz4 <= TOL_Z * np.abs(ora["z4"][ok]) + 1e-11 + 2 * (1 + ora["z0"][ok]) * isw_tol), summary
     if flip_tol_arcsec is not None and n_flip:
         summary["flip_max_sep_arcsec"] = float(sep[~same].max())
         assert summary["flip_max_sep_arcsec"] <= flip_tol_arcsec, summary
