@@ -33,11 +33,12 @@ _lib = None
 REACHED, LEFT_DOMAIN, MAX_STEPS, NONFINITE = 0, 1, 2, 3
 FIELD_GRID, FIELD_LINEAR, FIELD_QUADRATIC, FIELD_POINT = 0, 1, 2, 3
 STOP_REDSHIFT, STOP_CHI = 0, 1
+SURF_ETA, SURF_CHI, SURF_LAMBDA, SURF_Z = 0, 1, 2, 3
 
 RAY_DTYPE = np.dtype([
     ("theta", "f8", 2), ("beta", "f8", 2), ("alpha", "f8", 2), ("sep2", "f8"),
     ("z5", "f8"), ("z0", "f8"), ("z1", "f8"), ("z4", "f8"), ("isw", "f8"), ("phi_o", "f8"), ("phi_s", "f8"),
-    ("chi", "f8"), ("r", "f8", 3), ("k", "f8", 4), ("eta", "f8"), ("max_null", "f8"),
+    ("chi", "f8"), ("r", "f8", 3), ("k", "f8", 4), ("eta", "f8"), ("lam", "f8"), ("max_null", "f8"),
     ("n_steps", "i8"), ("status", "i4"), ("hash", "u4"),
 ], align=True)
 
@@ -54,7 +55,7 @@ class Cosmo(C.Structure):
 class CastParams(C.Structure):
     _fields_ = [("obs", C.c_double * 3), ("stop_kind", C.c_int), ("stop_value", C.c_double),
                 ("steps_per_cell", C.c_int), ("adaptive", C.c_int), ("ds_analytic", C.c_double),
-                ("max_steps", C.c_int64)]
+                ("max_steps", C.c_int64), ("surface", C.c_int)]
 
 
 def cosmo(omega_m=0.3, omega_l=0.7, h=0.7) -> Cosmo:
@@ -65,7 +66,7 @@ STATIC = Cosmo(0.0, 0.0, 1.0)
 
 
 def params(obs, z_src=None, chi=None, steps_per_cell=10, adaptive=False, ds=0.0,
-           max_steps=1 << 40) -> CastParams:
+           max_steps=1 << 40, surface=SURF_ETA) -> CastParams:
     p = CastParams()
     for i in range(3):
         p.obs[i] = float(obs[i])
@@ -77,6 +78,7 @@ def params(obs, z_src=None, chi=None, steps_per_cell=10, adaptive=False, ds=0.0,
     p.adaptive = int(bool(adaptive))
     p.ds_analytic = float(ds)
     p.max_steps = int(max_steps)
+    p.surface = int(surface)
     return p
 
 
@@ -103,6 +105,8 @@ def lib():
             getattr(L, name).argtypes = [C.POINTER(Cosmo), C.c_double]
         L.or_eta0.restype = C.c_double
         L.or_eta0.argtypes = [C.POINTER(Cosmo)]
+        L.or_lambda_of_a.restype = C.c_double
+        L.or_lambda_of_a.argtypes = [C.POINTER(Cosmo), C.c_double]
         L.or_cosmo_check.restype = C.c_int
         L.or_cosmo_check.argtypes = [C.POINTER(Cosmo)]
         L.or_pix2vec_nest.argtypes = [i64, i64, dp]
@@ -215,6 +219,11 @@ def conformal_hubble(c: Cosmo, eta: float) -> float:
 
 def eta0(c: Cosmo) -> float:
     return lib().or_eta0(C.byref(c))
+
+
+def lambda_of_a(c: Cosmo, a: float) -> float:
+    """Affine parameter of the FLRW photon from the observer to scale factor a."""
+    return lib().or_lambda_of_a(C.byref(c), a)
 
 
 def double_layer(phi1, phi2, a1, a2, c: Cosmo):

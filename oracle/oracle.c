@@ -42,7 +42,9 @@ struct or_field {
 
 typedef struct { const double* dphi; const double* dgrad; } cs_ctx;
 
-typedef struct { double eta0, eta_s, a_s; } derived_t;
+/* eta_s, a_s: the FLRW stop; p_s: the value of the stop surface's parameter
+ * there (ln(1 + z) for the redshift surface) */
+typedef struct { double eta0, eta_s, a_s, p_s; } derived_t;
 
 static inline uint32_t fnv_step(uint32_t h, uint32_t v) { return (h ^ v) * FNV_PRIME; }
 
@@ -296,6 +298,21 @@ static double hubble_of_a(const or_cosmo* c, double a)
 
 double or_eta0(const or_cosmo* c) { return is_static(c) ? 0.0 : or_eta_of_a(c, 1.0); }
 
+/* composite Simpson rule on 20000 intervals of 1/H(a) = a / (a'/a)(a) */
+double or_lambda_of_a(const or_cosmo* c, double a)
+{
+    if (is_static(c)) return NAN;
+    const int n = 20000;
+    const double h = (1.0 - a) / n;
+    double sum = 0.0;
+    for (int i = 0; i <= n; ++i) {
+        const double x = a + i * h;
+        const double f = 1.0 / (OR_H0 * sqrt(c->omega_m / (x * x * x) + c->omega_l));
+        sum += (i == 0 || i == n) ? f : (i % 2 ? 4.0 * f : 2.0 * f);
+    }
+    return sum * h / 3.0;
+}
+
 /* a(eta) by Newton iteration on eta as a function of y = sqrt(a), in which
  * eta is exactly linear during matter domination (d eta/dy = 2 / (y^3 H)),
  * started from the matter-dominated value and safeguarded by a bisection
@@ -407,6 +424,7 @@ static void tangent_basis(const double n[3], double e1[3], double e2[3])
 #define RE(z) (z)
 #define CSQRT sqrt
 #define CASIN asin
+#define CLOG log
 #define EXT1(f, df, z) (f)
 #define CELLV(v, dv) (v)
 #define SIGMA(st, c) atan2((st), (c))
@@ -417,6 +435,7 @@ static void tangent_basis(const double n[3], double e1[3], double e2[3])
 #undef RE
 #undef CSQRT
 #undef CASIN
+#undef CLOG
 #undef EXT1
 #undef CELLV
 #undef SIGMA
@@ -427,6 +446,7 @@ static void tangent_basis(const double n[3], double e1[3], double e2[3])
 #define RE(z) creal(z)
 #define CSQRT csqrt
 #define CASIN casin
+#define CLOG clog
 #define EXT1(f, df, z) ((f) + I * cimag(z) * (df))
 #define CELLV(v, dv) ((v) + I * (CS_H * (dv)))
 #define SIGMA(st, c) casin(st)
@@ -456,6 +476,18 @@ static int derive(const or_cosmo* c, const or_cast_params* p, derived_t* dv)
         dv->a_s = or_a_of_eta(c, dv->eta_s);
     } else {
         return -1;
+    }
+    switch (p->surface) {
+        case OR_SURF_ETA: dv->p_s = dv->eta_s; break;
+        case OR_SURF_CHI: dv->p_s = dv->eta0 - dv->eta_s; break;
+        case OR_SURF_LAMBDA:
+            dv->p_s = is_static(c) ? dv->eta0 - dv->eta_s : or_lambda_of_a(c, dv->a_s);
+            break;
+        case OR_SURF_Z:
+            if (is_static(c)) return -1;
+            dv->p_s = -log(dv->a_s);
+            break;
+        default: return -1;
     }
     return 0;
 }
@@ -570,13 +602,13 @@ static void* worker(void* arg)
                 }
                 trace_t_c R;
                 trace_c(J->f, &J->ctx, J->c, J->p, &J->dv, nc, &R, NULL, NULL);
-                observe_c(J->p, &J->dv, n, &R, J->out ? J->out + r : NULL, J->tan ? J->tan + r : NULL);
+                observe_c(J->c, J->p, &J->dv, n, &R, J->out ? J->out + r : NULL, J->tan ? J->tan + r : NULL);
             } else if (J->mode == 2) {
                 acc.f = J->f; acc.obs = J->p->obs; acc.n = n; acc.h_deriv = J->h_deriv;
                 acc.len = 0; acc.bad = 0;
                 trace_t_r R;
                 trace_r(J->f, &J->ctx, J->c, J->p, &J->dv, n, &R, inf_sample, &acc);
-                observe_r(J->p, &J->dv, n, &R, J->out ? J->out + r : NULL, NULL);
+                observe_r(J->c, J->p, &J->dv, n, &R, J->out ? J->out + r : NULL, NULL);
                 double* A = J->A + 4 * r;
                 A[0] = 1.0; A[1] = 0.0; A[2] = 0.0; A[3] = 1.0;
                 if (R.status != OR_REACHED || acc.len < 2) continue;
@@ -598,14 +630,14 @@ static void* worker(void* arg)
                  * (the landing step ends exactly on it), record the observables
                  * there, and continue from the landed state to the next */
                 trace_t_r R;
-                const int bad = trace_start_r(J->f, &J->ctx, J->p, &J->dvs[0], n, &R);
+                const int bad = trace_start_r(J->f, &J->ctx, J->c, J->p, &J->dvs[0], n, &R);
                 for (int k = 0; k < J->n_surf; ++k) {
                     if (!bad && (k == 0 || R.status == OR_REACHED)) {
                         R.status = -1;
                         trace_run_r(J->f, &J->ctx, J->c, J->p, &J->dvs[k], &R, NULL, NULL);
                         trace_end_r(J->f, &J->ctx, &R, NULL, NULL);
                     }
-                    observe_r(J->p, &J->dvs[k], n, &R, J->out + (int64_t)k * J->n_rays + r, NULL);
+                    observe_r(J->c, J->p, &J->dvs[k], n, &R, J->out + (int64_t)k * J->n_rays + r, NULL);
                 }
             } else if (J->mode == 3) {
                 /* Born approximation: the same line-of-sight integral along the
@@ -654,7 +686,7 @@ static void* worker(void* arg)
             } else {
                 trace_t_r R;
                 trace_r(J->f, &J->ctx, J->c, J->p, &J->dv, n, &R, NULL, NULL);
-                observe_r(J->p, &J->dv, n, &R, J->out + r, NULL);
+                observe_r(J->c, J->p, &J->dv, n, &R, J->out + r, NULL);
             }
         }
     }
@@ -723,7 +755,9 @@ int or_cast_surfaces(const or_field* f, const or_cosmo* c, const or_cast_params*
                      const double* stops, int64_t n_rays, const double* dirs, or_ray_out* out, int n_threads)
 {
     job_t J;
-    if (n_surf < 1 || n_surf > 64 || !stops || setup(&J, f, c, p, n_rays, dirs) || !out) return -1;
+    if (n_surf < 1 || n_surf > 64 || !stops || p->surface != OR_SURF_ETA || setup(&J, f, c, p, n_rays, dirs) ||
+        !out)
+        return -1;
     derived_t dvs[64];
     for (int k = 0; k < n_surf; ++k) {
         or_cast_params q = *p;
@@ -742,7 +776,7 @@ int or_born(const or_field* f, const or_cosmo* c, const or_cast_params* p, int64
             const double* dirs, double h_deriv, double* A, or_ray_out* out, int n_threads)
 {
     job_t J;
-    if (setup(&J, f, c, p, n_rays, dirs) || !A) return -1;
+    if (p->surface != OR_SURF_ETA || setup(&J, f, c, p, n_rays, dirs) || !A) return -1;
     J.A = A; J.out = out; J.h_deriv = h_deriv;
     J.mode = 3;
     return run_job(&J, n_threads);

@@ -64,12 +64,22 @@ double or_eta_of_a(const or_cosmo* c, double a);
 double or_a_of_eta(const or_cosmo* c, double eta);
 double or_conformal_hubble(const or_cosmo* c, double eta);   /* a'/a */
 double or_eta0(const or_cosmo* c);
+/* Affine parameter of the FLRW photon (k0 = -1 at a = 1) from the observer
+ * to scale factor a: int_a^1 da' / H(a') (a^2 d eta = da / H). */
+double or_lambda_of_a(const or_cosmo* c, double a);
 
 /* ---- HEALPix (NESTED scheme) pixel centre as a unit vector ---- */
 void or_pix2vec_nest(int64_t nside, int64_t pix, double vec[3]);
 
 /* ---- ray casting ---- */
 enum { OR_STOP_REDSHIFT = 0, OR_STOP_CHI = 1 };
+/* The surface a photon stops on (Sect. 2.4: maps on iso-p surfaces): the
+ * parameter p of the photon takes the value an FLRW photon has on the stop
+ * of stop_kind / stop_value.  ETA: eta = eta_s (iso-a too); CHI: comoving
+ * distance |x - x_obs| = eta_0 - eta_s; LAMBDA: affine parameter
+ * lambda = int a^2 d eta (k0 = -1 at the observer) of the FLRW photon;
+ * Z: observed redshift z5 = 1/a_s - 1. */
+enum { OR_SURF_ETA = 0, OR_SURF_CHI = 1, OR_SURF_LAMBDA = 2, OR_SURF_Z = 3 };
 enum { OR_REACHED = 0, OR_LEFT_DOMAIN = 1, OR_MAX_STEPS = 2, OR_NONFINITE = 3 };
 
 typedef struct {
@@ -80,6 +90,7 @@ typedef struct {
     int    adaptive;      /* 1: h of the leaf cell at the step start; 0: coarse h */
     double ds_analytic;   /* step length for closed-form fields */
     int64_t max_steps;
+    int    surface;       /* OR_SURF_*: the stop surface */
 } or_cast_params;
 
 typedef struct {
@@ -95,6 +106,7 @@ typedef struct {
     double r[3];          /* x_s - x_obs (unwrapped) */
     double k[4];          /* final (k^0, k^1, k^2, k^3) */
     double eta;           /* final conformal time */
+    double lam;           /* final affine parameter */
     double max_null;      /* max over step starts of |null condition| */
     int64_t n_steps;
     int32_t status;
