@@ -156,6 +156,11 @@ int mpath_grid_set_values(mpath_grid* grid, const float* values, void* stream);
 #define MPATH_STOP_REDSHIFT 0   /* stop_value[j] = z_src: eta_s = eta(a = 1/(1+z_src))         */
 #define MPATH_STOP_CHI 1        /* stop_value[j] = comoving distance: eta_s = eta_0 - value    */
 
+#define MPATH_SURFACE_ETA 0     /* stop surfaces (mpath_cast_desc.stop_surface)                  */
+#define MPATH_SURFACE_CHI 1
+#define MPATH_SURFACE_LAMBDA 2
+#define MPATH_SURFACE_Z 3
+
 #define MPATH_SCHED_AUTO 0      /* library choice (persistent when many observers/uneven rays) */
 #define MPATH_SCHED_STATIC 1    /* one lane per ray, one launch                                 */
 #define MPATH_SCHED_PERSISTENT 2/* resident waves pull ray batches from a global queue          */
@@ -210,6 +215,25 @@ typedef struct {
        cumulative).  Static schedule; order 1 and checkpoint_every 0 only. */
     int32_t n_surfaces;
     const double* surface_stops;
+    /* the parameter the stop surface holds (Sect. 2.4: maps on iso-p
+       surfaces, p in {a, eta, chi, z, lambda}, at the value p_n an FLRW
+       photon takes on the stop of stop_kind / stop_value):
+         MPATH_SURFACE_ETA     conformal time eta_s (iso-a too; the default)
+         MPATH_SURFACE_CHI     comoving distance |x - x_obs| = eta_0 - eta_s
+         MPATH_SURFACE_LAMBDA  affine parameter (k0 = -1 at the observer) of
+                               the FLRW photon, int_{a_s}^1 da / H(a)
+         MPATH_SURFACE_Z       observed redshift z5 = 1/a_s - 1
+       A photon stops where its own parameter reaches that value: on the
+       iso-eta surface the step that would cross it is solved by Newton
+       iterations; on the others the step that reaches the surface is taken
+       again from its start with the length that Newton iterations on
+       p(RK4(dl)) - p_n give (two iterations from the linear prediction, then
+       the step; iso-lambda: the remaining length exactly).  The observables
+       then refer to the end point's own scale factor a(eta) (z0 = 1/a - 1).
+       Non-eta surfaces: order 1, static potential, n_surfaces 0,
+       checkpoint_every 0 (no adjoint), static schedule; MPATH_SURFACE_Z
+       needs an expanding background. */
+    int32_t stop_surface;
 } mpath_cast_desc;
 
 /* Per-ray outputs: caller-allocated DEVICE arrays of length n_rays

@@ -46,6 +46,8 @@ struct RayRun {
     uint32_t hash;
     int status;           // -1 while running
     double isw;           // int dPhi/deta |d eta| so far (time-dependent potential; else 0)
+    double lam;           // affine parameter (iso-lambda stops)
+    double p_cur, dp_cur; // stop parameter and its lambda-derivative at y (iso-chi, iso-z stops)
     FC F;
 
     template <bool CKPT = false>
@@ -144,6 +146,136 @@ struct RayRun {
             ++n_steps;
         }
         return false;
+    }
+
+    // Stop parameter of state s and its lambda-derivative (iso-chi: the
+    // comoving distance r from the observer, d/dl = K r.m / r; iso-z:
+    // ln(1 + z5) with z5 of the end-point formula at s, d/dl =
+    // K (a'/a - m.G), the first-order rate of a K (1 + Phi)).  Returns false
+    // when the field has no stencil there.
+    template <int SURF>
+    __device__ __forceinline__ bool stop_param(const CastArgs& a, const GeoState& s, double& p, double& dp)
+    {
+        const double sp = a.grid.eta0 - s.eta;
+        double r[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[i] = fma(sp, geo.n[i], (double)s.dx[i]);
+        if constexpr (SURF == MPATH_SURFACE_CHI) {
+            const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+            double rm = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) rm += r[i] * (geo.n[i] + (double)s.d[i]);
+            p = rr;
+            dp = s.K * rm / rr;
+            return true;
+        } else {
+            double v[3];
+            grid_coords(a.grid, geo, s.eta, s.dx, v);
+            float phi, G[3];
+            int leafl, l;
+            if (F.eval(a.grid, v, phi, G, leafl, l)) return false;
+            const double sa = scale_factor(a.cosmo, s.eta);
+            p = log(sa * s.K * (1.0 + (double)phi) / (1.0 + (double)phi_o));
+            HubbleCubic Hc;
+            Hc.init(a.cosmo, s.eta);
+            double mG = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) mG += (geo.n[i] + (double)s.d[i]) * (double)G[i];
+            dp = s.K * (Hc(a.cosmo, s.eta) - mG);
+            return true;
+        }
+    }
+
+    // The integration to an iso-chi, iso-lambda or iso-z surface (SURF): the
+    // regular steps of advance; the step that reaches the surface is taken
+    // again from its start with the length from two Newton iterations on
+    // p(RK4(dl)) - p_s (iso-lambda: the remaining length exactly).
+    template <int SURF>
+    __device__ __forceinline__ void advance_stop(const CastArgs& a, double p_s)
+    {
+        if (status >= 0) return;
+        const GridDev& g = a.grid;
+        lam = 0.0;
+        if constexpr (SURF == MPATH_SURFACE_CHI) {
+            // at the observer: chi = 0, rising at |k| = K |n + d|
+            p_cur = 0.0;
+            dp_cur = 1.0 + (geo.n[0] * y.d[0] + geo.n[1] * y.d[1] + geo.n[2] * y.d[2]);
+        } else if constexpr (SURF == MPATH_SURFACE_Z) {
+            double v[3];
+            grid_coords(g, geo, y.eta, y.dx, v);
+            float phi, G[3];
+            int leafl, l;
+            F.eval(g, v, phi, G, leafl, l);
+            HubbleCubic Hc;
+            Hc.init(a.cosmo, y.eta);
+            double mG = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) mG += (geo.n[i] + (double)y.d[i]) * (double)G[i];
+            p_cur = 0.0;
+            dp_cur = Hc(a.cosmo, y.eta) - mG;
+        }
+        for (;;) {
+            if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return; }
+            double v[3];
+            grid_coords(g, geo, y.eta, y.dx, v);
+            int I[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
+            const int L = F.leaf(g, I);
+            if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+            hash = fnv(hash, (uint32_t)L);
+            const double dl = a.ds_level[L] / y.K;
+            GeoState yn;
+            if constexpr (SURF == MPATH_SURFACE_LAMBDA) {
+                if (lam + dl >= p_s) {
+                    const double dlx = p_s - lam;
+                    if (rk4_step<FC>(g, a.cosmo, F, geo, y, dlx, yn, hash)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+                    y = yn;
+                    lam += dlx;
+                    ++n_steps;
+                    status = finite_state(y) ? MPATH_RAY_REACHED : MPATH_RAY_NONFINITE;
+                    return;
+                }
+            }
+            if (rk4_step<FC>(g, a.cosmo, F, geo, y, dl, yn, hash)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+            if (!finite_state(yn)) { status = MPATH_RAY_NONFINITE; return; }
+            if constexpr (SURF != MPATH_SURFACE_LAMBDA) {
+                double pn, dpn;
+                if (!stop_param<SURF>(a, yn, pn, dpn)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+                if (pn >= p_s) {
+                    double dlx = (p_s - p_cur) / dp_cur;
+                    for (int it = 0; it < 2; ++it) {
+                        GeoState yt;
+                        double pt, dpt;
+                        if (rk4_step<FC>(g, a.cosmo, F, geo, y, dlx, yt, hash) || !stop_param<SURF>(a, yt, pt, dpt)) {
+                            status = MPATH_RAY_LEFT_DOMAIN;
+                            return;
+                        }
+                        dlx = dlx - (pt - p_s) / dpt;
+                    }
+                    if (rk4_step<FC>(g, a.cosmo, F, geo, y, dlx, yn, hash)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+                    y = yn;
+                    lam += dlx;
+                    ++n_steps;
+                    status = finite_state(y) ? MPATH_RAY_REACHED : MPATH_RAY_NONFINITE;
+                    return;
+                }
+                p_cur = pn;
+                dp_cur = dpn;
+            }
+            y = yn;
+            lam += dl;
+            ++n_steps;
+        }
+    }
+
+    // Outputs at the end of advance_stop: the end point's own scale factor.
+    __device__ __forceinline__ void finish_stop(const CastArgs& a)
+    {
+        int j = a.n_obs - 1;
+        while (j > 0 && a.obs[j].ray_first > ray) --j;
+        const double ae = scale_factor(a.cosmo, y.eta);
+        write_outputs(a, ray, j, ae, 1.0 / ae - 1.0, status);
     }
 
     // Redshift observables (Sect. 2.5) and the end state; the angular
@@ -451,6 +583,22 @@ __global__ __launch_bounds__(kBlock, 2) void cast_infbeam_kernel(CastArgs a, flo
     R.finish(a);
 }
 
+// One lane per ray to an iso-chi, iso-lambda or iso-z surface (SURF).
+template <bool AMR, int SURF>
+__global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_stop_kernel(CastArgs a)
+{
+    extern __shared__ float coef_lds[];
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    RayRun<AMR> R;
+    R.F.bind(coef_lds + threadIdx.x);
+    R.start(a, r);
+    int j = a.n_obs - 1;
+    while (j > 0 && a.obs[j].ray_first > r) --j;
+    R.template advance_stop<SURF>(a, a.obs[j].p_s);
+    R.finish_stop(a);
+}
+
 // Intermediate stop surfaces of a cast (the paper's maps at several source
 // redshifts from one run): landing on surface k < n_extra writes the ray's
 // observables there to output block k and sends the ray on to surface k + 1;
@@ -660,6 +808,31 @@ hipError_t launch_cast_surfaces(const CastArgs& a, const double2* surf, int n_ex
         hipLaunchKernelGGL(cast_surfaces_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, S);
     else
         hipLaunchKernelGGL(cast_surfaces_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_stop(const CastArgs& a, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n_rays + kBlock - 1) / kBlock)), blk(kBlock);
+    const size_t lds = (size_t)FieldCache<true>::kFloats * kBlock * sizeof(float);
+    const bool amr = a.grid.max_level > 0;
+    switch (a.surface) {
+        case MPATH_SURFACE_CHI:
+            if (amr) hipLaunchKernelGGL((cast_stop_kernel<true, MPATH_SURFACE_CHI>), grid, blk, lds, s, a);
+            else hipLaunchKernelGGL((cast_stop_kernel<false, MPATH_SURFACE_CHI>), grid, blk, lds, s, a);
+            break;
+        case MPATH_SURFACE_LAMBDA:
+            if (amr) hipLaunchKernelGGL((cast_stop_kernel<true, MPATH_SURFACE_LAMBDA>), grid, blk, lds, s, a);
+            else hipLaunchKernelGGL((cast_stop_kernel<false, MPATH_SURFACE_LAMBDA>), grid, blk, lds, s, a);
+            break;
+        case MPATH_SURFACE_Z:
+            if (amr) hipLaunchKernelGGL((cast_stop_kernel<true, MPATH_SURFACE_Z>), grid, blk, lds, s, a);
+            else hipLaunchKernelGGL((cast_stop_kernel<false, MPATH_SURFACE_Z>), grid, blk, lds, s, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

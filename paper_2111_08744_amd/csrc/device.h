@@ -128,6 +128,23 @@ struct HubbleCubic {
     }
 };
 
+// Scale factor a(eta): cubic Hermite interpolation of the (a, da/deta) table
+// on the nodes of the a'/a table (1 on a static background).
+__device__ inline double scale_factor(const CosmoDev& c, double eta)
+{
+    if (c.is_static) return 1.0;
+    const double u = (eta - c.eta_lo) * c.inv_deta;
+    int i = (int)floor(u);
+    i = i < 0 ? 0 : (i > c.n - 2 ? c.n - 2 : i);
+    const double t = u - (double)i;
+    const double2 p0 = c.atable[i];
+    const double2 p1 = c.atable[i + 1];
+    const double a0 = p0.x, a1 = c.deta * p0.y;
+    const double a2 = fma(-c.deta, fma(2.0, p0.y, p1.y), 3.0 * (p1.x - p0.x));
+    const double a3 = fma(c.deta, p0.y + p1.y, 2.0 * (p0.x - p1.x));
+    return fma(t, fma(t, fma(t, a3, a2), a1), a0);
+}
+
 // ---------------------------------------------------------------------------
 // Octree lookups.  Integer cell coordinates are kept unwrapped (a periodic
 // ray may leave the box) and wrapped only to address memory.

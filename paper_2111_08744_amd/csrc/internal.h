@@ -15,6 +15,7 @@ struct ObsDev {
     double eta_s;
     double a_s;
     double z0;
+    double p_s;          // value of the stop surface's parameter (eta, chi, lambda or ln(1 + z))
     int64_t pix_first;
     int64_t ray_first;   // index of the observer's first ray in the outputs
     int64_t count;
@@ -58,6 +59,7 @@ struct GridDev {
 // eta grid, for cubic Hermite interpolation.
 struct CosmoDev {
     const double2* table;     // (H, dH/deta) at eta_lo + i * deta
+    const double2* atable;    // (a, da/deta) at the same nodes
     double eta_lo;
     double inv_deta;
     double deta;
@@ -115,6 +117,7 @@ struct CastArgs {
     int32_t ckpt_slots;
     const double2* ray_stop;     // [n_rays] (eta_s, a_s) of each ray's own stop surface, or
                                  // NULL: the observer's (geodesic finder: one source per ray)
+    int32_t surface;             // MPATH_SURFACE_*: the parameter the stop surface holds
 };
 
 // Reverse-mode (adjoint) arguments.
@@ -136,6 +139,7 @@ struct AdjointArgs {
 inline int64_t grad_accumulator_floats(int64_t n) { return 4 * (((n + 7) >> 3) << 3); }
 
 // Kernel launchers (defined in cast.hip).
+hipError_t launch_cast_stop(const CastArgs& a, hipStream_t s);
 hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s);
 hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipStream_t s);
 hipError_t launch_observables(const CastArgs& a, hipStream_t s);

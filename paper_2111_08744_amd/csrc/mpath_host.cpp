@@ -92,6 +92,25 @@ struct Background {
     }
 
     double eta_of_a(double a) const { return is_static ? 0.0 : eta_of_y(std::sqrt(a)); }
+
+    // affine parameter of the FLRW photon (k0 = -1 at a = 1) from the
+    // observer to a: int_a^1 da' / H(a'), H = H0 sqrt(Om / a^3 + OL)
+    double lambda_of_a(double a) const
+    {
+        const int panels = 16;
+        const double w = (1.0 - a) / panels;
+        double sum = 0.0;
+        for (int p = 0; p < panels; ++p) {
+            const double c = a + (p + 0.5) * w;
+            double s = 0.0;
+            for (int i = 0; i < 20; ++i) {
+                const double x = c + 0.5 * w * gl_x[i];
+                s += gl_w[i] / (kH0 * std::sqrt(om / (x * x * x) + ol));
+            }
+            sum += 0.5 * w * s;
+        }
+        return sum;
+    }
     double eta0() const { return eta_of_a(1.0); }
 
     double a_of_eta(double eta) const
@@ -137,6 +156,7 @@ struct mpath_grid {
     int32_t* leafinfo = nullptr;
     int32_t* dual_ids = nullptr;
     double2* table = nullptr;
+    double2* atable = nullptr;    // (a, da/deta) on the nodes of table
     float* tpay = nullptr;        // dPhi/deta per cell (time-dependent potential), else null
     float4* tdual = nullptr;      // its 8 trilinear coefficients per stencil base
     int32_t level_start[kMaxLevels + 1] = {0};
@@ -147,7 +167,7 @@ namespace {
 
 struct GridLayout {
     size_t off_payload, off_child, off_perm, off_cellpos, off_dual, off_leafinfo, off_dual_ids, off_table;
-    size_t off_tpay, off_tdual, total;
+    size_t off_atable, off_tpay, off_tdual, total;
 };
 
 // Device workspace of a grid: 236 bytes per cell plus the background table,
@@ -164,7 +184,8 @@ GridLayout grid_layout(int64_t n, bool time_dep)
     L.off_leafinfo = align_up(L.off_dual + (size_t)n * 128, 256);
     L.off_dual_ids = align_up(L.off_leafinfo + (size_t)n * 32, 256);
     L.off_table = align_up(L.off_dual_ids + (size_t)n * 32, 256);
-    L.off_tpay = align_up(L.off_table + (size_t)kTableN * 16, 256);
+    L.off_atable = align_up(L.off_table + (size_t)kTableN * 16, 256);
+    L.off_tpay = align_up(L.off_atable + (size_t)kTableN * 16, 256);
     L.off_tdual = align_up(L.off_tpay + (time_dep ? (size_t)n * 4 : 0), 256);
     L.total = align_up(L.off_tdual + (time_dep ? (size_t)n * 32 : 0), 256);
     return L;
@@ -342,6 +363,7 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     G->bg.init(cosmo->omega_m, cosmo->omega_l);
     G->eta0 = G->bg.is_static ? 0.0 : G->bg.eta0();
     std::vector<double2> table(kTableN, make_double2(0.0, 0.0));
+    std::vector<double2> atable(kTableN, make_double2(1.0, 0.0));
     if (!G->bg.is_static) {
         const double lo = G->bg.eta_of_a(1.0 / (1.0 + kZMaxTable)) - 50.0;
         const double hi = G->eta0 + 50.0;
@@ -352,6 +374,7 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
             double H, dH;
             G->bg.hubble(a, H, dH);
             table[i] = make_double2(H, dH);
+            atable[i] = make_double2(a, a * H);
         }
     }
     // ---- upload ----
@@ -377,6 +400,7 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     G->leafinfo = (int32_t*)(G->ws + lay.off_leafinfo);
     G->dual_ids = (int32_t*)(G->ws + lay.off_dual_ids);
     G->table = (double2*)(G->ws + lay.off_table);
+    G->atable = (double2*)(G->ws + lay.off_atable);
     if (time_dep) {
         G->tpay = (float*)(G->ws + lay.off_tpay);
         G->tdual = (float4*)(G->ws + lay.off_tdual);
@@ -389,6 +413,7 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
         (e = hipMemcpyAsync(G->perm, perm.data(), (size_t)n * 8, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(G->cellpos, cellpos.data(), (size_t)n * 16, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(G->table, table.data(), (size_t)kTableN * 16, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(G->atable, atable.data(), (size_t)kTableN * 16, hipMemcpyHostToDevice, s)) ||
         (e = launch_build_dual(gd, G->cellpos, G->dual, n, s)) ||
         (e = launch_build_leafinfo(gd, G->cellpos, G->leafinfo, n, s)) ||
         (e = launch_build_dual_ids(gd, G->cellpos, G->dual_ids, n, s)) ||
@@ -512,6 +537,15 @@ int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_ra
     if (d->block_size && d->block_size != 256)
         return fail(MPATH_ERR_UNSUPPORTED, "the integration kernels run 256 threads per block (block_size 0 or 256)");
     if (d->checkpoint_every < 0) return fail(MPATH_ERR_INVALID_ARG, "checkpoint_every must be >= 0");
+    if (d->stop_surface < MPATH_SURFACE_ETA || d->stop_surface > MPATH_SURFACE_Z)
+        return fail(MPATH_ERR_INVALID_ARG, "unknown stop_surface");
+    if (d->stop_surface != MPATH_SURFACE_ETA &&
+        (d->order != 1 || d->checkpoint_every > 0 || d->n_surfaces > 0 || g->tdual))
+        return fail(MPATH_ERR_UNSUPPORTED,
+                    "iso-chi, iso-lambda and iso-z stops take order 1, a static potential, one surface and no "
+                    "checkpoints");
+    if (d->stop_surface == MPATH_SURFACE_Z && g->bg.is_static)
+        return fail(MPATH_ERR_UNSUPPORTED, "a static background has no redshift surface");
     const int64_t npix = 12ll * d->nside * d->nside;
     int64_t total = 0;
     for (int j = 0; j < d->n_obs; ++j) {
@@ -554,6 +588,13 @@ int make_obs_table(const mpath_grid* g, const mpath_cast_desc* d, std::vector<Ob
             o.a_s = g->bg.a_of_eta(o.eta_s);
         }
         o.z0 = 1.0 / o.a_s - 1.0;
+        // the stop surface's parameter at the FLRW photon's stop
+        switch (d->stop_surface) {
+            case MPATH_SURFACE_CHI: o.p_s = g->eta0 - o.eta_s; break;
+            case MPATH_SURFACE_LAMBDA: o.p_s = g->bg.is_static ? g->eta0 - o.eta_s : g->bg.lambda_of_a(o.a_s); break;
+            case MPATH_SURFACE_Z: o.p_s = -std::log(o.a_s); break;
+            default: o.p_s = o.eta_s; break;
+        }
         o.pix_first = d->pix_first ? d->pix_first[j] : 0;
         o.count = d->pix_count ? d->pix_count[j] : 12ll * d->nside * d->nside;
         o.ray_first = first;
@@ -588,6 +629,8 @@ CastArgs make_cast_args(const mpath_grid* g, const mpath_cast_desc* d, const Cas
     std::memset(&a, 0, sizeof a);
     a.grid = make_griddev(g);
     a.cosmo.table = g->table;
+    a.cosmo.atable = g->atable;
+    a.surface = d->stop_surface;
     a.cosmo.eta_lo = g->table_eta_lo;
     a.cosmo.deta = g->table_deta;
     a.cosmo.inv_deta = g->table_deta > 0 ? 1.0 / g->table_deta : 0.0;
@@ -744,6 +787,8 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
     if (g->tdual && (inf || d->order != 1 || d->checkpoint_every > 0 || d->n_surfaces > 0))
         return fail(MPATH_ERR_UNSUPPORTED,
                     "a time-dependent potential is cast with order 1, one stop surface and no checkpoints");
+    if (d->stop_surface != MPATH_SURFACE_ETA && (inf || ray_stop))
+        return fail(MPATH_ERR_UNSUPPORTED, "the infinitesimal beam and the finder stop on iso-eta surfaces");
 
     if (d->dirs) {
         e = n_rays ? hipMemcpyAsync(a.dirs, d->dirs, (size_t)n_rays * 24, hipMemcpyDeviceToDevice, s) : hipSuccess;
@@ -775,6 +820,8 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
     }
     if (inf) {
         e = launch_cast_infbeam(a, inf_A, s);
+    } else if (d->stop_surface != MPATH_SURFACE_ETA) {
+        e = launch_cast_stop(a, s);
     } else if (d->order != 1) {
         e = launch_cast_order(a, d->order, s);
     } else if (d->checkpoint_every > 0) {
@@ -820,6 +867,8 @@ int mpath_born_beam(const mpath_grid* g, const mpath_cast_desc* d, float* A, int
     if (rc) return rc;
     if (d->checkpoint_every != 0) return fail(MPATH_ERR_INVALID_ARG, "the Born beam takes checkpoint_every 0");
     if (g->tdual) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam of a time-dependent potential is not implemented");
+    if (d->stop_surface != MPATH_SURFACE_ETA)
+        return fail(MPATH_ERR_UNSUPPORTED, "the Born beam stops on iso-eta surfaces");
     if (d->n_surfaces) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam takes one stop surface");
     if (d->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam is implemented for order = 1 (CIC)");
     if (n_rays > 0 && !A) return fail(MPATH_ERR_INVALID_ARG, "A is NULL");

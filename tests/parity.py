@@ -65,10 +65,13 @@ def beta_to_vec(beta):
     return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1)
 
 
-def compare(gpu, ora, idx=None, max_flip_frac=0.0, flip_tol_arcsec=None, isw_tol=0.0):
+def compare(gpu, ora, idx=None, max_flip_frac=0.0, flip_tol_arcsec=None, isw_tol=0.0, z0_own=False):
     """Element-by-element comparison; returns a summary dict.  Asserts.
     isw_tol: absolute bar on the ISW integral (0 for a static potential,
-    where both sides must give exactly 0 and z4 = z1)."""
+    where both sides must give exactly 0 and z4 = z1).  z0_own: z0 is the
+    FLRW redshift of each end point's own scale factor (iso-chi, -lambda and
+    -z surfaces), which moves with the end point: the relative bar of z5;
+    otherwise it is the stop's, equal on both sides."""
     g = {k: (v if idx is None else v[idx]) for k, v in gpu.items()}
     n = len(ora)
     assert np.array_equal(g["status"], ora["status"]), "status differs"
@@ -95,7 +98,10 @@ def compare(gpu, ora, idx=None, max_flip_frac=0.0, flip_tol_arcsec=None, isw_tol
         dphi = np.abs(g["phi_src"][ok] - ora["phi_s"][ok]).max()
         summary["max_dphi"] = float(dphi)
         assert dphi <= 1e-6 * max(np.abs(ora["phi_s"]).max(), 1e-12), summary
-        assert np.all(g["z0"][ok] == ora["z0"][ok])
+        if z0_own:
+            assert np.all(np.abs(g["z0"][ok] - ora["z0"][ok]) <= TOL_Z * np.abs(ora["z0"][ok])), summary
+        else:
+            assert np.all(g["z0"][ok] == ora["z0"][ok])
         if "z1" in g:
             # z0 plus the potential term (Sect. 2.5): relative bar, with an
             # absolute floor at the level of float32 cell values (the term is
