@@ -34,6 +34,7 @@ REACHED, LEFT_DOMAIN, MAX_STEPS, NONFINITE = 0, 1, 2, 3
 FIELD_GRID, FIELD_LINEAR, FIELD_QUADRATIC, FIELD_POINT = 0, 1, 2, 3
 STOP_REDSHIFT, STOP_CHI = 0, 1
 SURF_ETA, SURF_CHI, SURF_LAMBDA, SURF_Z = 0, 1, 2, 3
+DPHIDL_CHAIN, DPHIDL_DIFF = 0, 1
 
 RAY_DTYPE = np.dtype([
     ("theta", "f8", 2), ("beta", "f8", 2), ("alpha", "f8", 2), ("sep2", "f8"),
@@ -55,7 +56,7 @@ class Cosmo(C.Structure):
 class CastParams(C.Structure):
     _fields_ = [("obs", C.c_double * 3), ("stop_kind", C.c_int), ("stop_value", C.c_double),
                 ("steps_per_cell", C.c_int), ("adaptive", C.c_int), ("ds_analytic", C.c_double),
-                ("max_steps", C.c_int64), ("surface", C.c_int)]
+                ("max_steps", C.c_int64), ("surface", C.c_int), ("dphidl", C.c_int)]
 
 
 def cosmo(omega_m=0.3, omega_l=0.7, h=0.7) -> Cosmo:
@@ -66,7 +67,7 @@ STATIC = Cosmo(0.0, 0.0, 1.0)
 
 
 def params(obs, z_src=None, chi=None, steps_per_cell=10, adaptive=False, ds=0.0,
-           max_steps=1 << 40, surface=SURF_ETA) -> CastParams:
+           max_steps=1 << 40, surface=SURF_ETA, dphidl=DPHIDL_CHAIN) -> CastParams:
     p = CastParams()
     for i in range(3):
         p.obs[i] = float(obs[i])
@@ -79,6 +80,7 @@ def params(obs, z_src=None, chi=None, steps_per_cell=10, adaptive=False, ds=0.0,
     p.ds_analytic = float(ds)
     p.max_steps = int(max_steps)
     p.surface = int(surface)
+    p.dphidl = int(dphidl)
     return p
 
 

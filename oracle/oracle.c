@@ -477,6 +477,7 @@ static int derive(const or_cosmo* c, const or_cast_params* p, derived_t* dv)
     } else {
         return -1;
     }
+    if (p->dphidl != OR_DPHIDL_CHAIN && p->dphidl != OR_DPHIDL_DIFF) return -1;
     switch (p->surface) {
         case OR_SURF_ETA: dv->p_s = dv->eta_s; break;
         case OR_SURF_CHI: dv->p_s = dv->eta0 - dv->eta_s; break;
@@ -788,7 +789,7 @@ int or_integrate_steps(const or_field* f, const or_cosmo* c, double* y, int64_t 
     double s[S_N] = {0}, out[S_N];
     memcpy(s, y, 8 * sizeof(double));
     for (int64_t i = 0; i < n; ++i) {
-        const int st = rk4_r(f, &ctx, c, s, dl[i], out, NULL, NULL);
+        const int st = rk4_r(f, &ctx, c, s, dl[i], out, NULL, NULL, NULL);
         if (st) return st;
         memcpy(s, out, sizeof out);
     }

@@ -80,6 +80,13 @@ enum { OR_STOP_REDSHIFT = 0, OR_STOP_CHI = 1 };
  * lambda = int a^2 d eta (k0 = -1 at the observer) of the FLRW photon;
  * Z: observed redshift z5 = 1/a_s - 1. */
 enum { OR_SURF_ETA = 0, OR_SURF_CHI = 1, OR_SURF_LAMBDA = 2, OR_SURF_Z = 3 };
+/* dPhi/dlambda in the geodesic equations (Sect. 2.2): CHAIN the chain rule
+ * grad Phi . k + (dPhi/deta) k0 (Eq. dPhi/dl, first form); DIFF the
+ * equations written with dPhi/dl only, which is estimated per step as the
+ * difference of Phi between the last two step starts over the affine
+ * length between them (Eq. dPhi/dl, second form; the first step takes
+ * grad Phi . k at the observer). */
+enum { OR_DPHIDL_CHAIN = 0, OR_DPHIDL_DIFF = 1 };
 enum { OR_REACHED = 0, OR_LEFT_DOMAIN = 1, OR_MAX_STEPS = 2, OR_NONFINITE = 3 };
 
 typedef struct {
@@ -91,6 +98,7 @@ typedef struct {
     double ds_analytic;   /* step length for closed-form fields */
     int64_t max_steps;
     int    surface;       /* OR_SURF_*: the stop surface */
+    int    dphidl;        /* OR_DPHIDL_* */
 } or_cast_params;
 
 typedef struct {
