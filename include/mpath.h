@@ -161,6 +161,9 @@ int mpath_grid_set_values(mpath_grid* grid, const float* values, void* stream);
 #define MPATH_SURFACE_LAMBDA 2
 #define MPATH_SURFACE_Z 3
 
+#define MPATH_DPHIDL_CHAIN 0    /* dPhi/dlambda (mpath_cast_desc.dphidl)                         */
+#define MPATH_DPHIDL_DIFF 1
+
 #define MPATH_SCHED_AUTO 0      /* library choice (persistent when many observers/uneven rays) */
 #define MPATH_SCHED_STATIC 1    /* one lane per ray, one launch                                 */
 #define MPATH_SCHED_PERSISTENT 2/* resident waves pull ray batches from a global queue          */
@@ -234,6 +237,22 @@ typedef struct {
        checkpoint_every 0 (no adjoint), static schedule; MPATH_SURFACE_Z
        needs an expanding background. */
     int32_t stop_surface;
+    /* dPhi/dlambda in the geodesic equations (Sect. 2.2):
+         MPATH_DPHIDL_CHAIN  the chain rule grad Phi . k + (dPhi/deta) k0 at
+                             every RK4 stage (Eq. dPhi/dl, first form; the default)
+         MPATH_DPHIDL_DIFF   the equations written with dPhi/dlambda only
+                             (dPhi/deta eliminated through the chain rule, so
+                             the time equation takes grad Phi . k), with
+                             dPhi/dlambda estimated once per step as the
+                             difference of Phi between the last two step
+                             starts over the affine length between them
+                             (Eq. dPhi/dl, second form); the first step takes
+                             grad Phi . k at the observer.  On a light cone it
+                             carries the time variation of Phi without a
+                             dPhi/deta field.
+       MPATH_DPHIDL_DIFF: order 1, static grid (no dphi_deta), iso-eta stop,
+       n_surfaces 0, checkpoint_every 0, static schedule. */
+    int32_t dphidl;
 } mpath_cast_desc;
 
 /* Per-ray outputs: caller-allocated DEVICE arrays of length n_rays

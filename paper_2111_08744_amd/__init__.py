@@ -138,7 +138,7 @@ class CastConfig:
     def __init__(self, obs, stop, nside, pix_first=None, pix_count=None, stop_kind="z",
                  steps_per_cell=10, adaptive=False, max_steps=1 << 40, schedule=0,
                  block_size=0, waves_per_cu=0, batch=0, checkpoint_every=0, dirs=None, order=1, surfaces=None,
-                 stop_surface="eta"):
+                 stop_surface="eta", dphidl="chain"):
         self.obs = np.ascontiguousarray(np.atleast_2d(obs), np.float64)
         self.stop = np.ascontiguousarray(np.atleast_1d(stop), np.float64)
         self.nside = int(nside)
@@ -158,6 +158,8 @@ class CastConfig:
         # the parameter the stop surface holds (mpath_cast_desc.stop_surface)
         self.stop_surface = {"eta": 0, "chi": 1, "lambda": 2, "z": 3}[stop_surface] \
             if isinstance(stop_surface, str) else int(stop_surface)
+        # dPhi/dlambda: "chain" (chain rule) or "diff" (difference between step starts)
+        self.dphidl = {"chain": 0, "diff": 1}[dphidl] if isinstance(dphidl, str) else int(dphidl)
         # intermediate stop surfaces [n_obs, n_s] (or [n_s] for every observer),
         # nearest first, each nearer than the observer's stop
         if surfaces is not None:
@@ -196,6 +198,7 @@ class CastConfig:
         d.n_surfaces = 0 if self.surfaces is None else self.surfaces.shape[1]
         d.surface_stops = None if self.surfaces is None else self.surfaces.ctypes.data
         d.stop_surface = self.stop_surface
+        d.dphidl = self.dphidl
         return d
 
     def n_blocks(self) -> int:

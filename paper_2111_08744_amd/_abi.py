@@ -29,6 +29,7 @@ MPATH_F32 = 1
 MPATH_STOP_REDSHIFT = 0
 MPATH_STOP_CHI = 1
 MPATH_SURFACE_ETA, MPATH_SURFACE_CHI, MPATH_SURFACE_LAMBDA, MPATH_SURFACE_Z = 0, 1, 2, 3
+MPATH_DPHIDL_CHAIN, MPATH_DPHIDL_DIFF = 0, 1
 MPATH_SCHED_AUTO = 0
 MPATH_SCHED_STATIC = 1
 MPATH_SCHED_PERSISTENT = 2
@@ -58,7 +59,7 @@ class mpath_cast_desc(C.Structure):
                 ("adaptive", C.c_int32), ("max_steps", C.c_int64), ("schedule", C.c_int32),
                 ("block_size", C.c_int32), ("waves_per_cu", C.c_int32), ("batch", C.c_int32),
                 ("checkpoint_every", C.c_int32), ("dirs", C.c_void_p), ("n_surfaces", C.c_int32),
-                ("surface_stops", C.c_void_p), ("stop_surface", C.c_int32)]
+                ("surface_stops", C.c_void_p), ("stop_surface", C.c_int32), ("dphidl", C.c_int32)]
 
 
 class mpath_observables(C.Structure):

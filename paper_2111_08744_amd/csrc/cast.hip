@@ -34,8 +34,8 @@ struct NoSample {
     __device__ __forceinline__ bool at_surface(const CastArgs&, Run&) { return false; }
 };
 
-// Everything one lane carries for its current ray.
-template <bool AMR, class FC = FieldCache<AMR>>
+// Everything one lane carries for its current ray (DP: the form of dPhi/dl).
+template <bool AMR, class FC = FieldCache<AMR>, class DP = ChainRule>
 struct RayRun {
     int64_t ray;          // -1: no ray
     RayGeom geo;
@@ -48,6 +48,7 @@ struct RayRun {
     double isw;           // int dPhi/deta |d eta| so far (time-dependent potential; else 0)
     double lam;           // affine parameter (iso-lambda stops)
     double p_cur, dp_cur; // stop parameter and its lambda-derivative at y (iso-chi, iso-z stops)
+    DP dp;
     FC F;
 
     template <bool CKPT = false>
@@ -75,6 +76,7 @@ struct RayRun {
         hash = kFnvOffset;
         status = -1;
         isw = 0.0;
+        if constexpr (DP::kDiff) dp.dl_prev = 0.0;
         float G[3];
         int leafl, l;
         if (F.eval(a.grid, geo.vo, phi_o, G, leafl, l)) {
@@ -125,7 +127,7 @@ struct RayRun {
             const int passes = landing ? 3 : 1;
             GeoState yn;
             for (int k = 0; k < passes; ++k) {
-                if (rk4_step<FC>(g, a.cosmo, F, geo, y, dlx, yn, hash)) {
+                if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dlx, yn, hash, dp)) {
                     status = MPATH_RAY_LEFT_DOMAIN;
                     return true;
                 }
@@ -144,6 +146,10 @@ struct RayRun {
             if (!fin) { status = MPATH_RAY_NONFINITE; return true; }
             y = yn;
             ++n_steps;
+            if constexpr (DP::kDiff) {
+                dp.phi_prev = dp.phi0;
+                dp.dl_prev = dl;
+            }
         }
         return false;
     }
@@ -583,6 +589,21 @@ __global__ __launch_bounds__(kBlock, 2) void cast_infbeam_kernel(CastArgs a, flo
     R.finish(a);
 }
 
+// One lane per ray with dPhi/dl from the difference of Phi between step
+// starts (the second form of the geodesic equations).
+template <bool AMR>
+__global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_diff_kernel(CastArgs a)
+{
+    extern __shared__ float coef_lds[];
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    RayRun<AMR, FieldCache<AMR>, StepDifference> R;
+    R.F.bind(coef_lds + threadIdx.x);
+    R.start(a, r);
+    R.advance(a, 0x7fffffff);
+    R.finish(a);
+}
+
 // One lane per ray to an iso-chi, iso-lambda or iso-z surface (SURF).
 template <bool AMR, int SURF>
 __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_stop_kernel(CastArgs a)
@@ -833,6 +854,16 @@ hipError_t launch_cast_stop(const CastArgs& a, hipStream_t s)
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_diff(const CastArgs& a, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n_rays + kBlock - 1) / kBlock)), blk(kBlock);
+    const size_t lds = (size_t)FieldCache<true>::kFloats * kBlock * sizeof(float);
+    if (a.grid.max_level > 0) hipLaunchKernelGGL(cast_diff_kernel<true>, grid, blk, lds, s, a);
+    else hipLaunchKernelGGL(cast_diff_kernel<false>, grid, blk, lds, s, a);
     return hipGetLastError();
 }
 

@@ -620,6 +620,25 @@ __device__ __forceinline__ void grid_coords(const GridDev& g, const RayGeom& r, 
     for (int i = 0; i < 3; ++i) v[i] = fma(fma(s, r.n[i], (double)dx[i]), g.inv_hf, r.vo[i]);
 }
 
+// dPhi/dl in the spatial geodesic equation.  ChainRule: grad Phi . k
+// (+ dPhi/deta k0 on a time-dependent grid) at every RK4 stage (Eq. dPhi/dl,
+// first form).  StepDifference: the equations written with dPhi/dl only
+// (dPhi/deta eliminated, so the time equation takes grad Phi . k) and
+// dPhi/dl estimated once per step as the difference of Phi between the last
+// two step starts over the affine length between them (Eq. dPhi/dl, second
+// form; the first step takes grad Phi . k at the observer).
+struct ChainRule {
+    static constexpr bool kDiff = false;
+};
+
+struct StepDifference {
+    static constexpr bool kDiff = true;
+    float phi_prev;     // Phi at the previous step start
+    double dl_prev;     // affine length of the previous step (0: no step yet)
+    float phi0;         // Phi at the start of the step being taken
+    float D;            // its dPhi/dl
+};
+
 // No-op stage recorder of the forward kernels.
 struct NoRecord {
     template <class FC>
@@ -635,10 +654,10 @@ struct NoRecord {
 // are appended to hash only when all four stages succeed (return 0).  When
 // record is set, the recorder receives every stage's state and stencil (base
 // id, level); the reverse sweep uses it to replay the forward stages exactly.
-template <class FC, class Rec>
-__device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC& F,
+template <class FC, class Rec, class DP>
+__device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
-                                        uint32_t& hash, Rec& rec, bool record)
+                                        uint32_t& hash, Rec& rec, bool record, DP& dp)
 {
     #pragma clang fp contract(off)
     const float nf[3] = {(float)r.n[0], (float)r.n[1], (float)r.n[2]};
@@ -691,6 +710,14 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC
         // subtracts n dK/dl, dK/dl = K^2 (2 H - 2 m.G)
         float cm = 4.0f * mG;
         if constexpr (FC::kTime) cm = fmaf(-2.0f, F.tv, cm);
+        if constexpr (DP::kDiff) {
+            // 2 m.G (from -n dK/dl) + 2 D / K (the spatial equation's dPhi/dl)
+            if (st == 0) {
+                dp.phi0 = phi;
+                dp.D = dp.dl_prev > 0.0 ? (float)(((double)phi - (double)dp.phi_prev) / dp.dl_prev) : Kf * mG;
+            }
+            cm = fmaf(2.0f, dp.D / Kf, 2.0f * mG);
+        }
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             f_dx[i] = Kf * yi.d[i];
@@ -728,6 +755,15 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC
     return 0;
 }
 
+template <class FC, class Rec>
+__device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC& F,
+                                        const RayGeom& r, const GeoState& y, double dl, GeoState& out,
+                                        uint32_t& hash, Rec& rec, bool record)
+{
+    ChainRule cr;
+    return rk4_core<FC, Rec, ChainRule>(g, cz, F, r, y, dl, out, hash, rec, record, cr);
+}
+
 template <class FC>
 __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
@@ -735,6 +771,16 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC
 {
     NoRecord none;
     return rk4_step<FC, NoRecord>(g, cz, F, r, y, dl, out, hash, none, false);
+}
+
+// The forward step with a choice of dPhi/dl (ChainRule or StepDifference).
+template <class FC, class DP>
+__device__ __forceinline__ int rk4_step_dp(const GridDev& g, const CosmoDev& cz, FC& F,
+                                           const RayGeom& r, const GeoState& y, double dl, GeoState& out,
+                                           uint32_t& hash, DP& dp)
+{
+    NoRecord none;
+    return rk4_core<FC, NoRecord, DP>(g, cz, F, r, y, dl, out, hash, none, false, dp);
 }
 
 // NaN or infinity anywhere in the state (a sum of the small FP32 parts is

@@ -140,6 +140,7 @@ inline int64_t grad_accumulator_floats(int64_t n) { return 4 * (((n + 7) >> 3) <
 
 // Kernel launchers (defined in cast.hip).
 hipError_t launch_cast_stop(const CastArgs& a, hipStream_t s);
+hipError_t launch_cast_diff(const CastArgs& a, hipStream_t s);
 hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s);
 hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipStream_t s);
 hipError_t launch_observables(const CastArgs& a, hipStream_t s);

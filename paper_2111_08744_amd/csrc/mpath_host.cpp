@@ -546,6 +546,14 @@ int check_cast_desc(const mpath_grid* g, const mpath_cast_desc* d, int64_t* n_ra
                     "checkpoints");
     if (d->stop_surface == MPATH_SURFACE_Z && g->bg.is_static)
         return fail(MPATH_ERR_UNSUPPORTED, "a static background has no redshift surface");
+    if (d->dphidl != MPATH_DPHIDL_CHAIN && d->dphidl != MPATH_DPHIDL_DIFF)
+        return fail(MPATH_ERR_INVALID_ARG, "unknown dphidl");
+    if (d->dphidl == MPATH_DPHIDL_DIFF &&
+        (d->order != 1 || d->checkpoint_every > 0 || d->n_surfaces > 0 || g->tdual ||
+         d->stop_surface != MPATH_SURFACE_ETA))
+        return fail(MPATH_ERR_UNSUPPORTED,
+                    "the step-difference dPhi/dlambda takes order 1, a static grid, the iso-eta stop, one surface "
+                    "and no checkpoints");
     const int64_t npix = 12ll * d->nside * d->nside;
     int64_t total = 0;
     for (int j = 0; j < d->n_obs; ++j) {
@@ -789,6 +797,8 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
                     "a time-dependent potential is cast with order 1, one stop surface and no checkpoints");
     if (d->stop_surface != MPATH_SURFACE_ETA && (inf || ray_stop))
         return fail(MPATH_ERR_UNSUPPORTED, "the infinitesimal beam and the finder stop on iso-eta surfaces");
+    if (d->dphidl != MPATH_DPHIDL_CHAIN && (inf || ray_stop))
+        return fail(MPATH_ERR_UNSUPPORTED, "the infinitesimal beam and the finder use the chain-rule dPhi/dlambda");
 
     if (d->dirs) {
         e = n_rays ? hipMemcpyAsync(a.dirs, d->dirs, (size_t)n_rays * 24, hipMemcpyDeviceToDevice, s) : hipSuccess;
@@ -822,6 +832,8 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
         e = launch_cast_infbeam(a, inf_A, s);
     } else if (d->stop_surface != MPATH_SURFACE_ETA) {
         e = launch_cast_stop(a, s);
+    } else if (d->dphidl != MPATH_DPHIDL_CHAIN) {
+        e = launch_cast_diff(a, s);
     } else if (d->order != 1) {
         e = launch_cast_order(a, d->order, s);
     } else if (d->checkpoint_every > 0) {
@@ -867,8 +879,8 @@ int mpath_born_beam(const mpath_grid* g, const mpath_cast_desc* d, float* A, int
     if (rc) return rc;
     if (d->checkpoint_every != 0) return fail(MPATH_ERR_INVALID_ARG, "the Born beam takes checkpoint_every 0");
     if (g->tdual) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam of a time-dependent potential is not implemented");
-    if (d->stop_surface != MPATH_SURFACE_ETA)
-        return fail(MPATH_ERR_UNSUPPORTED, "the Born beam stops on iso-eta surfaces");
+    if (d->stop_surface != MPATH_SURFACE_ETA || d->dphidl != MPATH_DPHIDL_CHAIN)
+        return fail(MPATH_ERR_UNSUPPORTED, "the Born beam stops on iso-eta surfaces (chain-rule dPhi/dlambda)");
     if (d->n_surfaces) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam takes one stop surface");
     if (d->order != 1) return fail(MPATH_ERR_UNSUPPORTED, "the Born beam is implemented for order = 1 (CIC)");
     if (n_rays > 0 && !A) return fail(MPATH_ERR_INVALID_ARG, "A is NULL");
