@@ -61,3 +61,33 @@ def test_grid_roots_reach_the_sources(O):
         rec = O.cast(f, c, O.params(obs, chi=chi, steps_per_cell=10), t1[i][None])[0]
         assert angular_separation(rec["r"], beta[i]) < 1e-11
     assert angular_separation(t1, beta).max() > 1e-6      # the sources are lensed
+
+
+def test_grid_search_fallback(O):
+    """Sources left unconverged by two identity-Jacobian iterations go to the
+    grid search: every round's best separation does not grow (the centre
+    candidate is the previous best direction), they converge, and the roots
+    are those of the exact Newton iteration (within the tolerance over the
+    smallest singular value of A, ~1)."""
+    import synth
+    cells = synth.make_cells("gauss64")
+    f = O.Field.grid(cells)
+    c = O.cosmo(0.3, 0.7, 0.7)
+    obs = np.array([250.0, 250.0, 250.0])
+    rng = np.random.default_rng(9)
+    src = obs + _dirs(4, 3) * rng.uniform(300.0, 1200.0, 4)[:, None]
+    tol = 1e-11
+    t0, it0, s0 = catalog.find_geodesics(f, c, obs, src, tol=tol, max_iter=2, identity_iters=2)
+    assert (it0 == -1).all()
+    t1, it1, s1 = catalog.find_geodesics(f, c, obs, src, tol=tol, max_iter=2, identity_iters=2,
+                                         grid_rounds=30, grid_n=5)
+    assert (it1 >= 2).all() and (s1 < tol).all()
+    tn, itn, _ = catalog.find_geodesics(f, c, obs, src, tol=tol)
+    assert (itn >= 0).all()
+    assert angular_separation(t1, tn).max() < 3 * tol
+    beta = (src - obs) / np.linalg.norm(src - obs, axis=1, keepdims=True)
+    for i in range(len(src)):
+        chi = np.linalg.norm(src[i] - obs)
+        p = O.params(obs, chi=chi, steps_per_cell=10)
+        _, r, _, seps = catalog.grid_search(f, c, p, t0[i], beta[i], 2.0 * s0[i], 5, 30, tol)
+        assert r >= 0 and all(b <= a for a, b in zip(seps, seps[1:]))
