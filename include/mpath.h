@@ -468,6 +468,20 @@ typedef struct {
     int32_t max_iter;           /* Newton iterations, >= 1                                */
     int32_t identity_iters;     /* iterations with A = I before the exact Jacobian, >= 0 */
     int32_t checkpoint_every;   /* K of the Jacobian sweeps, >= 1                         */
+    /* the last-resort root finder (Sect. 2.5) for sources still unconverged
+       after max_iter: grid_rounds (>= 0; 0 = none) rounds of grid_n x grid_n
+       candidate directions (grid_n odd, 3..15) on the screen plane of theta,
+       theta + a D e1 + b D e2 normalised, D = 2 w / (grid_n - 1), a and b in
+       -(grid_n-1)/2 .. (grid_n-1)/2 (candidate (b + h) grid_n + (a + h)); the
+       half-width w starts at twice the last Newton separation and becomes
+       the previous spacing D after every round.  All candidates are cast to
+       the source's surface in one launch; theta moves to the candidate that
+       lands nearest beta (the first of equal ones).  A source converging in
+       round r reports n_iter = max_iter + r.  At most grid_max sources
+       (0: all), the first by index, take part (it sizes the workspace). */
+    int32_t grid_rounds;
+    int32_t grid_n;
+    int64_t grid_max;
 } mpath_finder_desc;
 
 /* DEVICE outputs, arrays of n_src; theta is required, the others may be NULL. */
@@ -479,8 +493,9 @@ typedef struct {
     double* z0;                 /* FLRW redshift of the source's surface                            */
     float* phi_src;             /* Phi at the end point                                             */
     double* sep;                /* angle between the final end direction and beta (rad)             */
-    int32_t* n_iter;            /* iteration of convergence (0: the first cast); -1 not converged
-                                   within max_iter; -2 a cast did not reach the source              */
+    int32_t* n_iter;            /* iteration of convergence (0: the first cast; >= max_iter: in
+                                   round n_iter - max_iter of the grid search); -1 not converged;
+                                   -2 a cast did not reach the source                               */
     int32_t* status;            /* MPATH_RAY_* of the final cast                                    */
     double* z1;                 /* z0 + (1 + z0)(Phi_o - Phi_s)                                      */
 } mpath_finder_out;
@@ -488,11 +503,13 @@ typedef struct {
 /* Workspace: the checkpointed cast and Jacobian sweep of n_src rays plus
  * per-source tables (88 bytes per source). */
 int mpath_find_geodesics_workspace_bytes(const mpath_grid* grid, const mpath_finder_desc* desc, size_t* bytes);
-/* Synchronises the stream once per iteration (the count of sources still
- * iterating decides whether to continue).  Errors: INVALID_ARG (NULL
- * arrays, tol <= 0, max_iter < 1, identity_iters < 0, checkpoint_every < 1,
- * a source at the observer), UNSUPPORTED (order != 1, a source beyond the
- * background table, z > 20), WORKSPACE_TOO_SMALL, DEVICE. */
+/* Synchronises the stream once per iteration and grid round (the count of
+ * sources still iterating decides whether to continue).  Errors:
+ * INVALID_ARG (NULL arrays, tol <= 0, max_iter < 1, identity_iters < 0,
+ * checkpoint_every < 1, a source at the observer, grid_rounds < 0, grid_n
+ * not odd in 3..15 with grid_rounds > 0, grid_max < 0), UNSUPPORTED
+ * (order != 1, a source beyond the background table, z > 20),
+ * WORKSPACE_TOO_SMALL, DEVICE. */
 int mpath_find_geodesics(const mpath_grid* grid, const mpath_finder_desc* desc, mpath_finder_out* out,
                          void* dev_ws, size_t ws_bytes, void* stream);
 

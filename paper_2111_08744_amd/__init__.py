@@ -447,11 +447,14 @@ def infinitesimal_beam(grid: Grid, cfg: CastConfig, out=None, ws=None):
 
 
 def find_geodesics(grid: Grid, obs, src, steps_per_cell=10, adaptive=False, tol=1e-10, max_iter=10,
-                   identity_iters=3, checkpoint_every=32, max_steps=1 << 40, ws=None):
+                   identity_iters=3, checkpoint_every=32, max_steps=1 << 40, ws=None, grid_rounds=0, grid_n=5,
+                   grid_max=0):
     """mpath_find_geodesics: initial directions theta [n, 3] connecting the
     observer obs [3] to sources at comoving positions src [n, 3] (host
     arrays), with the exact distortion matrix A [n, 2, 2], dz5/dtheta [n, 2],
-    z5, z0, phi_src, the final angle sep to beta, n_iter and the status."""
+    z5, z0, phi_src, the final angle sep to beta, n_iter and the status.
+    grid_rounds > 0 adds the grid-search fallback (grid_n x grid_n
+    candidates, at most grid_max sources, 0 = all)."""
     torch = _torch()
     L = _abi.lib()
     obs = np.ascontiguousarray(obs, np.float64).reshape(3)
@@ -469,6 +472,9 @@ def find_geodesics(grid: Grid, obs, src, steps_per_cell=10, adaptive=False, tol=
     d.max_iter = int(max_iter)
     d.identity_iters = int(identity_iters)
     d.checkpoint_every = int(checkpoint_every)
+    d.grid_rounds = int(grid_rounds)
+    d.grid_n = int(grid_n)
+    d.grid_max = int(grid_max)
     nbytes = C.c_size_t()
     _abi.check(L.mpath_find_geodesics_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)),
                "mpath_find_geodesics_workspace_bytes")

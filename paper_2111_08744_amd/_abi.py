@@ -79,7 +79,8 @@ class mpath_finder_desc(C.Structure):
     _fields_ = [("obs_pos", C.c_void_p), ("n_src", C.c_int64), ("src_pos", C.c_void_p), ("order", C.c_int32),
                 ("steps_per_cell", C.c_int32), ("adaptive", C.c_int32), ("max_steps", C.c_int64),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("identity_iters", C.c_int32),
-                ("checkpoint_every", C.c_int32)]
+                ("checkpoint_every", C.c_int32), ("grid_rounds", C.c_int32),
+                ("grid_n", C.c_int32), ("grid_max", C.c_int64)]
 
 
 class mpath_finder_out(C.Structure):

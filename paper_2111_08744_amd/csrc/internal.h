@@ -184,6 +184,13 @@ hipError_t launch_finder_update(int64_t n, const RayEnd* ends, const double* tar
                                 double* sep, unsigned int* active, hipStream_t s);
 hipError_t launch_finder_sep(int64_t n, const RayEnd* ends, const double* target, const double* theta,
                              const int32_t* status, double eta0, double* sep, hipStream_t s);
+hipError_t launch_grid_init(int64_t m, const int64_t* idx, const double* sep, double* w, hipStream_t s);
+hipError_t launch_grid_dirs(int64_t m, int g, const int64_t* idx, const double* theta, const double* w,
+                            const double2* stop, double* dirs, double2* gstop, hipStream_t s);
+hipError_t launch_grid_pick(int64_t m, int g, const int64_t* idx, const RayEnd* ends, const double* dirs,
+                            const int32_t* status, const double* target, double eta0, double tol, int it,
+                            double* theta, double* sep, int32_t* n_iter, double* w, unsigned int* active,
+                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gather_probe(const void* table, size_t table_bytes, int record_bytes, int in_flight,
                                int64_t n_waves, int iters, uint32_t seed, float* out, hipStream_t s);

@@ -1241,6 +1241,11 @@ struct FinderPlan {
     size_t off_stop = 0, off_target = 0, off_iter = 0, off_status = 0, off_sep = 0, off_jac = 0, off_nsteps = 0,
            off_active = 0, off_cast = 0, off_adj = 0, cast_bytes = 0, adj_bytes = 0, total = 0;
     CastLayout lay;
+    // grid search: at most m_max sources, g x g candidates each
+    int64_t m_max = 0, gcount = 0;
+    int g = 0;
+    mpath_cast_desc gcd;
+    size_t off_gidx = 0, off_gw = 0, off_gdirs = 0, off_gstop = 0, off_gstatus = 0, off_gcast = 0, gcast_bytes = 0;
 };
 
 int finder_plan(const mpath_grid* g, const mpath_finder_desc* f, FinderPlan& P, bool tables)
@@ -1256,6 +1261,10 @@ int finder_plan(const mpath_grid* g, const mpath_finder_desc* f, FinderPlan& P, 
     if (f->max_iter < 1) return fail(MPATH_ERR_INVALID_ARG, "max_iter must be >= 1");
     if (f->identity_iters < 0) return fail(MPATH_ERR_INVALID_ARG, "identity_iters must be >= 0");
     if (f->checkpoint_every < 1) return fail(MPATH_ERR_INVALID_ARG, "checkpoint_every must be >= 1");
+    if (f->grid_rounds < 0) return fail(MPATH_ERR_INVALID_ARG, "grid_rounds must be >= 0");
+    if (f->grid_rounds > 0 && (f->grid_n < 3 || f->grid_n > 15 || f->grid_n % 2 == 0))
+        return fail(MPATH_ERR_INVALID_ARG, "grid_n must be odd in [3, 15]");
+    if (f->grid_max < 0) return fail(MPATH_ERR_INVALID_ARG, "grid_max must be >= 0");
     P.n = f->n_src;
     const double amin = 1.0 / (1.0 + kZMaxTable);
     const double eta_min = g->bg.is_static ? -INFINITY : g->bg.eta_of_a(amin);
@@ -1310,6 +1319,26 @@ int finder_plan(const mpath_grid* g, const mpath_finder_desc* f, FinderPlan& P, 
     P.off_adj = align_up(P.off_cast + P.cast_bytes, 256);
     P.adj_bytes = adjoint_layout(g, &P.cd, P.n).total;
     P.total = P.off_adj + P.adj_bytes;
+    if (f->grid_rounds > 0 && P.n > 0) {
+        P.g = f->grid_n;
+        P.m_max = f->grid_max > 0 ? std::min<int64_t>(f->grid_max, P.n) : P.n;
+        const size_t mg = (size_t)P.m_max * P.g * P.g;
+        P.gcount = (int64_t)mg;
+        P.gcd = P.cd;
+        P.gcd.pix_count = &P.gcount;
+        P.gcd.checkpoint_every = 0;
+        CastLayout gl;
+        rc = cast_plan(g, &P.gcd, &nr, obs, &gl);
+        if (rc) return rc;
+        P.off_gidx = align_up(P.total, 256);
+        P.off_gw = align_up(P.off_gidx + (size_t)P.m_max * 8, 256);
+        P.off_gdirs = align_up(P.off_gw + (size_t)P.m_max * 8, 256);
+        P.off_gstop = align_up(P.off_gdirs + mg * 24, 256);
+        P.off_gstatus = align_up(P.off_gstop + mg * 16, 256);
+        P.off_gcast = align_up(P.off_gstatus + mg * 4, 256);
+        P.gcast_bytes = gl.total;
+        P.total = P.off_gcast + P.gcast_bytes;
+    }
     return MPATH_OK;
 }
 
@@ -1383,6 +1412,55 @@ int mpath_find_geodesics(const mpath_grid* g, const mpath_finder_desc* f, mpath_
         if (!e) e = hipStreamSynchronize(s);
         if (e) return hip_fail(e, "finder iteration");
         if (left == 0) break;
+    }
+    if (f->grid_rounds > 0) {
+        // the last-resort root finder for the sources still iterating
+        std::vector<int32_t> it_h(n);
+        e = hipMemcpyAsync(it_h.data(), n_iter, n * 4, hipMemcpyDeviceToHost, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (e) return hip_fail(e, "grid search set-up");
+        std::vector<int64_t> idx;
+        for (int64_t i = 0; i < P.n && (int64_t)idx.size() < P.m_max; ++i)
+            if (it_h[i] == -1) idx.push_back(i);
+        const int64_t m = (int64_t)idx.size();
+        if (m > 0) {
+            int64_t* gidx = reinterpret_cast<int64_t*>(ws + P.off_gidx);
+            double* gw = reinterpret_cast<double*>(ws + P.off_gw);
+            double* gdirs = reinterpret_cast<double*>(ws + P.off_gdirs);
+            double2* gstop = reinterpret_cast<double2*>(ws + P.off_gstop);
+            int32_t* gstatus = reinterpret_cast<int32_t*>(ws + P.off_gstatus);
+            char* gws = ws + P.off_gcast;
+            e = hipMemcpyAsync(gidx, idx.data(), (size_t)m * 8, hipMemcpyHostToDevice, s);
+            if (!e) e = hipStreamSynchronize(s);
+            if (!e) e = launch_grid_init(m, gidx, sep, gw, s);
+            if (e) return hip_fail(e, "grid search set-up");
+            mpath_cast_desc gcd = P.gcd;
+            int64_t count = m * P.g * P.g;
+            gcd.pix_count = &count;
+            gcd.dirs = gdirs;
+            int64_t nr;
+            std::vector<ObsDev> gobs;
+            CastLayout gl;
+            rc = cast_plan(g, &gcd, &nr, gobs, &gl);
+            if (rc) return rc;
+            const RayEnd* gends = reinterpret_cast<const RayEnd*>(gws + gl.off_ends);
+            for (int r = 0; r < f->grid_rounds; ++r) {
+                e = launch_grid_dirs(m, P.g, gidx, theta, gw, stop, gdirs, gstop, s);
+                if (e) return hip_fail(e, "grid search directions");
+                mpath_observables go;
+                std::memset(&go, 0, sizeof go);
+                go.status = gstatus;
+                rc = cast_impl(g, &gcd, &go, gws, P.gcast_bytes, stream, false, nullptr, gstop);
+                if (rc) return rc;
+                e = launch_grid_pick(m, P.g, gidx, gends, gdirs, gstatus, target, g->eta0, f->tol, f->max_iter + r,
+                                     theta, sep, n_iter, gw, active, s);
+                unsigned int left = 0;
+                if (!e) e = hipMemcpyAsync(&left, active, sizeof left, hipMemcpyDeviceToHost, s);
+                if (!e) e = hipStreamSynchronize(s);
+                if (e) return hip_fail(e, "grid search round");
+                if (left == 0) break;
+            }
+        }
     }
     // final cast along theta, checkpointed for the distortion matrix there
     P.cd.checkpoint_every = K;

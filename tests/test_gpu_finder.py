@@ -130,3 +130,35 @@ def test_finder_edge_cases(M, gauss64):
         M.find_geodesics(grid, obs, obs[None, :] + 1e5)       # beyond z = 20
     with pytest.raises(RuntimeError):
         M.find_geodesics(grid, obs, obs[None, :] + 100.0, tol=0.0)
+
+
+def test_finder_grid_search_fallback(M, gauss64):
+    """Two identity-Jacobian iterations leave every lensed source
+    unconverged; the grid-search rounds (5 x 5 candidates, the grid halving
+    each round) bring them below the tolerance.  The roots land on the
+    sources under the oracle's integration and agree with the oracle's own
+    grid-search roots to the bar of the Newton roots (the two integrations
+    differ by ~1e-4 arcsec, so the candidate picks need not agree)."""
+    obs = np.array([250.0, 250.0, 250.0])
+    src = _sources(obs, 24, 24, 300.0, 1200.0)
+    grid = M.Grid(gauss64, COSMO)
+    tol = 2e-10
+    res = M.find_geodesics(grid, obs, src, tol=tol, max_iter=2, identity_iters=2, grid_rounds=30, grid_n=5)
+    it = res["n_iter"].cpu().numpy()
+    _print("grid-search rounds:", np.bincount(it - 2))
+    assert (it >= 2).all() and (res["status"].cpu().numpy() == 0).all()
+    assert res["sep"].cpu().numpy().max() < tol
+    _check_against_oracle(gauss64, obs, src, res, 10, False)
+    t_o, it_o, _ = catalog.find_geodesics(O.Field.grid(gauss64), O.cosmo(*COSMO), obs, src[:8], tol=tol, max_iter=2,
+                                          identity_iters=2, grid_rounds=30, grid_n=5)
+    assert (it_o >= 2).all()
+    d = angular_separation(res["theta"].cpu().numpy()[:8], t_o) / ARCSEC
+    _print(f"GPU vs oracle grid-search roots: max {d.max():.2e} arcsec")
+    assert d.max() < 2 * TOL_ARCSEC
+    # grid_max caps the refined sources: the others stay unconverged
+    cap = M.find_geodesics(grid, obs, src, tol=tol, max_iter=2, identity_iters=2, grid_rounds=30, grid_n=5,
+                           grid_max=5)
+    itc = cap["n_iter"].cpu().numpy()
+    assert (itc[:5] >= 2).all() and (itc[5:] == -1).all()
+    with pytest.raises(M.MpathError):
+        M.find_geodesics(grid, obs, src, grid_rounds=3, grid_n=4)
