@@ -347,3 +347,85 @@ def test_amr_deep_jacobian_vs_oracle(M):
     d = np.abs(jac[ok] - A[ok]).max(axis=(1, 2))
     print("deep adjoint: max |dA|", d.max(), "median", np.median(d), flush=True)
     assert np.median(d) < 2e-7 and (d > 5e-6).sum() <= 1
+
+
+def _gpu_end_dirs(M, grid, z, dirs):
+    """End directions (unit vectors of x_s - x_obs) of GPU casts along dirs."""
+    import torch
+    from parity import beta_to_vec
+    cfg = M.CastConfig(OBS, z, 16, pix_count=[len(dirs)], dirs=torch.from_numpy(np.ascontiguousarray(dirs)).cuda(),
+                       steps_per_cell=10)
+    out = _fwd(M, grid, cfg)
+    assert (_np(out["status"]) == 0).all()
+    return beta_to_vec(_np(out["beta"]))
+
+
+def test_jacobian_vs_gpu_finite_differences(M, gauss64):
+    """A of the reverse sweep against central differences of GPU casts: the
+    192 pixel directions moved by +-1e-5 rad along e1, e2 (the screen basis
+    at theta), the end directions read on the basis at the unperturbed end
+    direction.  The end directions hold ~1e-11 rad; the float32 rounding
+    along two neighbouring paths differs by ~1e-10 rad, i.e. ~1e-5 in the
+    quotient, and a pair of paths straddling a cell face sees the kink of
+    the CIC force (rare)."""
+    from oracle.lensing import screen_basis
+    grid = M.Grid(gauss64, COSMO)
+    cfg = _cfg(M, 0.3, 4, 32)
+    out = _fwd(M, grid, cfg)
+    jac = _np(M.adjoint(grid, cfg, out, jacobian=True)["jac"]).astype(np.float64)
+    dirs = oracle_dirs(4, [0], [192])
+    e1, e2 = screen_basis(dirs)
+    f1, f2 = screen_basis(_gpu_end_dirs(M, grid, 0.3, dirs))
+    h = 1e-5
+    unit = lambda v: v / np.linalg.norm(v, axis=1, keepdims=True)
+    A = np.empty((len(dirs), 2, 2))
+    for b, e in enumerate((e1, e2)):
+        d = (_gpu_end_dirs(M, grid, 0.3, unit(dirs + h * e)) - _gpu_end_dirs(M, grid, 0.3, unit(dirs - h * e))) / (2 * h)
+        A[:, 0, b] = np.sum(d * f1, 1)
+        A[:, 1, b] = np.sum(d * f2, 1)
+    diff = np.abs(jac - A).max(axis=(1, 2))
+    lens = np.abs(A - np.eye(2)).max(axis=(1, 2))
+    _print(f"reverse sweep vs GPU central differences: max {diff.max():.2e}, median {np.median(diff):.2e}, "
+           f"|A - I| max {lens.max():.2e}")
+    assert lens.max() > 1e-3
+    assert np.median(diff) < 2e-5 and (diff > 1e-4).mean() <= 0.02
+
+
+def test_jacobian_vs_oracle_infinitesimal_beam(M):
+    """A of the reverse sweep (the exact derivative of the discrete map)
+    against the oracle's infinitesimal beam (Sect. 2.3.1: the line-of-sight
+    integral of the force Hessian, from differences of the interpolated
+    force over the leaf size): two estimators of the same distortion that
+    agree to first order in the lensing when the field is smooth on the cell
+    scale.  A band-limited potential (Fourier modes with |n| <= 3 over the
+    500 Mpc/h box, wavelengths >= 96 Mpc/h = 12 cells, rms 5e-5) keeps the
+    difference of the two Hessians at O((k h)^2 / 6) ~ 4 % of the shortest
+    modes; on the k^-3 Gaussian field the cell-scale part of the Hessian
+    dominates and the two differ by up to half the signal.  The symmetric
+    part of A is compared: its columns live on the e_phi basis at theta and
+    its rows on the one at beta, which near the poles are rotated against
+    each other by ~ alpha cot(theta) (an antisymmetric part of ~5e-4 here),
+    while the beam integrates on one basis per point."""
+    n, box = 64, 500.0
+    ff = synth.fourier_field(box, 7, kmax=3, rms=5e-5)
+    ii, jj, kk = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    centres = (np.stack([ii, jj, kk], -1).reshape(-1, 3) + 0.5) * (box / n)
+    phi, grad = ff(centres)
+    cells = synth.uniform_cells(phi.reshape(n, n, n), grad.reshape(n, n, n, 3), box)
+    grid = M.Grid(cells, COSMO)
+    cfg = _cfg(M, 0.3, 4, 32)
+    out = _fwd(M, grid, cfg)
+    jac = _np(M.adjoint(grid, cfg, out, jacobian=True)["jac"]).astype(np.float64)
+    dirs = oracle_dirs(4, [0], [192])
+    Ainf, rec = O.infinitesimal(O.Field.grid(cells), O.cosmo(*COSMO), _oracle_params(0.3), dirs)
+    assert (rec["status"] == O.REACHED).all()
+    sym = 0.5 * (jac + np.transpose(jac, (0, 2, 1)))
+    diff = np.abs(sym - Ainf).max(axis=(1, 2))
+    lens = np.abs(Ainf - np.eye(2)).max(axis=(1, 2))
+    k_adj = 1 - 0.5 * (jac[:, 0, 0] + jac[:, 1, 1])
+    k_inf = 1 - 0.5 * (Ainf[:, 0, 0] + Ainf[:, 1, 1])
+    corr = np.corrcoef(k_adj, k_inf)[0, 1]
+    _print(f"reverse sweep vs oracle infinitesimal beam: max |dA| {diff.max():.2e}, median {np.median(diff):.2e}, "
+           f"|A - I| max {lens.max():.2e}, convergence correlation {corr:.5f}")
+    assert lens.max() > 1e-3
+    assert corr > 0.99 and diff.max() < 0.1 * lens.max()
