@@ -286,9 +286,57 @@ def measure_finder(M, torch, dev):
     hist = np.bincount(it[it >= 0]).tolist()
     log(f"[bench] finder: {len(src)} sources in {t:.1f} ms, converged {int((it >= 0).sum())}, "
         f"iterations {hist}, max sep {float(res['sep'].max()):.2e} rad")
+    # the grid-search fallback alone: two identity iterations leave the
+    # first 2,048 sources unconverged, then 5 x 5 candidate rounds
+    sub = src[:2048]
+    g = {}
+    tg = _time_ms(torch, lambda: g.update(M.find_geodesics(grid, obs, sub, tol=1e-9, max_iter=2, identity_iters=2,
+                                                           grid_rounds=40, grid_n=5, ws=g.get("_ws"))), reps=1)
+    itg = g["n_iter"].cpu().numpy()
+    rounds = np.bincount(itg[itg >= 2] - 2).tolist()
+    log(f"[bench] finder grid search: {len(sub)} sources in {tg:.1f} ms, converged {int((itg >= 0).sum())}, "
+        f"rounds {rounds}")
     return {"workload": "16384 sources, chi U[200, 2300] Mpc/h, uniform 64^3 grid, tol 1e-9 rad",
             "sources": len(src), "ms": t, "sources_per_s": len(src) / (t / 1e3),
-            "converged": int((it >= 0).sum()), "iterations_histogram": hist}
+            "converged": int((it >= 0).sum()), "iterations_histogram": hist,
+            "grid_search": {"workload": "the first 2048 sources: 2 identity iterations, then 5x5 grid rounds",
+                            "ms": tg, "converged": int((itg >= 0).sum()), "rounds_histogram": rounds}}
+
+
+def measure_variants(M, torch, dev):
+    """The cast variants on the same rays, 196,608 rays (nside 128) to z = 1
+    on the uniform 64^3 grid, 10 steps per cell: the plain cast; with
+    dPhi/deta from the two synthetic layers (Sect. 2.2) and the ISW integral;
+    the iso-chi, iso-lambda and iso-z stops (Sect. 2.4); the second form of
+    the geodesic equations (dPhi/dl from step differences); three more stop
+    surfaces at z = 0.25, 0.5, 0.75 in the same cast."""
+    import synth
+    cz = (0.3, 0.7, 0.7)
+    c1 = synth.make_cells("gauss64")
+    grid = M.Grid(c1, cz, device=dev)
+    c2 = synth.make_cells("gauss64")
+    c2.dphi_deta = M.double_layer(c1.phi, synth.make_cells("gauss64_layer2").phi, *synth.ISW_LAYER_A, cz)
+    tgrid = M.Grid(c2, cz, device=dev)
+    obs = [250.0, 250.0, 250.0]
+    base = dict(steps_per_cell=10, schedule=1)
+    cases = (("plain", grid, {}), ("time_dependent", tgrid, {}), ("iso_chi", grid, {"stop_surface": "chi"}),
+             ("iso_lambda", grid, {"stop_surface": "lambda"}), ("iso_z", grid, {"stop_surface": "z"}),
+             ("step_difference", grid, {"dphidl": "diff"}), ("surfaces_4", grid, {"surfaces": [0.25, 0.5, 0.75]}))
+    res = {}
+    for label, gr, kw in cases:
+        cfg = M.CastConfig(obs, 1.0, 128, **base, **kw)
+        n = cfg.n_rays()
+        out = M.alloc_outputs(n * cfg.n_blocks(), dev)
+        t = _time_ms(torch, lambda: M.cast(gr, cfg, out, out.get("_ws")))
+        steps = int(out["n_steps"][-n:].to(torch.int64).sum())
+        res[label] = {"ms": t, "ray_steps": steps, "ray_steps_per_s": steps / (t / 1e3)}
+    plain = res["plain"]["ms"]
+    for v in res.values():
+        v["cost_vs_plain"] = v["ms"] / plain
+    log("[bench] variants (uniform, nside 128, z = 1): " + ", ".join(
+        f"{k} {v['ms']:.2f} ms ({v['ray_steps_per_s'] / 1e9:.2f} G ray-steps/s)" for k, v in res.items()))
+    return {"workload": "196608 rays (nside 128) to z = 1 on the uniform 64^3 grid, 10 steps per cell",
+            **res}
 
 
 def measure_orders(M, torch, dev):
@@ -450,7 +498,7 @@ def main():
     if not args.no_secondary:
         sec = {"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev),
                "lensing": measure_lensing(M, torch, dev), "finder": measure_finder(M, torch, dev),
-               "orders": measure_orders(M, torch, dev)}
+               "orders": measure_orders(M, torch, dev), "variants": measure_variants(M, torch, dev)}
         res["secondary"] = sec
         res["adjoint_forward_ratio"] = sec["adjoint"]["adjoint_forward_ratio"]
     if not args.no_cpu_baseline:

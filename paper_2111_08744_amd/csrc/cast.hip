@@ -104,54 +104,61 @@ struct RayRun {
     {
         if (status >= 0) return true;
         const GridDev& g = a.grid;
-        for (int it = 0; it < max_iter; ++it) {
-            if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return true; }
-            if (CKPT && n_steps % a.ckpt_every == 0)
-                a.ckpt[(n_steps / a.ckpt_every) * a.n_rays + ray] = y;
-            // leaf level at the step start sets the step length (N steps per cell)
-            double v[3];
-            grid_coords(g, geo, y.eta, y.dx, v);
-            int I[3];
+        int it = 0;
+        for (;;) {
+            // regular steps up to the one that would cross the stop surface
+            for (;; ++it) {
+                if (it >= max_iter) return false;
+                if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return true; }
+                if (CKPT && n_steps % a.ckpt_every == 0)
+                    a.ckpt[(n_steps / a.ckpt_every) * a.n_rays + ray] = y;
+                // leaf level at the step start sets the step length (N steps per cell)
+                double v[3];
+                grid_coords(g, geo, y.eta, y.dx, v);
+                int I[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
-            const int L = F.leaf(g, I);
-            if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
-            hash = fnv(hash, (uint32_t)L);
-            smp.at_step(a, geo, y, L);
-            const double ds = a.ds_level[L];
-            const double dl = ds / y.K;
+                for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
+                const int L = F.leaf(g, I);
+                if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
+                hash = fnv(hash, (uint32_t)L);
+                smp.at_step(a, geo, y, L);
+                const double dl = a.ds_level[L] / y.K;
+                if (fma(-y.K, dl, y.eta) < eta_s) break;
+                GeoState yn;
+                if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dl, yn, hash, dp)) {
+                    status = MPATH_RAY_LEFT_DOMAIN;
+                    return true;
+                }
+                if constexpr (FC::kTime) isw += (double)F.isw_step;
+                if (!finite_state(yn)) { status = MPATH_RAY_NONFINITE; return true; }
+                y = yn;
+                ++n_steps;
+                if constexpr (DP::kDiff) {
+                    dp.phi_prev = dp.phi0;
+                    dp.dl_prev = dl;
+                }
+            }
+            ++it;
             // landing on the iso-eta surface: Newton on eta_RK4(dl) = eta_s
             // with derivative -K at the trial end, two iterations, then the step
-            const bool landing = fma(-y.K, dl, y.eta) < eta_s;
-            double dlx = landing ? (y.eta - eta_s) / y.K : dl;
-            const int passes = landing ? 3 : 1;
+            double dlx = (y.eta - eta_s) / y.K;
             GeoState yn;
-            for (int k = 0; k < passes; ++k) {
+            for (int k = 0; k < 3; ++k) {
                 if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dlx, yn, hash, dp)) {
                     status = MPATH_RAY_LEFT_DOMAIN;
                     return true;
                 }
-                if (k + 1 < passes) dlx = dlx + (yn.eta - eta_s) / yn.K;
+                if (k < 2) dlx = dlx + (yn.eta - eta_s) / yn.K;
             }
             const bool fin = finite_state(yn);
             if constexpr (FC::kTime) isw += (double)F.isw_step;
-            if (landing) {
-                y = yn;
-                ++n_steps;
-                if constexpr (!std::is_same<Smp, NoSample>::value)
-                    if (fin && smp.at_surface(a, *this)) continue;   // on to the next stop surface
-                status = fin ? MPATH_RAY_REACHED : MPATH_RAY_NONFINITE;
-                return true;
-            }
-            if (!fin) { status = MPATH_RAY_NONFINITE; return true; }
             y = yn;
             ++n_steps;
-            if constexpr (DP::kDiff) {
-                dp.phi_prev = dp.phi0;
-                dp.dl_prev = dl;
-            }
+            if constexpr (!std::is_same<Smp, NoSample>::value)
+                if (fin && smp.at_surface(a, *this)) continue;   // on to the next stop surface
+            status = fin ? MPATH_RAY_REACHED : MPATH_RAY_NONFINITE;
+            return true;
         }
-        return false;
     }
 
     // Stop parameter of state s and its lambda-derivative (iso-chi: the
