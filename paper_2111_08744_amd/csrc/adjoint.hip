@@ -557,17 +557,21 @@ __device__ __forceinline__ bool forward_step(const CastArgs& a, FieldCache<AMR>&
 {
     double ds, dl;
     if (!plan_step<AMR>(a, F, geo, y, eta_s, ds, dl, landing)) return false;
-    double dlx = landing ? (y.eta - eta_s) / y.K : dl;
     uint32_t h = 0;
+    ds_out = ds;
+    if (__builtin_expect(!landing, 1)) {
+        if (rk4_step<FieldCache<AMR>, Rec>(a.grid, a.cosmo, F, geo, y, dl, yn, h, rec, record)) return false;
+        dl_taken = dl;
+        return true;
+    }
     // landing: two Newton passes for the step length, then the step
-    const int passes = landing ? 3 : 1;
-    for (int k = 0; k < passes; ++k) {
-        if (rk4_step<FieldCache<AMR>, Rec>(a.grid, a.cosmo, F, geo, y, dlx, yn, h, rec, record && k + 1 == passes))
+    double dlx = (y.eta - eta_s) / y.K;
+    for (int k = 0; k < 3; ++k) {
+        if (rk4_step<FieldCache<AMR>, Rec>(a.grid, a.cosmo, F, geo, y, dlx, yn, h, rec, record && k == 2))
             return false;
-        if (k + 1 < passes) dlx = dlx + (yn.eta - eta_s) / yn.K;
+        if (k < 2) dlx = dlx + (yn.eta - eta_s) / yn.K;
     }
     dl_taken = dlx;
-    ds_out = ds;
     return true;
 }
 
