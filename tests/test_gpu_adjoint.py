@@ -429,3 +429,34 @@ def test_jacobian_vs_oracle_infinitesimal_beam(M):
            f"|A - I| max {lens.max():.2e}, convergence correlation {corr:.5f}")
     assert lens.max() > 1e-3
     assert corr > 0.99 and diff.max() < 0.1 * lens.max()
+
+
+def test_differentiated_full_size_sampled(M):
+    """The differentiated benchmark configuration itself: all 2^20 rays
+    (nside 512) to z = 1 on the 64^3 grid, checkpoints every 32 steps, the
+    Jacobian and the loss gradient in the sweep the benchmark times; A and
+    dz/dtheta of 48 seeded random rays against the oracle's complex step."""
+    import torch
+    w = synth.WORKLOADS["differentiated"]
+    cells = synth.make_cells(w.grid)
+    grid = M.Grid(cells, COSMO)
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, steps_per_cell=w.steps_per_cell,
+                       adaptive=w.adaptive, checkpoint_every=32)
+    fwd = _fwd(M, grid, cfg)
+    res = M.adjoint(grid, cfg, fwd, dL_dalpha=2 * fwd["alpha"], cells=True, jacobian=True)
+    torch.cuda.synchronize()
+    st = _np(res["ray_status"])
+    assert (st == 0).all()
+    idx = np.sort(np.random.default_rng(2026).choice(w.n_rays, 48, replace=False))
+    jac = _np(res["jac"]).astype(np.float64)[idx]
+    dz = _np(res["dz_dtheta"]).astype(np.float64)[idx]
+    dirs = O.pix2vec_nest(w.nside, np.asarray(w.pix_first)[0] + idx)
+    p = O.params(w.obs[0], z_src=float(np.atleast_1d(w.z_src)[0]), steps_per_cell=w.steps_per_cell,
+                 adaptive=w.adaptive)
+    A, dzo, rec = O.jacobian_cs(lambda d, t: O.cast_cs(O.Field.grid(cells), O.cosmo(*COSMO), p, d, dtheta=t), dirs)
+    dA = np.abs(jac - A).reshape(-1, 4).max(1)
+    rz = np.abs(dz - dzo).max(1) / np.abs(dzo).max()
+    _print(f"full-size differentiated: max |dA| {dA.max():.2e}, median {np.median(dA):.2e}; "
+           f"max rel dz/dtheta {rz.max():.2e}")
+    assert dA.max() < 5e-6 and np.median(dA) < 2e-7
+    assert rz.max() < 1e-5

@@ -243,3 +243,27 @@ def test_amr_deep_five_levels(M):
     _print(compare(g, o, max_flip_frac=0.02, flip_tol_arcsec=1.0))
     coarse_only = 1322.038 / (500.0 / 64) * 4
     assert g["n_steps"].max() > 1.2 * coarse_only        # some rays cross the refined haloes
+
+
+def test_batched_full_size_sampled(M):
+    """The batched benchmark configuration itself: 64 observers, z_src in
+    [0.1, 2], one NESTED base pixel at nside 128 each (1,048,576 rays of
+    uneven length) in the autotuned launch the benchmark times and in the
+    persistent schedule; 256 seeded random rays recomputed by the oracle."""
+    w = synth.WORKLOADS["batched"]
+    cells = synth.make_cells(w.grid)
+    grid = M.Grid(cells, COSMO)
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, steps_per_cell=w.steps_per_cell,
+                       adaptive=w.adaptive, schedule=1)
+    tuned, _ = M.autotune(grid, cfg, sample_div=8)
+    _print("batched: tuned schedule", tuned.schedule, "waves/CU", tuned.waves_per_cu, "batch", tuned.batch)
+    g = run_gpu(grid, tuned)
+    assert np.all(g["status"] == M.MPATH_RAY_REACHED)
+    p = run_gpu(grid, M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count,
+                                   steps_per_cell=w.steps_per_cell, adaptive=w.adaptive, schedule=2))
+    for k in ("beta", "z5", "n_steps", "hash"):
+        assert np.array_equal(p[k], g[k]), k
+    idx = np.sort(np.random.default_rng(2025).choice(w.n_rays, 256, replace=False))
+    o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), w.obs, w.z_src, w.nside, w.pix_first, w.pix_count,
+                   w.steps_per_cell, w.adaptive, ray_index=idx)
+    _print(compare(g, o, idx=idx))
