@@ -213,19 +213,6 @@ struct RayRun {
             // at the observer: chi = 0, rising at |k| = K |n + d|
             p_cur = 0.0;
             dp_cur = 1.0 + (geo.n[0] * y.d[0] + geo.n[1] * y.d[1] + geo.n[2] * y.d[2]);
-        } else if constexpr (SURF == MPATH_SURFACE_Z) {
-            double v[3];
-            grid_coords(g, geo, y.eta, y.dx, v);
-            float phi, G[3];
-            int leafl, l;
-            F.eval(g, v, phi, G, leafl, l);
-            HubbleCubic Hc;
-            Hc.init(a.cosmo, y.eta);
-            double mG = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) mG += (geo.n[i] + (double)y.d[i]) * (double)G[i];
-            p_cur = 0.0;
-            dp_cur = Hc(a.cosmo, y.eta) - mG;
         }
         for (;;) {
             if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return; }
@@ -253,28 +240,45 @@ struct RayRun {
             if (rk4_step<FC>(g, a.cosmo, F, geo, y, dl, yn, hash)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
             if (!finite_state(yn)) { status = MPATH_RAY_NONFINITE; return; }
             if constexpr (SURF != MPATH_SURFACE_LAMBDA) {
-                double pn, dpn;
-                if (!stop_param<SURF>(a, yn, pn, dpn)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
-                if (pn >= p_s) {
-                    double dlx = (p_s - p_cur) / dp_cur;
-                    for (int it = 0; it < 2; ++it) {
-                        GeoState yt;
-                        double pt, dpt;
-                        if (rk4_step<FC>(g, a.cosmo, F, geo, y, dlx, yt, hash) || !stop_param<SURF>(a, yt, pt, dpt)) {
-                            status = MPATH_RAY_LEFT_DOMAIN;
-                            return;
-                        }
-                        dlx = dlx - (pt - p_s) / dpt;
+                bool check = true;
+                if constexpr (SURF == MPATH_SURFACE_Z) {
+                    // interpolation weights are convex, so Phi <= phi_max anywhere (up
+                    // to float32 rounding) and 1 + z5 <= a K (1 + phi_max) / (1 + Phi_o):
+                    // below 1 + z_s (with a relative margin of 1e-9) the surface is not
+                    // reached and the field need not be evaluated
+                    const double bound = scale_factor(a.cosmo, yn.eta) * yn.K * (1.0 + (double)g.phi_max) /
+                                         (1.0 + (double)phi_o);
+                    check = bound >= exp(p_s) * (1.0 - 1e-9);
+                }
+                double pn = 0.0, dpn = 0.0;
+                if (check && !stop_param<SURF>(a, yn, pn, dpn)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+                if (check && pn >= p_s) {
+                    if constexpr (SURF == MPATH_SURFACE_Z) {
+                        // the parameter and its rate at the step start (the previous
+                        // step's end), skipped while far from the surface
+                        if (!stop_param<SURF>(a, y, p_cur, dp_cur)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
                     }
-                    if (rk4_step<FC>(g, a.cosmo, F, geo, y, dlx, yn, hash)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+                    // two Newton passes, then the step
+                    double dlx = (p_s - p_cur) / dp_cur;
+#pragma unroll 1
+                    for (int it = 0; it < 3; ++it) {
+                        if (rk4_step<FC>(g, a.cosmo, F, geo, y, dlx, yn, hash)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+                        if (it < 2) {
+                            double pt, dpt;
+                            if (!stop_param<SURF>(a, yn, pt, dpt)) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+                            dlx = dlx - (pt - p_s) / dpt;
+                        }
+                    }
                     y = yn;
                     lam += dlx;
                     ++n_steps;
                     status = finite_state(y) ? MPATH_RAY_REACHED : MPATH_RAY_NONFINITE;
                     return;
                 }
-                p_cur = pn;
-                dp_cur = dpn;
+                if constexpr (SURF == MPATH_SURFACE_CHI) {
+                    p_cur = pn;
+                    dp_cur = dpn;
+                }
             }
             y = yn;
             lam += dl;

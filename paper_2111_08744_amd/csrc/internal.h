@@ -49,6 +49,7 @@ struct GridDev {
     double inv_h0;
     double inv_hf;            // 2^(max_level + 1) / h0: fine-grid coordinates
     double eta0;              // conformal time at the observers (a = 1)
+    float phi_max;            // largest cell value of phi (+inf when unknown)
     int32_t n0;               // coarse cells per side (power of two)
     int32_t max_level;
     int32_t periodic;

@@ -157,6 +157,7 @@ struct mpath_grid {
     int32_t* dual_ids = nullptr;
     double2* table = nullptr;
     double2* atable = nullptr;    // (a, da/deta) on the nodes of table
+    float phi_max = INFINITY;     // largest payload phi (+inf after set_values)
     float* tpay = nullptr;        // dPhi/deta per cell (time-dependent potential), else null
     float4* tdual = nullptr;      // its 8 trilinear coefficients per stencil base
     int32_t level_start[kMaxLevels + 1] = {0};
@@ -205,6 +206,7 @@ GridDev make_griddev(const mpath_grid* g)
     d.inv_h0 = g->n0 / g->box;
     d.inv_hf = std::ldexp(d.inv_h0, g->max_level + 1);
     d.eta0 = g->eta0;
+    d.phi_max = g->phi_max;
     d.n0 = g->n0;
     d.max_level = g->max_level;
     d.periodic = g->periodic;
@@ -360,6 +362,8 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     }
     // ---- background table of a'/a ----
     mpath_grid* G = new mpath_grid();
+    G->phi_max = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) G->phi_max = std::max(G->phi_max, payload[i].x);
     G->bg.init(cosmo->omega_m, cosmo->omega_l);
     G->eta0 = G->bg.is_static ? 0.0 : G->bg.eta0();
     std::vector<double2> table(kTableN, make_double2(0.0, 0.0));
@@ -478,6 +482,7 @@ int mpath_grid_get_info(const mpath_grid* g, mpath_grid_info* info)
 int mpath_grid_set_values(mpath_grid* g, const float* values, void* stream)
 {
     if (!g || !values) return fail(MPATH_ERR_INVALID_ARG, "NULL argument");
+    g->phi_max = INFINITY;   // the new values stay on the device: no bound
     hipError_t e = launch_permute_values(g->payload, g->perm, (const float4*)values, g->n_cells,
                                          (hipStream_t)stream);
     if (!e) e = launch_build_dual(make_griddev(g), g->cellpos, g->dual, g->n_cells, (hipStream_t)stream);
