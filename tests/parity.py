@@ -1,7 +1,7 @@
 """Helpers shared by the GPU parity tests: run the same seeded workload through
 the HIP library (via its C ABI) and through the FP64 oracle, and compare.
 
-Tolerances (spec targets for this method):
+Tolerances (the parity bar of the method's observables):
   * deflection: angular separation of the end-point directions r_s - x_obs,
     GPU vs oracle, <= 1e-3 arcsec;
   * observed redshift: |z5_gpu - z5_oracle| / z5_oracle <= 1e-7.
