@@ -339,6 +339,24 @@ def measure_variants(M, torch, dev):
             **res}
 
 
+def measure_ray_order(M, torch, dev, grid, w):
+    """Why rays are ordered by NESTED pixel: the AMR workload's 786,432 rays
+    cast along the same directions, once in NESTED order (neighbouring rays
+    in a wave share stencil lines) and once randomly permuted (seed 5)."""
+    dirs = M.healpix_dirs(w.nside, int(w.pix_first[0]), int(w.pix_count[0]), device=dev)
+    perm = torch.from_numpy(np.random.default_rng(5).permutation(dirs.shape[0])).to(dev)
+    res = {}
+    for label, td in (("nested", dirs), ("shuffled", dirs[perm].contiguous())):
+        cfg = M.CastConfig(w.obs, w.z_src, w.nside, pix_count=[td.shape[0]], dirs=td, steps_per_cell=w.steps_per_cell,
+                           adaptive=w.adaptive, schedule=1)
+        out = M.alloc_outputs(td.shape[0], dev)
+        res[label] = {"ms": _time_ms(torch, lambda: M.cast(grid, cfg, out, out.get("_ws")))}
+    res["shuffled_over_nested"] = res["shuffled"]["ms"] / res["nested"]["ms"]
+    log(f"[bench] ray order (AMR cast): NESTED {res['nested']['ms']:.1f} ms, shuffled {res['shuffled']['ms']:.1f} ms "
+        f"({res['shuffled_over_nested']:.2f}x)")
+    return {"workload": "the AMR workload's rays as caller directions, NESTED order vs a random permutation", **res}
+
+
 def measure_orders(M, torch, dev):
     """The three interpolation orders (Sect. 2.2) on the same rays: 196,608
     rays (nside 128) to z = 1 on the uniform 64^3 grid and 49,152 rays
@@ -496,9 +514,10 @@ def main():
             "algorithmic_bytes_per_ray_step": ALGO_BYTES_PER_RAY_STEP.get(w.name),
         }
     if not args.no_secondary:
-        sec = {"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev),
+        sec = {"ray_order": measure_ray_order(M, torch, dev, grid, w)} if w.name == "amr" else {}
+        sec.update({"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev),
                "lensing": measure_lensing(M, torch, dev), "finder": measure_finder(M, torch, dev),
-               "orders": measure_orders(M, torch, dev), "variants": measure_variants(M, torch, dev)}
+               "orders": measure_orders(M, torch, dev), "variants": measure_variants(M, torch, dev)})
         res["secondary"] = sec
         res["adjoint_forward_ratio"] = sec["adjoint"]["adjoint_forward_ratio"]
     if not args.no_cpu_baseline:

@@ -133,6 +133,15 @@ int mpath_grid_build(const mpath_grid_desc* desc, const mpath_cosmo* cosmo, void
 int mpath_double_layer(int64_t n, const double* phi1, const double* phi2, const double* a1, const double* a2,
                        const mpath_cosmo* cosmo, double* dphi_deta);
 
+/* Pixel-centre directions of the NESTED HEALPix pixels pix_first ..
+ * pix_first + count - 1 at resolution nside (Sect. 2.4: the initial
+ * directions of the maps), the unit vectors the casts start along when
+ * mpath_cast_desc.dirs is NULL.  dirs: DEVICE double[count][3], written
+ * asynchronously on the stream.  Errors: INVALID_ARG (nside outside
+ * [1, 8192], a range outside the 12 nside^2 pixels, dirs NULL with
+ * count > 0), DEVICE. */
+int mpath_healpix_dirs(int32_t nside, int64_t pix_first, int64_t count, double* dirs, void* stream);
+
 /* Release the handle (not dev_ws, which the caller owns). */
 int mpath_grid_free(mpath_grid* grid);
 

@@ -539,3 +539,15 @@ def double_layer(phi1, phi2, a1, a2, cosmo=(0.3, 0.7, 0.7)):
     _abi.check(_abi.lib().mpath_double_layer(n, phi1.ctypes.data, phi2.ctypes.data, a1.ctypes.data, a2.ctypes.data,
                                              C.byref(cz), out.ctypes.data), "mpath_double_layer")
     return out
+
+
+def healpix_dirs(nside: int, pix_first: int = 0, count=None, device="cuda"):
+    """mpath_healpix_dirs: NESTED pixel-centre directions [count, 3] (float64
+    CUDA tensor) of pixels pix_first .. pix_first + count - 1."""
+    torch = _torch()
+    count = 12 * nside * nside - pix_first if count is None else int(count)
+    out = torch.empty((count, 3), dtype=torch.float64, device=device)
+    with torch.cuda.device(out.device):
+        _abi.check(_abi.lib().mpath_healpix_dirs(int(nside), int(pix_first), count, _ptr(out) if count else None,
+                                                 _stream_ptr(out.device)), "mpath_healpix_dirs")
+    return out

@@ -123,6 +123,7 @@ def lib():
         L.mpath_born_beam.argtypes = [vp, P(mpath_cast_desc), vp, vp, vp, sz, vp]
         L.mpath_gather_probe.argtypes = [vp, sz, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_uint32, vp, vp]
         L.mpath_double_layer.argtypes = [C.c_int64, vp, vp, vp, vp, P(mpath_cosmo), vp]
+        L.mpath_healpix_dirs.argtypes = [C.c_int32, C.c_int64, C.c_int64, vp, vp]
         L.mpath_status_string.restype = C.c_char_p
         L.mpath_status_string.argtypes = [C.c_int]
         L.mpath_last_error.restype = C.c_char_p
@@ -133,7 +134,7 @@ def lib():
                      "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune", "mpath_gather_probe",
                      "mpath_lensing_maps", "mpath_finite_beam_workspace_bytes", "mpath_finite_beam",
                      "mpath_infinitesimal_beam", "mpath_find_geodesics_workspace_bytes", "mpath_find_geodesics",
-                     "mpath_born_beam", "mpath_double_layer"):
+                     "mpath_born_beam", "mpath_double_layer", "mpath_healpix_dirs"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

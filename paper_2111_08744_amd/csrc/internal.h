@@ -175,6 +175,7 @@ struct BeamObs {
     int64_t count;       // reference rays of the observer
 };
 hipError_t launch_lensing_maps(const float* A, int64_t n, float* out, hipStream_t s);
+hipError_t launch_healpix_dirs(int nside, int64_t pix_first, int64_t count, double* dirs, hipStream_t s);
 hipError_t launch_beam_dirs(const BeamObs* obs, int n_obs, int nside, const double* user_dirs, double tan_eps,
                             int64_t n_rays, double* dirs5, hipStream_t s);
 hipError_t launch_finite_beam(const BeamObs* obs, int n_obs, const RayEnd* ends, const double* dirs5,

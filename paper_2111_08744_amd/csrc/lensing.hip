@@ -60,6 +60,19 @@ __device__ inline int beam_observer(const BeamObs* obs, int n_obs, int64_t r)
 // n -+ tan(eps) e2 normalised (rays A, B, C, D).  Observer j's block of 5 c_j
 // rays holds the reference rays, then the A, B, C and D rays, each in the
 // order of the reference rays.
+// Pixel centres of NESTED pixels pix_first .. pix_first + count - 1.
+__global__ __launch_bounds__(256) void healpix_dirs_kernel(int nside, int64_t pix_first, int64_t count,
+                                                           double* __restrict__ dirs)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double v[3];
+    healpix_nest_dir(nside, pix_first + i, v);
+    dirs[3 * i] = v[0];
+    dirs[3 * i + 1] = v[1];
+    dirs[3 * i + 2] = v[2];
+}
+
 __global__ __launch_bounds__(256) void beam_dirs_kernel(const BeamObs* __restrict__ obs, int n_obs, int nside,
                                                         const double* __restrict__ user_dirs, double tan_eps,
                                                         int64_t n_rays, double* __restrict__ dirs5)
@@ -154,6 +167,13 @@ hipError_t launch_lensing_maps(const float* A, int64_t n, float* out, hipStream_
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(lensing_maps_kernel, blocks_for(n), dim3(256), 0, s, A, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_healpix_dirs(int nside, int64_t pix_first, int64_t count, double* dirs, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(healpix_dirs_kernel, blocks_for(count), dim3(256), 0, s, nside, pix_first, count, dirs);
     return hipGetLastError();
 }
 

@@ -457,6 +457,16 @@ int mpath_double_layer(int64_t n, const double* phi1, const double* phi2, const 
     return MPATH_OK;
 }
 
+int mpath_healpix_dirs(int32_t nside, int64_t pix_first, int64_t count, double* dirs, void* stream)
+{
+    if (nside < 1 || nside > 8192) return fail(MPATH_ERR_INVALID_ARG, "nside must be in [1, 8192]");
+    if (pix_first < 0 || count < 0 || pix_first + count > 12ll * nside * nside)
+        return fail(MPATH_ERR_INVALID_ARG, "pixel range outside the sky");
+    if (count > 0 && !dirs) return fail(MPATH_ERR_INVALID_ARG, "dirs is NULL");
+    const hipError_t e = launch_healpix_dirs(nside, pix_first, count, dirs, (hipStream_t)stream);
+    return e ? hip_fail(e, "healpix directions launch") : MPATH_OK;
+}
+
 int mpath_grid_free(mpath_grid* grid)
 {
     delete grid;

@@ -165,3 +165,11 @@ def test_born_beam_rejects_missing_grid(abi):
     from paper_2111_08744_amd import CastConfig
     d = CastConfig([0, 0, 0], 0.5, 4).desc()
     assert L.mpath_born_beam(None, C.byref(d), None, None, None, 0, None) == abi.MPATH_ERR_INVALID_ARG
+
+
+def test_healpix_dirs_argument_checks(abi):
+    """Rejected before any device work: nside outside [1, 8192], a pixel
+    range outside the sky, no output array."""
+    L = abi.lib()
+    for nside, first, count, ptr in ((0, 0, 1, 16), (8193, 0, 1, 16), (2, -1, 1, 16), (2, 40, 9, 16), (2, 0, 4, None)):
+        assert L.mpath_healpix_dirs(nside, first, count, ptr, None) == abi.MPATH_ERR_INVALID_ARG, (nside, first, count)
