@@ -669,7 +669,10 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
     uint32_t h = hash;
     HubbleCubic Hc;
     Hc.init(cz, y.eta);
-    // one stage; true when no complete stencil exists at its position
+    // one stage; true when no complete stencil exists at its position (the
+    // remaining stages then run on meaningless values, every lookup staying
+    // in bounds, and the step is rejected after the loop, so that the loop
+    // has a single exit)
     auto stage = [&](const int st) -> bool {
         #pragma clang fp contract(off)
         GeoState yi;
@@ -693,9 +696,9 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
         }
         double u[3];
         grid_coords(g, r, yi.eta, yi.dx, u);
-        float phi, G[3];
-        int leafl, l;
-        if (F.eval(g, u, phi, G, leafl, l)) return true;
+        float phi = 0.0f, G[3] = {0.0f, 0.0f, 0.0f};
+        int leafl, l = 0;
+        const bool bad = F.eval(g, u, phi, G, leafl, l) != 0;
         h = fnv(h, (uint32_t)l);
         if (record) rec.stage(st, yi, F, G);
         const double H = Hc(cz, yi.eta);
@@ -733,11 +736,12 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
             acc_dx[i] = fmaf(wf, f_dx[i], acc_dx[i]);
             acc_P[i] = fmaf(wf, f_P[i], acc_P[i]);
         }
-        return false;
+        return bad;
     };
+    bool failed = false;
 #pragma unroll 1
-    for (int st = 0; st < 4; ++st)
-        if (stage(st)) return 1;
+    for (int st = 0; st < 4; ++st) failed |= stage(st);
+    if (failed) return 1;
     const double h6 = dl / 6.0;
     out.eta = fma(h6, acc_eta, y.eta);
     out.K = fma(h6, acc_K, y.K);
