@@ -248,7 +248,11 @@ struct FieldCache {
     // for every (f, k) (no bank conflicts) at compile-time offsets
     __device__ __forceinline__ void bind(float* lds) { c = lds; }
 
-    __device__ __forceinline__ void reset() { keyL = -1; }
+    __device__ __forceinline__ void reset()
+    {
+        keyL = -1;
+        lvl = 0;
+    }
 
     // Leaf level at the point with unwrapped coordinates I at level
     // max_level + 1; -1 outside a non-periodic box.  The cached leaf is the
@@ -354,11 +358,12 @@ struct FieldCache {
 #pragma unroll
         for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
         int L;
+        bool bad = false;
         if (AMR && keyL >= 0 && (I[0] >> (Lm - keyL)) == key[0] && (I[1] >> (Lm - keyL)) == key[1] &&
             (I[2] >> (Lm - keyL)) == key[2]) {
             // same half-cell of the same leaf as the cached stencil
             L = keyL;
-        } else {
+        } else if constexpr (AMR) {
             L = leaf(g, I);
             if (L < 0) {
                 leaf_level = L;
@@ -368,6 +373,13 @@ struct FieldCache {
                 leaf_level = L;
                 return 1;
             }
+        } else {
+            // uniform grid: a single exit (measured faster there, while the
+            // refined kernel keeps its early returns, which spill less); the
+            // cached coefficients are evaluated all the same without a
+            // stencil and the values replaced by zeros
+            L = leaf(g, I);
+            bad = L < 0 || !stencil(g, L, I);
         }
         leaf_level = L;
         stencil_level = lvl;
@@ -388,16 +400,17 @@ struct FieldCache {
             const float k4 = k[4 * cstride], k5 = k[5 * cstride], k6 = k[6 * cstride], k7 = k[7 * cstride];
             f[q] = trilinear_eval(k0, k1, k2, k3, k4, k5, k6, k7, tx, ty, tz);
         }
-        phi = f[0];
-        G[0] = f[1];
-        G[1] = f[2];
-        G[2] = f[3];
+        phi = bad ? 0.0f : f[0];
+        G[0] = bad ? 0.0f : f[1];
+        G[1] = bad ? 0.0f : f[2];
+        G[2] = bad ? 0.0f : f[3];
         if constexpr (TIME) {
             const float* k = c + 32 * cstride;
             tv = trilinear_eval(k[0], k[cstride], k[2 * cstride], k[3 * cstride], k[4 * cstride], k[5 * cstride],
                                 k[6 * cstride], k[7 * cstride], tx, ty, tz);
+            if (bad) tv = 0.0f;
         }
-        return 0;
+        return bad ? 1 : 0;
     }
 };
 
