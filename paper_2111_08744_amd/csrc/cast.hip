@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kBlock, kMinWavesPerSimd) void cast_persistent_kern
 // cache so that the integration's own cache is left in place.
 template <bool AMR>
 struct InfBeam {
-    FieldCache<AMR> P;
+    FieldCache<AMR, false, false> P;
     double chi_p, Tp[3];         // previous sample (T11, T12, T22)
     double J1[3], J2[3];         // trapezoid sums of chi T and chi^2 T
     int n;

@@ -226,8 +226,10 @@ __device__ __forceinline__ float trilinear_eval(float c0, float c1, float c2, fl
 //
 // TIME: the grid also carries dPhi/deta (Sect. 2.2, from a double-layer
 // light cone); its 8 coefficients follow the 32 of (phi, grad) in LDS and
-// eval leaves the interpolated value in tv.
-template <bool AMR, bool TIME = false>
+// eval leaves the interpolated value in tv.  ONE_EXIT: eval without early
+// returns (measured faster inside the RK4 stage loop on the uniform grid;
+// the refined grid and the field probes of the beams keep the returns).
+template <bool AMR, bool TIME = false, bool ONE_EXIT = !AMR>
 struct FieldCache {
     static constexpr bool kTime = TIME;
     int leafId;         // id of the leaf cell containing the cached half-cell
@@ -363,7 +365,7 @@ struct FieldCache {
             (I[2] >> (Lm - keyL)) == key[2]) {
             // same half-cell of the same leaf as the cached stencil
             L = keyL;
-        } else if constexpr (AMR) {
+        } else if constexpr (!ONE_EXIT) {
             L = leaf(g, I);
             if (L < 0) {
                 leaf_level = L;
@@ -374,10 +376,8 @@ struct FieldCache {
                 return 1;
             }
         } else {
-            // uniform grid: a single exit (measured faster there, while the
-            // refined kernel keeps its early returns, which spill less); the
-            // cached coefficients are evaluated all the same without a
-            // stencil and the values replaced by zeros
+            // a single exit: the cached coefficients are evaluated all the
+            // same without a stencil and the values replaced by zeros
             L = leaf(g, I);
             bad = L < 0 || !stencil(g, L, I);
         }
