@@ -20,11 +20,14 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Optional
 
 import numpy as np
 
 __all__ = [
+    "sphere_and_uniform_centres", "LARGE_OBS",
     "Cells", "gaussian_potential", "central_gradient", "uniform_cells",
     "fourier_field", "random_amr_cells", "amr_halo_cells", "Workload",
     "WORKLOADS", "make_cells", "batched_cones", "second_layer", "ISW_LAYER_A",
@@ -198,20 +201,50 @@ def random_amr_cells(n0: int, box: float, max_level: int, seed: int,
 # AMR grid with haloes: Gaussian background + truncated NFW-like haloes,
 # refined where a lognormal-plus-halo density exceeds 8x the mean
 # ---------------------------------------------------------------------------
-def _cic_sample_periodic(grid: np.ndarray, x: np.ndarray, box: float) -> np.ndarray:
+def _workers() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _in_chunks(fn, n: int, chunk: int = 1 << 22) -> None:
+    """fn(a, b) over consecutive ranges of [0, n) on a thread pool (numpy
+    releases the GIL in its array operations; every range writes only its own
+    slice of the outputs, so the result does not depend on the pool)."""
+    spans = [(a, min(n, a + chunk)) for a in range(0, n, chunk)]
+    if len(spans) <= 1:
+        for a, b in spans:
+            fn(a, b)
+        return
+    with ThreadPoolExecutor(_workers()) as ex:
+        for _ in ex.map(lambda ab: fn(*ab), spans):
+            pass
+
+
+def _cic_sample_periodic(grid: np.ndarray, x: np.ndarray, box: float, chunk: int = 1 << 21) -> np.ndarray:
     """Trilinear (cloud-in-cell) sample of a periodic cell-centred grid.
-    Used only to give refined cells a background value (input synthesis)."""
+    Used only to give refined cells a background value (input synthesis).
+    Points are taken in chunks; corner weights are the products
+    (w_x w_y) w_z and corners are summed in octant order."""
     n = grid.shape[0]
-    u = x / (box / n) - 0.5
-    b = np.floor(u).astype(np.int64)
-    t = u - b
+    flat = grid.reshape((n ** 3,) + grid.shape[3:])
     out = np.zeros(x.shape[:1] + grid.shape[3:], dtype=np.float64)
-    for o in range(8):
-        o3 = np.array([o & 1, (o >> 1) & 1, (o >> 2) & 1])
-        idx = (b + o3) % n
-        w = np.prod(np.where(o3 == 1, t, 1.0 - t), axis=1)
-        v = grid[idx[:, 0], idx[:, 1], idx[:, 2]]
-        out += (w[:, None] * v) if v.ndim > 1 else w * v
+
+    def run(s0, s1):
+        u = x[s0:s1] / (box / n) - 0.5
+        b = np.floor(u).astype(np.int64)
+        t = u - b
+        lo = [(b[:, d] % n, 1.0 - t[:, d]) for d in range(3)]
+        hi = [((b[:, d] + 1) % n, t[:, d]) for d in range(3)]
+        acc = out[s0:s1]
+        for o in range(8):
+            (i, wi), (j, wj), (k, wk) = [(hi if (o >> d) & 1 else lo)[d] for d in range(3)]
+            w = wi * wj * wk
+            v = flat[(i * n + j) * n + k]
+            acc += (w[:, None] * v) if v.ndim > 1 else w * v
+    _in_chunks(run, len(x), chunk)
     return out
 
 
@@ -235,46 +268,56 @@ class HaloSet:
         # (Poisson: Phi ~ rho rs^2); dens_norm tunes the refined volume
         self.d0 = dens_norm * self.p0 / self.rs ** 2 * 1e5
 
-    def _iter_near(self, x, lo_cell=None):
-        """Yield (halo index, indices of x within the halo truncation radius,
+    def _iter_near(self, x, R):
+        """Yield (halo index, indices of x within radius R[h] of halo h,
         minimum-image separations, distances).  Points are bucketed on a
-        periodic grid of cells no smaller than the largest radius, so each
-        halo only inspects the 27 buckets around it."""
+        periodic grid of cells a quarter of the largest radius wide; each
+        halo inspects the buckets within its own radius (plus one)."""
         box = self.box
-        nb = max(1, int(box // max(self.R.max(), 1e-9)))
+        nb = max(1, int(box // max(0.25 * R.max(), 1e-9)))
         bsz = box / nb
         bidx = np.floor(np.mod(x, box) / bsz).astype(np.int64) % nb
         key = (bidx[:, 0] * nb + bidx[:, 1]) * nb + bidx[:, 2]
+        del bidx
         order = np.argsort(key, kind="stable")
-        skey = key[order]
-        starts = np.searchsorted(skey, np.arange(nb ** 3 + 1))
-        offs = np.array([(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+        starts = np.searchsorted(key[order], np.arange(nb ** 3 + 1))
+        del key
         for h in range(len(self.pos)):
             hb = np.floor(np.mod(self.pos[h], box) / bsz).astype(np.int64) % nb
-            nbk = np.unique(((hb[None, :] + offs) % nb) @ np.array([nb * nb, nb, 1]))
-            cand = np.concatenate([order[starts[b]:starts[b + 1]] for b in nbk])
-            if cand.size == 0:
+            m = int(np.ceil(R[h] / bsz)) + 1
+            r = np.arange(-m, m + 1) if 2 * m + 1 < nb else np.arange(nb)
+            bi, bj, bk = [np.unique((hb[d] + r) % nb) for d in range(3)]
+            nbk = ((bi[:, None, None] * nb + bj[None, :, None]) * nb + bk[None, None, :]).ravel()
+            s0, ln = starts[nbk], starts[nbk + 1] - starts[nbk]
+            tot = int(ln.sum())
+            if tot == 0:
                 continue
+            # the bucket ranges back to back, in bucket order
+            cand = order[np.repeat(s0 - (np.cumsum(ln) - ln), ln) + np.arange(tot)]
             d = x[cand] - self.pos[h]
             d -= box * np.round(d / box)
             r2 = np.einsum("ij,ij->i", d, d)
-            m = r2 < self.R[h] ** 2
+            m = r2 < R[h] ** 2
             if m.any():
                 yield h, cand[m], d[m], np.sqrt(r2[m])
 
     def potential(self, x):
         phi = np.zeros(len(x))
         grad = np.zeros((len(x), 3))
-        for h, sel, d, r in self._iter_near(x, None):
-            rs, R, p0 = self.rs[h], self.R[h], self.p0[h]
-            y = np.maximum(r / rs, 1e-12)
-            f = np.log1p(y) / y
-            fR = np.log1p(R / rs) / (R / rs)
-            phi[sel] += -p0 * (f - fR)
-            # d f/dy = 1/(y(1+y)) - ln(1+y)/y^2 ; dPhi/dr = -p0 f'(y)/rs
-            fp = 1.0 / (y * (1.0 + y)) - np.log1p(y) / y ** 2
-            dphidr = -p0 * fp / rs
-            grad[sel] += (dphidr / np.maximum(r, 1e-12))[:, None] * d
+
+        def run(a, b):
+            ph, gr = phi[a:b], grad[a:b]
+            for h, sel, d, r in self._iter_near(x[a:b], self.R):
+                rs, R, p0 = self.rs[h], self.R[h], self.p0[h]
+                y = np.maximum(r / rs, 1e-12)
+                f = np.log1p(y) / y
+                fR = np.log1p(R / rs) / (R / rs)
+                ph[sel] += -p0 * (f - fR)
+                # d f/dy = 1/(y(1+y)) - ln(1+y)/y^2 ; dPhi/dr = -p0 f'(y)/rs
+                fp = 1.0 / (y * (1.0 + y)) - np.log1p(y) / y ** 2
+                dphidr = -p0 * fp / rs
+                gr[sel] += (dphidr / np.maximum(r, 1e-12))[:, None] * d
+        _in_chunks(run, len(x))
         return phi, grad
 
     def density(self, x, half=0.0):
@@ -283,30 +326,31 @@ class HaloSet:
         any part of it is dense enough)."""
         rho = np.zeros(len(x))
         Rext = self.R + np.sqrt(3.0) * half
-        saved = self.R
-        self.R = Rext
-        try:
-            for h, sel, d, r in self._iter_near(x):
+
+        def run(a, b):
+            out = rho[a:b]
+            for h, sel, d, r in self._iter_near(x[a:b], Rext):
                 dd = np.maximum(np.abs(d) - half, 0.0)
                 rr = np.sqrt(np.einsum("ij,ij->i", dd, dd))
-                inside = rr < saved[h]
+                inside = rr < self.R[h]
                 y = np.maximum(rr / self.rs[h], 1e-3)
-                rho[sel] += np.where(inside, self.d0[h] / (y * (1.0 + y) ** 2), 0.0)
-        finally:
-            self.R = saved
+                out[sel] += np.where(inside, self.d0[h] / (y * (1.0 + y) ** 2), 0.0)
+        _in_chunks(run, len(x))
         return rho
 
 
 def amr_halo_cells(n0: int, box: float, max_level: int, seed: int, n_halo: int = 200,
                    threshold: float = 8.0, dens_norm: float = 1.0, rms: float = 1e-5,
-                   halo_centres=None, max_cells: int | None = None) -> Cells:
+                   halo_centres=None, max_cells: int | None = None, log=None) -> Cells:
     """AMR tree: Gaussian potential on the coarse grid (P(k) ~ k^-3, rms `rms`),
     plus `n_halo` truncated NFW-like haloes.  Density 1 + delta =
     exp(g - 1/2) (g: the unit Gaussian paired with Phi) + halo densities; a
     cell is refined when the density at its centre exceeds `threshold`,
     at every level up to max_level.  Refined cells take the background
     potential by trilinear sampling of the coarse grid plus the exact halo
-    potential at their own centre."""
+    potential at their own centre.  log: optional callable taking a progress
+    message (very large trees take minutes)."""
+    say = log if log is not None else (lambda msg: None)
     rng_seed = seed
     phi0 = gaussian_potential(n0, box, rng_seed, rms=rms)
     grad0 = central_gradient(phi0, box)
@@ -328,6 +372,7 @@ def amr_halo_cells(n0: int, box: float, max_level: int, seed: int, n_halo: int =
         if not refine.any():
             break
         kids = _children(cur[refine])
+        say(f"level {lev}: {len(cur)} cells, {int(refine.sum())} refined")
         if max_cells is not None and sum(len(a) for a in lev_ijk) + len(kids) > max_cells:
             break
         lev_ijk.append(kids)
@@ -342,9 +387,13 @@ def amr_halo_cells(n0: int, box: float, max_level: int, seed: int, n_halo: int =
     if len(level) > n_coarse:
         xr = _cell_centres(level[n_coarse:], ijk[n_coarse:], box, n0)
         phi[n_coarse:] = _cic_sample_periodic(phi0, xr, box)
+        say("background potential sampled on the refined cells")
         grad[n_coarse:] = _cic_sample_periodic(grad0, xr, box)
+        say("background gradient sampled on the refined cells")
+        del xr
     xall = _cell_centres(level, ijk, box, n0)
     hp, hg = halos.potential(xall)
+    say("halo potentials added")
     phi += hp
     grad += hg
     return Cells(box=float(box), n0=n0, max_level=len(lev_ijk) - 1, periodic=True,
@@ -388,8 +437,8 @@ def second_layer(phi1: np.ndarray, n: int, box: float, seed: int, a1: float, a2:
     return phi1 * (1.0 + d) + noise * d * g2
 
 
-def make_cells(grid: str) -> Cells:
-    """Build a named grid (deterministic)."""
+def make_cells(grid: str, log=None) -> Cells:
+    """Build a named grid (deterministic); log as in amr_halo_cells."""
     if grid == "gauss64":
         # uniform 64^3 grid, box 500 Mpc/h, P(k) ~ k^-3, rms 1e-5, seed 1
         phi = gaussian_potential(64, 500.0, seed=1)
@@ -415,7 +464,30 @@ def make_cells(grid: str) -> Cells:
     if grid == "amr128":
         # 128^3 coarse, box 500 Mpc/h, 3 levels, 200 haloes, ~1e7 cells
         return amr_halo_cells(128, 500.0, 3, seed=2, n_halo=200, dens_norm=AMR128_DENS_NORM)
+    if grid == "amr512":
+        # 512^3 coarse, box 2000 Mpc/h (coarse cells 3.9 Mpc/h), 5 levels
+        # (finest 0.12 Mpc/h): 950 haloes uniform in a sphere of 400 Mpc/h
+        # around the observer plus 950 uniform in the box; refinement as in
+        # amr_deep (threshold 30, density normalisation 3000): about 4e8 cells
+        cen = sphere_and_uniform_centres(2000.0, LARGE_OBS, 400.0, 950, 950, seed=108)
+        return amr_halo_cells(512, 2000.0, 5, seed=7, n_halo=len(cen), threshold=30.0, dens_norm=3000.0,
+                              halo_centres=cen, log=log)
     raise KeyError(grid)
+
+
+# observer of the 512^3 + 5 level light cone (the box centre)
+LARGE_OBS = (1000.0, 1000.0, 1000.0)
+
+
+def sphere_and_uniform_centres(box: float, centre, radius: float, n_in: int, n_out: int, seed: int) -> np.ndarray:
+    """n_in points uniform in the ball of `radius` around `centre` (periodic)
+    followed by n_out points uniform in the box."""
+    rng = _rng(seed)
+    u = rng.standard_normal((n_in, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    r = radius * rng.uniform(0.0, 1.0, n_in) ** (1.0 / 3.0)
+    inner = np.asarray(centre, np.float64) + u * r[:, None]
+    return np.concatenate([inner, rng.uniform(0.0, box, (n_out, 3))]) % box
 
 
 # density normalisation of the 128^3 AMR grid's haloes, chosen so the tree holds
@@ -452,6 +524,9 @@ def _wl(name):
     if name == "batched":        # 64 cones of 16384 rays on the 64^3 grid
         obs, z, first, count = batched_cones(500.0, 64, 128, seed=3)
         return Workload(name, "gauss64", 128, obs, z, first, count, 10, False)
+    if name == "large":          # 512^3 + 5 levels, full sky at nside 2048 (50,331,648 rays) to z = 2
+        f, n = _full_sky(2048)
+        return Workload(name, "amr512", 2048, np.array([LARGE_OBS]), np.array([2.0]), f, n, 4, True)
     if name == "differentiated":  # 2^20 rays to z = 1 on the 64^3 grid
         return Workload(name, "gauss64", 512, c, np.array([1.0]),
                         np.array([0], np.int64), np.array([1 << 20], np.int64), 10, False)
