@@ -178,7 +178,10 @@ or_field* or_field_grid(double box, int n0, int max_level, int periodic, int64_t
     f->hvals = (int64_t*)malloc(sizeof(int64_t) * cap);
     memset(f->hkeys, 0xff, sizeof(uint64_t) * cap);
     char msg[256];
+    const int progress = n_cells >= ((int64_t)1 << 26);   /* very large grids report their progress */
     for (int64_t c = 0; c < n_cells; ++c) {
+        if (progress && (c & (((int64_t)1 << 25) - 1)) == 0)
+            fprintf(stderr, "oracle grid: indexed %lld of %lld cells\n", (long long)c, (long long)n_cells);
         const int l = level[c];
         const int64_t m = (int64_t)n0 << l;
         const int64_t i = ijk[3 * c], j = ijk[3 * c + 1], k = ijk[3 * c + 2];
@@ -196,14 +199,21 @@ or_field* or_field_grid(double box, int n0, int max_level, int periodic, int64_t
     }
     for (int64_t i = 0; i < nc; ++i)
         if (f->coarse[i] < 0) { set_err(err, errlen, "missing coarse cell"); or_field_free(f); return NULL; }
-    /* full tree: every refined cell's parent exists and has all 8 children */
+    /* full tree: every refined cell's parent exists and has all 8 children.
+     * A family is checked in full once, through its first child (octant 0);
+     * any other child only checks that the first child exists. */
     for (int64_t c = 0; c < n_cells; ++c) {
+        if (progress && (c & (((int64_t)1 << 25) - 1)) == 0)
+            fprintf(stderr, "oracle grid: checked %lld of %lld cells\n", (long long)c, (long long)n_cells);
         const int l = level[c];
         if (l == 0) continue;
         const int64_t P[3] = {ijk[3 * c] >> 1, ijk[3 * c + 1] >> 1, ijk[3 * c + 2] >> 1};
         if (find_cell(f, l - 1, P) < 0) { set_err(err, errlen, "orphan cell (parent missing)"); or_field_free(f); return NULL; }
         int64_t b[3] = {2 * P[0], 2 * P[1], 2 * P[2]}, ids[8];
-        if (!stencil_cells(f, l, b, ids)) { set_err(err, errlen, "not a full tree (a parent has 1-7 children)"); or_field_free(f); return NULL; }
+        const int first = ijk[3 * c] == b[0] && ijk[3 * c + 1] == b[1] && ijk[3 * c + 2] == b[2];
+        if (first ? !stencil_cells(f, l, b, ids) : find_cell(f, l, b) < 0) {
+            set_err(err, errlen, "not a full tree (a parent has 1-7 children)"); or_field_free(f); return NULL;
+        }
     }
     return f;
 }

@@ -117,6 +117,18 @@ def test_rejects_non_full_tree(O):
                       cells.ijk[keep], cells.phi[keep], cells.grad[keep])
     with pytest.raises(ValueError):
         O.Field.grid(bad)
+    # a family of leaves missing any one of its 8 cells (the first one included)
+    deep = np.nonzero(cells.level == 2)[0]
+    par = cells.ijk[deep] >> 1
+    fam = deep[np.all(par == par[0], axis=1)]
+    assert len(fam) == 8
+    for c in fam:
+        keep = np.ones(cells.n_cells, bool)
+        keep[c] = False
+        bad = synth.Cells(cells.box, cells.n0, cells.max_level, cells.periodic, cells.level[keep],
+                          cells.ijk[keep], cells.phi[keep], cells.grad[keep])
+        with pytest.raises(ValueError, match="full tree"):
+            O.Field.grid(bad)
     # and a missing coarse cell
     keep = np.ones(cells.n_cells, bool)
     keep[0] = False
