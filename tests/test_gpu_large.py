@@ -1,0 +1,156 @@
+"""The largest configuration at full size: 512^3 coarse cells + 5 levels
+(about 4e8 cells, box 2000 Mpc/h), the full sky at nside 2048 (50,331,648
+rays) to z = 2 with 4 steps per leaf cell, in the launch the benchmark times;
+rays sampled at random and the rays with the most steps recomputed by the
+oracle one by one; then the adjoint distortion matrix on a 2^20-ray chunk
+against the oracle's complex-step Jacobian on sampled rays.
+
+Building the tree takes a few minutes of host time and about 60 GB of host
+memory, the oracle's copy about 40 GB more, the device image about 100 GB of
+HBM; the tests run when MPATH_TEST_LARGE=1 is set."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from parity import compare
+
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skipif(os.environ.get("MPATH_TEST_LARGE") != "1",
+                       reason="the 4e8-cell tree needs minutes and ~100 GB of host memory: set MPATH_TEST_LARGE=1"),
+]
+
+COSMO = (0.3, 0.7, 0.7)
+T0 = time.time()
+
+
+def _print(*a):
+    print(f"[{time.time() - T0:6.0f}s]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2111_08744_amd as M
+    return M
+
+
+@pytest.fixture(scope="module")
+def large():
+    w = synth.WORKLOADS["large"]
+    _print("building the 512^3 + 5 level tree")
+    cells = synth.make_cells(w.grid, log=_print)
+    _print("cells", cells.n_cells, "per level", cells.counts_per_level().tolist())
+    return w, cells
+
+
+@pytest.fixture(scope="module")
+def grid(M, large):
+    _, cells = large
+    t = time.time()
+    g = M.Grid(cells, COSMO)
+    _print(f"device grid built in {time.time() - t:.1f} s")
+    return g
+
+
+@pytest.fixture(scope="module")
+def field(large):
+    _, cells = large
+    t = time.time()
+    f = O.Field.grid(cells)
+    _print(f"oracle grid built in {time.time() - t:.1f} s")
+    return f
+
+
+def _host(out):
+    res = {k: v.cpu().numpy() for k, v in out.items() if not k.startswith("_")}
+    res["hash"] = res["hash"].view(np.uint32)
+    return res
+
+
+def test_large_tree_shape(large):
+    _, cells = large
+    counts = cells.counts_per_level()
+    assert cells.max_level == 5 and counts[0] == 512 ** 3 and counts[5] > 0
+    assert 3.2e8 < cells.n_cells < 4.8e8
+
+
+def test_large_full_sky_sampled(M, large, grid, field):
+    import torch
+    w, cells = large
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, steps_per_cell=w.steps_per_cell,
+                       adaptive=w.adaptive)
+    M.cast(grid, cfg)                      # warm-up (allocations)
+    torch.cuda.synchronize()
+    t = time.time()
+    out = M.cast(grid, cfg)
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    g = _host(out)
+    del out
+    steps = int(g["n_steps"].astype(np.int64).sum())
+    _print(f"full sky: {w.n_rays} rays, {steps} ray-steps in {dt * 1e3:.0f} ms: {steps / dt / 1e9:.2f} G ray-steps/s, "
+           f"steps per ray {g['n_steps'].min()}..{g['n_steps'].max()}")
+    assert np.all(g["status"] == M.MPATH_RAY_REACHED)
+    coarse_only = 3625.90 / (2000.0 / 512) * 4
+    assert steps / w.n_rays > coarse_only
+    rng = np.random.default_rng(2026)
+    most = np.argsort(g["n_steps"])[-32:]                 # rays through the deepest refinement
+    idx = np.unique(np.concatenate([rng.choice(w.n_rays, 256, replace=False), most]))
+    t = time.time()
+    o = _oracle(field, w, idx)
+    _print(f"oracle: {len(idx)} rays in {time.time() - t:.0f} s; most steps {g['n_steps'][most].min()}.."
+           f"{g['n_steps'][most].max()}")
+    _print(compare(g, o, idx=idx, max_flip_frac=0.02, flip_tol_arcsec=1.0))
+
+
+def _oracle(field, w, idx, max_steps=1 << 40):
+    dirs = O.pix2vec_nest(w.nside, w.pix_first[0] + idx)
+    p = O.params(w.obs[0], z_src=float(w.z_src[0]), steps_per_cell=w.steps_per_cell, adaptive=w.adaptive,
+                 max_steps=max_steps)
+    return O.cast(field, O.cosmo(*COSMO), p, dirs)
+
+
+def test_large_adjoint_jacobian_sampled(M, large, grid, field):
+    """The distortion matrix by the reverse sweep (checkpoint every 32 steps)
+    on the first 2^20 NESTED pixels, at most 32768 steps per ray (the
+    checkpoints take 43 GB); 24 rays (the 12 with the most steps and 12 at
+    random) against the oracle's complex-step Jacobian."""
+    import torch
+    w, cells = large
+    n = 1 << 20
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, [0], [n], steps_per_cell=w.steps_per_cell, adaptive=w.adaptive,
+                       checkpoint_every=32, max_steps=32768)
+    torch.cuda.synchronize()
+    t = time.time()
+    fwd = M.cast(grid, cfg)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    res = M.adjoint(grid, cfg, fwd, jacobian=True)
+    torch.cuda.synchronize()
+    t2 = time.time()
+    nst = fwd["n_steps"].cpu().numpy()
+    st = res["ray_status"].cpu().numpy()
+    jac = res["jac"].cpu().numpy().astype(np.float64)
+    _print(f"adjoint chunk: {n} rays, {int(nst.astype(np.int64).sum())} ray-steps; checkpointed forward "
+           f"{(t1 - t) * 1e3:.0f} ms, reverse sweep {(t2 - t1) * 1e3:.0f} ms; not differentiated {(st != 0).sum()}")
+    assert (st == 0).mean() > 0.999
+    rng = np.random.default_rng(2027)
+    idx = np.unique(np.concatenate([np.argsort(nst)[-12:], rng.choice(n, 12, replace=False)]))
+    dirs = O.pix2vec_nest(w.nside, idx)
+    p = O.params(w.obs[0], z_src=float(w.z_src[0]), steps_per_cell=w.steps_per_cell, adaptive=w.adaptive,
+                 max_steps=32768)
+    t = time.time()
+    A, dz, out = O.jacobian_cs(lambda d, th: O.cast_cs(field, O.cosmo(*COSMO), p, d, dtheta=th), dirs)
+    ok = (st[idx] == 0) & (out["status"] == O.REACHED)
+    d = np.abs(jac[idx][ok] - A[ok]).max(axis=(1, 2))
+    _print(f"oracle complex-step Jacobian of {len(idx)} rays in {time.time() - t:.0f} s; steps "
+           f"{nst[idx].min()}..{nst[idx].max()}; max |dA| {d.max():.3g}, median {np.median(d):.3g}")
+    assert ok.sum() >= len(idx) - 1
+    assert np.median(d) < 1e-6 and (d > 2e-5).sum() <= 1
