@@ -319,7 +319,9 @@ __device__ __forceinline__ int64_t grad_slot(int64_t id, int q, int64_t n)
 // Per-wave table in LDS aggregating the gradient cotangents of recently
 // touched cells: direct-mapped on a hash of the cell id, filled with LDS
 // atomics by the lanes of one wave and evicted to the cell array with device
-// atomics when half full.  The 64 rays of a wave start from
+// atomics when a quarter full (a fuller table sends more colliding cells
+// straight to the cell array, which costs more than the extra evictions).
+// The 64 rays of a wave start from
 // neighbouring sky pixels and cross the same cells many times, so the table
 // absorbs most additions and the device atomics (which resolve beyond the
 // per-XCD L2) drop by that reuse factor.
@@ -926,8 +928,8 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
         GeoState y = ck, yin = ck;
         for (int it = 0; it < nf + len; ++it) {
             const bool fwd = it < nf;
-            // the lanes still iterating empty the table when it is half full
-            if (SCATTER && *T.count > kTab / 2) T.evict(A);
+            // the lanes still iterating empty the table when it is a quarter full
+            if (SCATTER && *T.count > kTab / 4) T.evict(A);
             if (it == nf) {
                 // the state before the segment's last step is in registers
                 pre = last ? yin : y;
