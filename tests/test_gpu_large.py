@@ -3,7 +3,8 @@
 rays) to z = 2 with 4 steps per leaf cell, in the launch the benchmark times;
 rays sampled at random and the rays with the most steps recomputed by the
 oracle one by one; then the adjoint distortion matrix on a 2^20-ray chunk
-against the oracle's complex-step Jacobian on sampled rays.
+against the oracle's complex-step Jacobian on sampled rays, and of the whole
+sky in 48 such chunks.
 
 Building the tree takes a few minutes of host time and about 60 GB of host
 memory, the oracle's copy about 40 GB more, the device image about 100 GB of
@@ -154,3 +155,37 @@ def test_large_adjoint_jacobian_sampled(M, large, grid, field):
            f"{nst[idx].min()}..{nst[idx].max()}; max |dA| {d.max():.3g}, median {np.median(d):.3g}")
     assert ok.sum() >= len(idx) - 1
     assert np.median(d) < 1e-6 and (d > 2e-5).sum() <= 1
+
+
+def test_large_full_sky_adjoint(M, large, grid):
+    """The distortion matrix of every ray of the full sky: 48 chunks of 2^20
+    NESTED pixels, each a checkpointed cast and a reverse sweep; every ray
+    differentiated, every matrix finite."""
+    import torch
+    w, _ = large
+    n = 1 << 20
+    assert w.n_rays % n == 0
+    t_fwd = t_rev = 0.0
+    steps = bad = 0
+    for c in range(w.n_rays // n):
+        cfg = M.CastConfig(w.obs, w.z_src, w.nside, [c * n], [n], steps_per_cell=w.steps_per_cell,
+                           adaptive=w.adaptive, checkpoint_every=32, max_steps=32768)
+        torch.cuda.synchronize()
+        t = time.time()
+        fwd = M.cast(grid, cfg)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        res = M.adjoint(grid, cfg, fwd, jacobian=True)
+        torch.cuda.synchronize()
+        t2 = time.time()
+        t_fwd += t1 - t
+        t_rev += t2 - t1
+        steps += int(fwd["n_steps"].to(torch.int64).sum())
+        bad += int((res["ray_status"] != 0).sum())
+        assert bool(torch.isfinite(res["jac"]).all())
+        if c % 8 == 7:
+            _print(f"adjoint: {c + 1} of {w.n_rays // n} chunks")
+        del fwd, res
+    _print(f"full-sky adjoint: {w.n_rays} rays, {steps} ray-steps; checkpointed forward {t_fwd:.2f} s, "
+           f"reverse sweep {t_rev:.2f} s; not differentiated {bad}")
+    assert bad == 0
