@@ -6,8 +6,10 @@ the step rule, the landing or the observables fails at least one of them.
   P1  Phi = 0: straight rays, |x_s - x_o| = eta_0 - eta_s, 1 + z = 1/a, a^2 k0 conserved
   P13 Phi = 0 in a static universe: step count floor(chi/ds) + 1
   P2  constant gradient, static: transverse displacement -g_perp lambda^2, bend
-      2 |g_perp| lambda, z = Phi_o - Phi_s (first order)
-  P3  static potential in FLRW: a^2 k0 = exp(-2 (Phi_s - Phi_o)) exactly
+      2 |g_perp| lambda, z5 = z1 = Phi_o - Phi_s (first order); the deflection
+      alpha = +g_perp chi component by component on (e_phi, -e_theta)
+  P3  static potential in FLRW: a^2 k0 = exp(-2 (Phi_s - Phi_o)) exactly, and
+      z1 = z5 + O(Phi^2)
   P4  point mass, static: total deflection 4 m / b (Born, first order)
   P5  quadratic potential: A = I - chi_s^2/3 H_perp (eq. infinitesimal A) for the
       exact (complex-step) Jacobian, the infinitesimal beam and the finite beam
@@ -87,6 +89,51 @@ def test_p2_constant_gradient(O):
     dphi = out["phi_o"] - out["phi_s"]
     assert np.allclose(out["z5"], dphi, rtol=0, atol=10 * np.max(np.abs(dphi)) ** 2 + 1e-15)
     assert np.max(np.abs(dphi)) > 1e-6      # the test is not trivial
+    # z1 (Sect. 2.5, FLRW redshift plus the potential term): z0 = 0 in a
+    # static universe, so z1 is the gravitational shift Phi_o - Phi_s that
+    # z5 carries at first order; its sign is fixed by z5 above
+    assert np.all(out["z0"] == 0.0)
+    assert np.allclose(out["z1"], out["z5"], rtol=0, atol=10 * np.max(np.abs(dphi)) ** 2 + 1e-15)
+
+
+def _spherical_frame(n):
+    """Unit vectors of the spherical coordinates at directions n: e_theta =
+    dn/dtheta and e_phi = (dn/dphi)/sin(theta) of
+    n = (sin t cos p, sin t sin p, cos t)."""
+    t = np.arccos(np.clip(n[:, 2], -1, 1))
+    p = np.arctan2(n[:, 1], n[:, 0])
+    e_t = np.stack([np.cos(t) * np.cos(p), np.cos(t) * np.sin(p), -np.sin(t)], 1)
+    e_p = np.stack([-np.sin(p), np.cos(p), np.zeros_like(p)], 1)
+    return e_t, e_p
+
+
+def test_p2_deflection_components(O):
+    """Lens equation beta = theta - alpha (Sect. 2.3) with alpha on the screen
+    basis (e1, e2) = (e_phi, -e_theta): for Phi = g.x in a static universe
+    the photon ends displaced by -g_perp chi^2, so beta - theta = -g_perp chi
+    and alpha = +g_perp chi, i.e. alpha_1 = chi g.e_phi and
+    alpha_2 = -chi g.e_theta (first order).  Independently of g, the end
+    direction satisfies r_hat = n - alpha_1 e1 - alpha_2 e2 to second order
+    in the deflection.  A flipped sign of alpha, a flipped e2 or swapped
+    components fail here."""
+    g = np.array([2e-8, -1e-8, 3e-8])
+    f = O.Field.linear(g, phi0=1e-6)
+    dirs = O.pix2vec_nest(2, np.arange(48))
+    chi = 300.0
+    out = O.cast(f, O.STATIC, O.params([0, 0, 0], chi=chi, ds=0.5), dirs)
+    assert np.all(out["status"] == O.REACHED)
+    e_t, e_p = _spherical_frame(dirs)
+    a1 = chi * (e_p @ g)
+    a2 = -chi * (e_t @ g)
+    big = np.hypot(a1, a2)
+    assert big.max() > 5e-6                             # the test is not trivial
+    tol = 20 * np.linalg.norm(g) ** 2 * chi ** 3 + 1e-14
+    assert np.allclose(out["alpha"][:, 0], a1, rtol=0, atol=tol)
+    assert np.allclose(out["alpha"][:, 1], a2, rtol=0, atol=tol)
+    rh = out["r"] / np.linalg.norm(out["r"], axis=1, keepdims=True)
+    d = rh - dirs
+    assert np.allclose(np.sum(d * e_p, 1), -out["alpha"][:, 0], rtol=0, atol=4 * big.max() ** 2)
+    assert np.allclose(np.sum(d * -e_t, 1), -out["alpha"][:, 1], rtol=0, atol=4 * big.max() ** 2)
 
 
 @pytest.mark.parametrize("kind", ["quadratic", "point"])
@@ -108,6 +155,13 @@ def test_p3_redshift_identity(O, kind):
     assert np.max(np.abs(out["phi_s"] - out["phi_o"])) > 1e-7      # not trivial
     # z5 from the same quantities: 1 + z5 = a_s |k0_s| (1 + Phi_s) / (1 + Phi_o)
     assert np.allclose(1 + out["z5"], a_s * (-out["k"][:, 0]) * (1 + out["phi_s"]) / (1 + out["phi_o"]), rtol=1e-14)
+    # z1 = z0 + (1 + z0)(Phi_o - Phi_s) (Sect. 2.5) is z5 to first order in
+    # Phi: the two differ by O(Phi^2) only, while the potential term itself
+    # is of order Phi (a flipped sign of Phi_o - Phi_s fails by 2x it)
+    dphi = np.abs(out["phi_s"] - out["phi_o"])
+    phimax = max(np.abs(out["phi_o"]).max(), np.abs(out["phi_s"]).max())
+    assert np.all(np.abs(out["z5"] - out["z1"]) <= 10 * phimax ** 2 * (1 + out["z0"]))
+    assert np.all(out["z0"] == pytest.approx(0.3, rel=1e-13))
 
 
 def test_p4_point_mass_deflection(O):
