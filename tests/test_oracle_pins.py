@@ -289,3 +289,44 @@ def test_p12_steps_per_cell_convergence(O):
     d1 = sep(r[1]["r"], r[8]["r"])
     assert np.median(d4 / defl) < 0.02
     assert np.median(d1) > np.median(d4)
+
+
+def _with_nan(cells, ijk, field):
+    """Copy of a uniform grid with a NaN in one cell's potential or gradient."""
+    import copy
+    c = copy.deepcopy(cells)
+    n = c.n0
+    i = (ijk[0] * n + ijk[1]) * n + ijk[2]
+    assert tuple(c.ijk[i]) == tuple(ijk)
+    if field == "phi":
+        c.phi[i] = np.nan
+    else:
+        c.grad[i, 1] = np.nan
+    return c
+
+
+def test_t6_nonfinite(O):
+    """Status NONFINITE (Sect. 2.2 stop conditions): a NaN in one cell's
+    gradient stops exactly the rays whose stencils meet that cell, during the
+    step that meets it (that step is not counted), and leaves every other ray
+    bit for bit as on the clean grid; a NaN potential in the observer's
+    stencil makes the initial |k| NaN, so every ray stops in its first step."""
+    cells = synth.make_cells("gauss32")
+    obs = [125.0, 125.0, 125.0]
+    dirs = O.pix2vec_nest(4, np.arange(192))
+    p = O.params(obs, z_src=0.2, steps_per_cell=4)
+    clean = O.cast(O.Field.grid(cells), O.cosmo(), p, dirs)
+    out = O.cast(O.Field.grid(_with_nan(cells, (18, 16, 16), "grad")), O.cosmo(), p, dirs)
+    hit = out["status"] == O.NONFINITE
+    assert 0 < hit.sum() < len(dirs) // 2
+    assert np.all(out["status"][~hit] == O.REACHED) and np.all(clean["status"] == O.REACHED)
+    for k in ("r", "z5", "alpha", "n_steps", "hash"):
+        assert np.array_equal(out[k][~hit], clean[k][~hit]), k
+    assert np.all(out["n_steps"][hit] < clean["n_steps"][hit])
+    assert np.all(out["n_steps"][hit] >= 1)          # the cell is a few cells from the observer
+    # the rays stopped are those pointing at the cell (centre 2.5 cells along +x)
+    cen = (np.array([18, 16, 16]) + 0.5) * 250.0 / 32 - obs
+    cos = dirs @ (cen / np.linalg.norm(cen))
+    assert cos[hit].min() > cos[~hit].min() and np.median(cos[hit]) > np.median(cos[~hit])
+    out0 = O.cast(O.Field.grid(_with_nan(cells, (16, 16, 16), "phi")), O.cosmo(), p, dirs)
+    assert np.all(out0["status"] == O.NONFINITE) and np.all(out0["n_steps"] == 0)
