@@ -79,7 +79,15 @@ typedef struct {
  *   ijk[i][3]   integer coordinates at the cell's own level, in [0, n0 2^level)
  *   phi[i]      potential at the cell centre (each cell, internal or leaf,
  *               carries its own value: used when interpolating at its level)
- *   grad[i][3]  gradient of the potential at the cell centre
+ *   grad[i][3]  gradient of the potential at the cell centre, or grad == NULL:
+ *               the library takes second-order central differences of phi
+ *               between the two neighbours of the cell at its own level
+ *               (periodic wrap on periodic grids), (phi[+] - phi[-]) / (2 h_l)
+ *               in double precision, h_l = box / (n0 2^l); where only one
+ *               neighbour exists at that level (the edge of a refined region
+ *               or of a non-periodic box) the one-sided difference with it,
+ *               and 0 where neither does.  Sect. 2.1 stores the force with
+ *               the potential; this is the gradient such grids carry.
  *   dphi_deta[i] optional (NULL: a static potential): the time derivative of
  *               the potential at the cell centre (Sect. 2.2; from two light
  *               cones shifted in time, see mpath_double_layer).  A grid that
@@ -106,9 +114,20 @@ typedef struct {
 
 typedef struct mpath_grid mpath_grid;   /* opaque host handle */
 
-/* Device workspace needed by mpath_grid_build for this tree (payload of
- * 16 B/cell, child links, cell permutation, cosmology table). */
+/* Device workspace needed by mpath_grid_build for this tree: the image every
+ * cast reads, 148 B per cell (payload 16 B, child link 4 B, stencil record
+ * 128 B) plus 32 B per refined cell (level >= 1: the stencil of each
+ * half-cell), 36 B more per cell with dphi_deta, the background tables and a
+ * 64 MB staging area used during the build. */
 int mpath_grid_workspace_bytes(const mpath_grid_desc* desc, size_t* bytes);
+
+/* Device workspace of the grid's auxiliary tables, 40 B per cell: the
+ * caller's index of every library cell and the 8 cell ids of every stencil.
+ * Only mpath_grid_set_values and the cell cotangents of mpath_adjoint
+ * (dL_dvalues, dL_dphi_total) read them; a grid built without them casts,
+ * differentiates per ray (distortion matrix, dz/dtheta) and runs every
+ * product the same. */
+int mpath_grid_aux_bytes(const mpath_grid_desc* desc, size_t* bytes);
 
 /* Validate the tree (MPATH_ERR_NOT_FULL_TREE if a cell's parent is missing, a
  * refined cell has 1-7 children, a coarse cell is missing or a cell repeats),
@@ -119,6 +138,13 @@ int mpath_grid_workspace_bytes(const mpath_grid_desc* desc, size_t* bytes);
  * outlive the handle. */
 int mpath_grid_build(const mpath_grid_desc* desc, const mpath_cosmo* cosmo, void* dev_ws,
                      size_t ws_bytes, void* stream, mpath_grid** out);
+
+/* mpath_grid_build plus the auxiliary tables in aux_ws (aux_bytes >=
+ * mpath_grid_aux_bytes; a DEVICE buffer the caller owns and keeps alive with
+ * dev_ws).  aux_ws == NULL is mpath_grid_build.  Errors as mpath_grid_build,
+ * and WORKSPACE_TOO_SMALL for aux_bytes. */
+int mpath_grid_build_with_aux(const mpath_grid_desc* desc, const mpath_cosmo* cosmo, void* dev_ws,
+                              size_t ws_bytes, void* aux_ws, size_t aux_bytes, void* stream, mpath_grid** out);
 
 /* dPhi/deta of every cell from a double-layer light cone (Sect. 2.2, the
  * equation for dPhi/deta from two light cones slightly shifted in time):
@@ -152,13 +178,15 @@ typedef struct {
     double eta0;              /* conformal time today */
     int64_t cells_per_level[16];
     float* payload;           /* DEVICE [n_cells][4] (phi, gx, gy, gz), library order */
-    const int64_t* perm;      /* DEVICE [n_cells]: user index of library cell i */
+    const int64_t* perm;      /* DEVICE [n_cells]: user index of library cell i (NULL
+                                 without the auxiliary tables) */
 } mpath_grid_info;
 
 int mpath_grid_get_info(const mpath_grid* grid, mpath_grid_info* info);
 
 /* Replace the cell values from a DEVICE array values[n_cells][4] = (phi, gx,
- * gy, gz) float32 in the caller's original cell order (asynchronous). */
+ * gy, gz) float32 in the caller's original cell order (asynchronous).
+ * MPATH_ERR_UNSUPPORTED for a grid without its auxiliary tables. */
 int mpath_grid_set_values(mpath_grid* grid, const float* values, void* stream);
 
 /* ---- casting rays ---- */
@@ -344,7 +372,8 @@ int mpath_cast(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observ
  * ray's outputs are then NaN and its cell terms incomplete).
  * Any output pointer may be NULL; the cell cotangents are float32 sums
  * accumulated with atomics, so their last bits depend on the order of the
- * additions. */
+ * additions, and need the grid's auxiliary tables (mpath_grid_build_with_aux;
+ * MPATH_ERR_UNSUPPORTED without them). */
 typedef struct {
     const float* dL_dalpha;
     const double* dL_dz;

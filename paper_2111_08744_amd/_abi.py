@@ -102,6 +102,8 @@ def lib():
         P, vp, sz = C.POINTER, C.c_void_p, C.c_size_t
         L.mpath_grid_workspace_bytes.argtypes = [P(mpath_grid_desc), P(sz)]
         L.mpath_grid_build.argtypes = [P(mpath_grid_desc), P(mpath_cosmo), vp, sz, vp, P(vp)]
+        L.mpath_grid_aux_bytes.argtypes = [P(mpath_grid_desc), P(sz)]
+        L.mpath_grid_build_with_aux.argtypes = [P(mpath_grid_desc), P(mpath_cosmo), vp, sz, vp, sz, vp, P(vp)]
         L.mpath_grid_free.argtypes = [vp]
         L.mpath_grid_get_info.argtypes = [vp, P(mpath_grid_info)]
         L.mpath_grid_set_values.argtypes = [vp, vp, vp]
@@ -129,6 +131,7 @@ def lib():
         L.mpath_last_error.restype = C.c_char_p
         L.mpath_version.restype = C.c_char_p
         for name in ("mpath_grid_workspace_bytes", "mpath_grid_build", "mpath_grid_free",
+                     "mpath_grid_aux_bytes", "mpath_grid_build_with_aux",
                      "mpath_grid_get_info", "mpath_grid_set_values", "mpath_cast_workspace_bytes",
                      "mpath_cast", "mpath_cast_count_rays", "mpath_adjoint_workspace_bytes",
                      "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune", "mpath_gather_probe",

@@ -1037,13 +1037,14 @@ __global__ void scatter_grad_kernel(const float* __restrict__ g_lib, const int64
 // cotangent of Phi is the direct one plus the transposed difference operator
 // applied to the cotangents of g:
 //   dL/dPhi[c] += sum_d (gbar_d[c - e_d] - gbar_d[c + e_d]) / (2 h0).
-__global__ void central_transpose_kernel(const float* __restrict__ g_lib, const int4* __restrict__ cellpos,
-                                         const int64_t* __restrict__ perm, float* __restrict__ out, int n0,
-                                         double inv_2h, int64_t n)
+__global__ void central_transpose_kernel(const float* __restrict__ g_lib, const int64_t* __restrict__ perm,
+                                         float* __restrict__ out, int n0, double inv_2h, int64_t n)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    const int4 p = cellpos[c];
+    // the id of a coarse cell is its Morton index
+    const int3 p = make_int3((int)compact1by2((uint32_t)c), (int)compact1by2((uint32_t)c >> 1),
+                             (int)compact1by2((uint32_t)c >> 2));
     const uint32_t m = (uint32_t)n0 - 1u;
     auto id = [m](int i, int j, int k) { return (int64_t)morton3((uint32_t)i & m, (uint32_t)j & m, (uint32_t)k & m); };
     auto gq = [&](int64_t cell, int q) { return (double)g_lib[grad_slot(cell, q, n)]; };
@@ -1094,12 +1095,12 @@ hipError_t launch_scatter_grad(const float* grad_lib, const int64_t* perm, float
     return hipGetLastError();
 }
 
-hipError_t launch_central_transpose(const float* g_lib, const int4* cellpos, const int64_t* perm, float* out,
-                                    int n0, double h0, int64_t n, hipStream_t s)
+hipError_t launch_central_transpose(const float* g_lib, const int64_t* perm, float* out, int n0, double h0,
+                                    int64_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(central_transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g_lib, cellpos,
-                       perm, out, n0, 0.5 / h0, n);
+    hipLaunchKernelGGL(central_transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g_lib, perm,
+                       out, n0, 0.5 / h0, n);
     return hipGetLastError();
 }
 

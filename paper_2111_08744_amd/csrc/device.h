@@ -310,7 +310,7 @@ struct FieldCache {
         // the edge of a non-periodic box), whose base follows from the Morton
         // order without the per-half-cell table
         if (AMR && L > 0) {
-            base = g.leafinfo[8 * (int64_t)leafId + ((k0 & 1) | ((k1 & 1) << 1) | ((k2 & 1) << 2))];
+            base = g.leafinfo[8 * (int64_t)(leafId - g.level_start[1]) + ((k0 & 1) | ((k1 & 1) << 1) | ((k2 & 1) << 2))];
             if (base < 0) return false;
             l = level_of(g, base);
         } else {

@@ -31,7 +31,8 @@ struct ObsDev {
 //   dual[c]      the trilinear coefficients c0..c7 (see device.h) of the
 //                payloads of the 8 cells (l, ijk(c) + {0,1}^3) of c's level
 //                (zeros where such a cell does not exist);
-//   leafinfo[c]  for a leaf c of level L and each half-cell q of it (the
+//   leafinfo[c - level_start[1]]  for a leaf c of level L >= 1 and each
+//                half-cell q of it (the
 //                8 sub-octants, q = qx + 2 qy + 4 qz), the id of the lowest
 //                corner cell of the CIC stencil that the AMR fallback
 //                procedure selects for points in that half-cell, or -1 when
@@ -42,8 +43,9 @@ struct GridDev {
     const float4* payload;    // (phi, gx, gy, gz) per cell
     const int32_t* child;     // first child id, -1 for a leaf
     const float4* dual;       // [n][8]
-    const int32_t* leafinfo;  // [n][8]
-    const int32_t* dual_ids;  // [n][8] ids of the 8 cells of dual[c] (-1: missing)
+    const int32_t* leafinfo;  // [n - level_start[1]][8]: rows of the refined cells only
+    const int32_t* dual_ids;  // [n][8] ids of the 8 cells of dual[c] (-1: missing); null
+                              // unless the grid has its auxiliary tables
     const float4* tdual;      // [n][2]: 8 trilinear coefficients of dPhi/deta, or null (static potential)
     double h0;                // coarse cell size
     double inv_h0;
@@ -152,21 +154,24 @@ hipError_t launch_born_beam(const CastArgs& a, float* A, int32_t* status, hipStr
 hipError_t launch_cast_surfaces(const CastArgs& a, const double2* surf, int n_extra, hipStream_t s);
 hipError_t launch_permute_values(float4* payload, const int64_t* perm, const float4* values,
                                  int64_t n, hipStream_t s);
-// Derived tables (defined in grid.hip); cellpos[c] = (i, j, k, level).
-hipError_t launch_build_dual(const GridDev& g, const int4* cellpos, float4* dual, int64_t n, hipStream_t s);
-hipError_t launch_build_tdual(const GridDev& g, const int4* cellpos, const float* tpay, float4* tdual, int64_t n,
-                              hipStream_t s);
-hipError_t launch_build_leafinfo(const GridDev& g, const int4* cellpos, int32_t* leafinfo, int64_t n,
+// Derived tables (defined in grid.hip), built for the cells [c0, c0 + m)
+// from their positions pos[0 .. m) = (i, j, k, level) (a staged chunk).
+hipError_t launch_build_dual(const GridDev& g, const int4* pos, int64_t c0, int64_t m, float4* dual, hipStream_t s);
+hipError_t launch_rebuild_dual(const GridDev& g, const int32_t* ids, float4* dual, int64_t n, hipStream_t s);
+hipError_t launch_build_tdual(const GridDev& g, const int4* pos, int64_t c0, int64_t m, const float* tpay,
+                              float4* tdual, hipStream_t s);
+hipError_t launch_build_leafinfo(const GridDev& g, const int4* pos, int64_t c0, int64_t m, int32_t* leafinfo,
                                  hipStream_t s);
-hipError_t launch_build_dual_ids(const GridDev& g, const int4* cellpos, int32_t* ids, int64_t n, hipStream_t s);
+hipError_t launch_build_dual_ids(const GridDev& g, const int4* pos, int64_t c0, int64_t m, int32_t* ids,
+                                 hipStream_t s);
 // Adjoint (defined in adjoint.hip).
 hipError_t launch_cast_checkpointed(const CastArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjointArgs& a, int columns, hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 hipError_t launch_scatter_grad(const float* grad_lib, const int64_t* perm, float4* out_user, int64_t n,
                                hipStream_t s);
-hipError_t launch_central_transpose(const float* g_lib, const int4* cellpos, const int64_t* perm, float* out,
-                                    int n0, double h0, int64_t n, hipStream_t s);
+hipError_t launch_central_transpose(const float* g_lib, const int64_t* perm, float* out, int n0, double h0,
+                                    int64_t n, hipStream_t s);
 int cast_occupancy_blocks_per_cu(int block, bool amr, bool time_dep);
 // Reference rays of one observer for the finite-beam casts.
 struct BeamObs {
@@ -211,6 +216,17 @@ __host__ __device__ inline uint32_t part1by2(uint32_t x)
 __host__ __device__ inline uint32_t morton3(uint32_t i, uint32_t j, uint32_t k)
 {
     return part1by2(i) | (part1by2(j) << 1) | (part1by2(k) << 2);
+}
+
+// Inverse of part1by2: every third bit of x, compacted.
+__host__ __device__ inline uint32_t compact1by2(uint32_t x)
+{
+    x &= 0x09249249u;
+    x = (x | (x >> 2)) & 0x030C30C3u;
+    x = (x | (x >> 4)) & 0x0300F00Fu;
+    x = (x | (x >> 8)) & 0x030000FFu;
+    x = (x | (x >> 16)) & 0x000003FFu;
+    return x;
 }
 
 }  // namespace mpath

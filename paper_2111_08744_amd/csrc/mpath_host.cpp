@@ -9,6 +9,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -150,10 +151,9 @@ struct mpath_grid {
     char* ws = nullptr;
     float4* payload = nullptr;
     int32_t* child = nullptr;
-    int64_t* perm = nullptr;
-    int4* cellpos = nullptr;
     float4* dual = nullptr;
-    int32_t* leafinfo = nullptr;
+    int32_t* leafinfo = nullptr;  // rows of the refined cells (ids >= level_start[1])
+    int64_t* perm = nullptr;      // auxiliary tables (null without them)
     int32_t* dual_ids = nullptr;
     double2* table = nullptr;
     double2* atable = nullptr;    // (a, da/deta) on the nodes of table
@@ -167,29 +167,108 @@ struct mpath_grid {
 namespace {
 
 struct GridLayout {
-    size_t off_payload, off_child, off_perm, off_cellpos, off_dual, off_leafinfo, off_dual_ids, off_table;
-    size_t off_atable, off_tpay, off_tdual, total;
+    size_t off_payload, off_child, off_dual, off_leafinfo, off_table, off_atable, off_tpay, off_tdual, off_stage;
+    size_t total;
+    int64_t stage_cells;
 };
 
-// Device workspace of a grid: 236 bytes per cell plus the background table,
-// and 36 more per cell for a time-dependent potential (dPhi/deta and its
-// stencil coefficients).
-GridLayout grid_layout(int64_t n, bool time_dep)
+// Cells whose positions one staging chunk of the build holds (64 MB).
+constexpr int64_t kStageCells = (int64_t)1 << 22;
+
+// Device image of a grid, everything a cast reads: payload (16 B), child
+// link (4 B) and stencil record (128 B) per cell, the per-half-cell stencil
+// table (32 B) per refined cell (level >= 1), the background tables, and for
+// a time-dependent potential 36 B more per cell (dPhi/deta and its stencil
+// coefficients); plus a staging area for cell positions during the build.
+GridLayout grid_layout(int64_t n, int64_t n_coarse, bool time_dep)
 {
     GridLayout L;
+    const int64_t n_ref = n - n_coarse;
+    L.stage_cells = std::min<int64_t>(n, kStageCells);
     L.off_payload = 0;
     L.off_child = align_up(L.off_payload + (size_t)n * 16, 256);
-    L.off_perm = align_up(L.off_child + (size_t)n * 4, 256);
-    L.off_cellpos = align_up(L.off_perm + (size_t)n * 8, 256);
-    L.off_dual = align_up(L.off_cellpos + (size_t)n * 16, 256);
+    L.off_dual = align_up(L.off_child + (size_t)n * 4, 256);
     L.off_leafinfo = align_up(L.off_dual + (size_t)n * 128, 256);
-    L.off_dual_ids = align_up(L.off_leafinfo + (size_t)n * 32, 256);
-    L.off_table = align_up(L.off_dual_ids + (size_t)n * 32, 256);
+    L.off_table = align_up(L.off_leafinfo + (size_t)n_ref * 32, 256);
     L.off_atable = align_up(L.off_table + (size_t)kTableN * 16, 256);
     L.off_tpay = align_up(L.off_atable + (size_t)kTableN * 16, 256);
     L.off_tdual = align_up(L.off_tpay + (time_dep ? (size_t)n * 4 : 0), 256);
-    L.total = align_up(L.off_tdual + (time_dep ? (size_t)n * 32 : 0), 256);
+    L.off_stage = align_up(L.off_tdual + (time_dep ? (size_t)n * 32 : 0), 256);
+    L.total = align_up(L.off_stage + (size_t)L.stage_cells * 16, 256);
     return L;
+}
+
+// Auxiliary tables: the caller's index of every library cell (8 B) and the
+// ids of the 8 cells of every stencil record (32 B).
+struct AuxLayout {
+    size_t off_perm, off_dual_ids, total;
+};
+
+AuxLayout aux_layout(int64_t n)
+{
+    AuxLayout L;
+    L.off_perm = 0;
+    L.off_dual_ids = align_up((size_t)n * 8, 256);
+    L.total = align_up(L.off_dual_ids + (size_t)n * 32, 256);
+    return L;
+}
+
+int host_threads()
+{
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(h, 32u));
+}
+
+// fn(a, b) over consecutive ranges of [0, n) on up to host_threads()
+// threads; each range writes only its own outputs.
+template <class F>
+void parallel_ranges(int64_t n, F fn, int64_t min_per_thread = (int64_t)1 << 16)
+{
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / min_per_thread));
+    if (T <= 1) {
+        fn((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) {
+        const int64_t a = n * t / T, b = n * (t + 1) / T;
+        th.emplace_back([=, &fn] { fn(a, b); });
+    }
+    for (auto& x : th) x.join();
+}
+
+// Sort (key, cell) pairs by key: sorted runs on threads, then pairwise merges.
+void parallel_sort(std::vector<std::pair<uint64_t, int64_t>>& v)
+{
+    const int64_t n = (int64_t)v.size();
+    int T = 1;
+    while (T * 2 <= host_threads() && n / (T * 2) >= ((int64_t)1 << 18)) T *= 2;
+    if (T == 1) {
+        std::sort(v.begin(), v.end());
+        return;
+    }
+    std::vector<int64_t> cut(T + 1);
+    for (int t = 0; t <= T; ++t) cut[t] = n * t / T;
+    {
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; ++t) th.emplace_back([&, t] { std::sort(v.begin() + cut[t], v.begin() + cut[t + 1]); });
+        for (auto& x : th) x.join();
+    }
+    std::vector<std::pair<uint64_t, int64_t>> tmp(n);
+    auto* src = &v;
+    auto* dst = &tmp;
+    for (int w = 1; w < T; w *= 2) {
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; t += 2 * w) {
+            th.emplace_back([&, t] {
+                const int64_t a = cut[t], m = cut[std::min(t + w, T)], b = cut[std::min(t + 2 * w, T)];
+                std::merge(src->begin() + a, src->begin() + m, src->begin() + m, src->begin() + b, dst->begin() + a);
+            });
+        }
+        for (auto& x : th) x.join();
+        std::swap(src, dst);
+    }
+    if (src != &v) v.swap(tmp);
 }
 
 GridDev make_griddev(const mpath_grid* g)
@@ -229,7 +308,7 @@ int check_grid_desc(const mpath_grid_desc* d)
     const int64_t nc = (int64_t)d->n0 * d->n0 * d->n0;
     if (d->n_cells < nc) return fail(MPATH_ERR_NOT_FULL_TREE, "fewer cells than the coarse grid");
     if (d->n_cells > ((int64_t)1 << 31) - 8) return fail(MPATH_ERR_INVALID_ARG, "n_cells must be < 2^31");
-    if (!d->level || !d->ijk || !d->phi || !d->grad) return fail(MPATH_ERR_INVALID_ARG, "a cell array is NULL");
+    if (!d->level || !d->ijk || !d->phi) return fail(MPATH_ERR_INVALID_ARG, "a cell array is NULL");
     return MPATH_OK;
 }
 
@@ -274,12 +353,22 @@ int mpath_grid_workspace_bytes(const mpath_grid_desc* desc, size_t* bytes)
     if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
     const int rc = check_grid_desc(desc);
     if (rc) return rc;
-    *bytes = grid_layout(desc->n_cells, desc->dphi_deta != nullptr).total;
+    const int64_t nc = (int64_t)desc->n0 * desc->n0 * desc->n0;
+    *bytes = grid_layout(desc->n_cells, nc, desc->dphi_deta != nullptr).total;
     return MPATH_OK;
 }
 
-int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* dev_ws, size_t ws_bytes,
-                     void* stream, mpath_grid** out)
+int mpath_grid_aux_bytes(const mpath_grid_desc* desc, size_t* bytes)
+{
+    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
+    const int rc = check_grid_desc(desc);
+    if (rc) return rc;
+    *bytes = aux_layout(desc->n_cells).total;
+    return MPATH_OK;
+}
+
+int mpath_grid_build_with_aux(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* dev_ws, size_t ws_bytes,
+                              void* aux_ws, size_t aux_bytes, void* stream, mpath_grid** out)
 {
     if (!out) return fail(MPATH_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -291,75 +380,131 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
                    std::fabs(cosmo->omega_m + cosmo->omega_l - 1.0) < 1e-12))
         return fail(MPATH_ERR_UNSUPPORTED, "only flat LCDM (omega_m + omega_l = 1) or a static background");
     const bool time_dep = d->dphi_deta != nullptr;
-    const GridLayout lay = grid_layout(d->n_cells, time_dep);
-    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
-    if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "grid workspace too small");
-
     const int64_t n = d->n_cells;
     const int L = d->max_level;
     const uint32_t n0 = (uint32_t)d->n0;
+    const int64_t nc = (int64_t)n0 * n0 * n0;
+    const GridLayout lay = grid_layout(n, nc, time_dep);
+    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
+    if (ws_bytes < lay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "grid workspace too small");
+    const bool aux = aux_ws != nullptr;
+    const AuxLayout alay = aux_layout(n);
+    if (aux && aux_bytes < alay.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "grid auxiliary workspace too small");
+
     // ---- bucket cells by level, keyed by Morton order at their level ----
+    for (int64_t c = 0; c < n; ++c)
+        if (d->level[c] > L) return fail(MPATH_ERR_INVALID_ARG, "cell " + std::to_string(c) + " level above max_level");
+    std::vector<int64_t> per_level(L + 1, 0);
+    for (int64_t c = 0; c < n; ++c) ++per_level[d->level[c]];
+    if (per_level[0] != nc) return fail(MPATH_ERR_NOT_FULL_TREE, "the coarse level must hold n0^3 cells");
+    // keys of the coarse level are 0 .. nc-1 when every coarse cell is
+    // present once: they go straight to their slot
+    std::vector<int64_t> coarse(nc, -1);
     std::vector<std::vector<std::pair<uint64_t, int64_t>>> lev(L + 1);
+    for (int l = 1; l <= L; ++l) lev[l].reserve(per_level[l]);
     for (int64_t c = 0; c < n; ++c) {
         const int l = d->level[c];
-        if (l > L) return fail(MPATH_ERR_INVALID_ARG, "cell " + std::to_string(c) + " level above max_level");
         const int64_t m = (int64_t)n0 << l;
         const int32_t* q = d->ijk + 3 * c;
         if (q[0] < 0 || q[1] < 0 || q[2] < 0 || q[0] >= m || q[1] >= m || q[2] >= m)
             return fail(MPATH_ERR_INVALID_ARG, "cell " + std::to_string(c) + " coordinates out of range");
-        lev[l].push_back({morton_key((uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]), c});
+        const uint64_t key = morton_key((uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]);
+        if (l == 0) {
+            if (coarse[key] >= 0) return fail(MPATH_ERR_NOT_FULL_TREE, "missing or repeated coarse cell");
+            coarse[key] = c;
+        } else {
+            lev[l].push_back({key, c});
+        }
     }
-    for (int l = 0; l <= L; ++l) std::sort(lev[l].begin(), lev[l].end());
-    // coarse level: exactly n0^3 distinct cells, so the sorted keys are 0..n0^3-1
-    const int64_t nc = (int64_t)n0 * n0 * n0;
-    if ((int64_t)lev[0].size() != nc) return fail(MPATH_ERR_NOT_FULL_TREE, "the coarse level must hold n0^3 cells");
-    for (int64_t i = 0; i < nc; ++i)
-        if (lev[0][i].first != (uint64_t)i) return fail(MPATH_ERR_NOT_FULL_TREE, "missing or repeated coarse cell");
+    for (int l = 1; l <= L; ++l) parallel_sort(lev[l]);
     // refined levels: complete sibling groups whose parent exists
     std::vector<int32_t> child(n, -1);
     std::vector<int64_t> perm(n);
+    for (int64_t i = 0; i < nc; ++i) perm[i] = coarse[i];
     int64_t base_prev = 0, base = nc;
-    for (int64_t i = 0; i < nc; ++i) perm[i] = lev[0][i].second;
     for (int l = 1; l <= L; ++l) {
         const auto& cur = lev[l];
-        const auto& par = lev[l - 1];
         if (cur.size() % 8) return fail(MPATH_ERR_NOT_FULL_TREE, "a refined cell has 1-7 children (level " + std::to_string(l) + ")");
-        size_t pj = 0;
+        // keys of the parent level in library order
+        auto parent_key = [&](int64_t j) -> uint64_t {
+            return l == 1 ? (uint64_t)j : lev[l - 1][(size_t)j].first;
+        };
+        const int64_t n_par = l == 1 ? nc : (int64_t)lev[l - 1].size();
+        int64_t pj = 0;
         for (size_t g = 0; g < cur.size(); g += 8) {
             const uint64_t pk = cur[g].first >> 3;
             for (int o = 0; o < 8; ++o)
                 if (cur[g + o].first != (pk << 3) + (uint64_t)o)
                     return fail(MPATH_ERR_NOT_FULL_TREE, "a refined cell has 1-7 children or a repeated child (level " + std::to_string(l) + ")");
-            while (pj < par.size() && par[pj].first < pk) ++pj;
-            if (pj == par.size() || par[pj].first != pk)
+            while (pj < n_par && parent_key(pj) < pk) ++pj;
+            if (pj == n_par || parent_key(pj) != pk)
                 return fail(MPATH_ERR_NOT_FULL_TREE, "a cell's parent is missing (level " + std::to_string(l) + ")");
             const int64_t id = base + (int64_t)g;
-            child[base_prev + (int64_t)pj] = (int32_t)id;
+            child[base_prev + pj] = (int32_t)id;
             for (int o = 0; o < 8; ++o) perm[id + o] = cur[g + o].second;
         }
         base_prev = base;
         base += (int64_t)cur.size();
     }
-    // ---- pack (phi, grad) as float32 and the cell coordinates in library order ----
+    // ---- caller index of cell (l, i, j, k), -1 if absent (gradients) ----
+    auto find_cell = [&](int l, int64_t i, int64_t j, int64_t k) -> int64_t {
+        const int64_t m = (int64_t)n0 << l;
+        if (d->periodic) {
+            i = ((i % m) + m) % m; j = ((j % m) + m) % m; k = ((k % m) + m) % m;
+        } else if (i < 0 || j < 0 || k < 0 || i >= m || j >= m || k >= m) {
+            return -1;
+        }
+        const uint64_t key = morton_key((uint32_t)i, (uint32_t)j, (uint32_t)k);
+        if (l == 0) return coarse[key];
+        const auto& v = lev[l];
+        auto it = std::lower_bound(v.begin(), v.end(), std::make_pair(key, (int64_t)-1));
+        return (it != v.end() && it->first == key) ? it->second : -1;
+    };
+    auto phi_at = [&](int64_t c) -> double {
+        return d->value_dtype == MPATH_F64 ? ((const double*)d->phi)[c] : (double)((const float*)d->phi)[c];
+    };
+    // ---- pack (phi, grad) as float32 and the cell positions in library order ----
     std::vector<float4> payload(n);
     std::vector<int4> cellpos(n);
     std::vector<float> tpay(time_dep ? n : 0);
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t c = perm[i];
-        if (time_dep)
-            tpay[i] = d->value_dtype == MPATH_F64 ? (float)((const double*)d->dphi_deta)[c]
-                                                  : ((const float*)d->dphi_deta)[c];
-        cellpos[i] = make_int4(d->ijk[3 * c], d->ijk[3 * c + 1], d->ijk[3 * c + 2], (int)d->level[c]);
-        if (d->value_dtype == MPATH_F64) {
-            const double* p = (const double*)d->phi;
-            const double* g = (const double*)d->grad;
-            payload[i] = make_float4((float)p[c], (float)g[3 * c], (float)g[3 * c + 1], (float)g[3 * c + 2]);
-        } else {
-            const float* p = (const float*)d->phi;
-            const float* g = (const float*)d->grad;
-            payload[i] = make_float4(p[c], g[3 * c], g[3 * c + 1], g[3 * c + 2]);
+    parallel_ranges(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const int64_t c = perm[i];
+            const int l = d->level[c];
+            const int32_t* q = d->ijk + 3 * c;
+            if (time_dep)
+                tpay[i] = d->value_dtype == MPATH_F64 ? (float)((const double*)d->dphi_deta)[c]
+                                                      : ((const float*)d->dphi_deta)[c];
+            cellpos[i] = make_int4(q[0], q[1], q[2], l);
+            float gr[3];
+            if (d->grad) {
+                for (int a = 0; a < 3; ++a)
+                    gr[a] = d->value_dtype == MPATH_F64 ? (float)((const double*)d->grad)[3 * c + a]
+                                                        : ((const float*)d->grad)[3 * c + a];
+            } else {
+                // second-order central differences of phi between the two
+                // neighbours at the cell's own level; where one of them does
+                // not exist (the edge of a refined region or of a
+                // non-periodic box), the one-sided difference with the other
+                const double h = d->box / (double)((int64_t)n0 << l);
+                const double p0 = phi_at(c);
+                for (int a = 0; a < 3; ++a) {
+                    const int e0 = a == 0, e1 = a == 1, e2 = a == 2;
+                    const int64_t cp = find_cell(l, (int64_t)q[0] + e0, (int64_t)q[1] + e1, (int64_t)q[2] + e2);
+                    const int64_t cm = find_cell(l, (int64_t)q[0] - e0, (int64_t)q[1] - e1, (int64_t)q[2] - e2);
+                    double g = 0.0;
+                    if (cp >= 0 && cm >= 0) g = (phi_at(cp) - phi_at(cm)) / (2.0 * h);
+                    else if (cp >= 0) g = (phi_at(cp) - p0) / h;
+                    else if (cm >= 0) g = (p0 - phi_at(cm)) / h;
+                    gr[a] = (float)g;
+                }
+            }
+            payload[i] = make_float4((float)phi_at(c), gr[0], gr[1], gr[2]);
         }
-    }
+    });
+    lev.clear();
+    lev.shrink_to_fit();
+    std::vector<int64_t>().swap(coarse);
     // ---- background table of a'/a ----
     mpath_grid* G = new mpath_grid();
     G->phi_max = -INFINITY;
@@ -391,41 +536,52 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
     for (int l = 0; l <= kMaxLevels; ++l) {
         G->level_start[l] = (int32_t)start;
         if (l <= L) {
-            G->cells_per_level[l] = (int64_t)lev[l].size();
-            start += (int64_t)lev[l].size();
+            G->cells_per_level[l] = per_level[l];
+            start += per_level[l];
         }
     }
     G->ws = (char*)dev_ws;
     G->payload = (float4*)(G->ws + lay.off_payload);
     G->child = (int32_t*)(G->ws + lay.off_child);
-    G->perm = (int64_t*)(G->ws + lay.off_perm);
-    G->cellpos = (int4*)(G->ws + lay.off_cellpos);
     G->dual = (float4*)(G->ws + lay.off_dual);
     G->leafinfo = (int32_t*)(G->ws + lay.off_leafinfo);
-    G->dual_ids = (int32_t*)(G->ws + lay.off_dual_ids);
     G->table = (double2*)(G->ws + lay.off_table);
     G->atable = (double2*)(G->ws + lay.off_atable);
     if (time_dep) {
         G->tpay = (float*)(G->ws + lay.off_tpay);
         G->tdual = (float4*)(G->ws + lay.off_tdual);
     }
+    if (aux) {
+        G->perm = (int64_t*)((char*)aux_ws + alay.off_perm);
+        G->dual_ids = (int32_t*)((char*)aux_ws + alay.off_dual_ids);
+    }
+    int4* stage = (int4*)(G->ws + lay.off_stage);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     const GridDev gd = make_griddev(G);
     if ((e = hipMemcpyAsync(G->payload, payload.data(), (size_t)n * 16, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(G->child, child.data(), (size_t)n * 4, hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(G->perm, perm.data(), (size_t)n * 8, hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(G->cellpos, cellpos.data(), (size_t)n * 16, hipMemcpyHostToDevice, s)) ||
+        (aux && (e = hipMemcpyAsync(G->perm, perm.data(), (size_t)n * 8, hipMemcpyHostToDevice, s))) ||
         (e = hipMemcpyAsync(G->table, table.data(), (size_t)kTableN * 16, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(G->atable, atable.data(), (size_t)kTableN * 16, hipMemcpyHostToDevice, s)) ||
-        (e = launch_build_dual(gd, G->cellpos, G->dual, n, s)) ||
-        (e = launch_build_leafinfo(gd, G->cellpos, G->leafinfo, n, s)) ||
-        (e = launch_build_dual_ids(gd, G->cellpos, G->dual_ids, n, s)) ||
-        (time_dep && (e = hipMemcpyAsync(G->tpay, tpay.data(), (size_t)n * 4, hipMemcpyHostToDevice, s))) ||
-        (time_dep && (e = launch_build_tdual(gd, G->cellpos, G->tpay, G->tdual, n, s))) ||
-        (e = hipStreamSynchronize(s))) {
+        (time_dep && (e = hipMemcpyAsync(G->tpay, tpay.data(), (size_t)n * 4, hipMemcpyHostToDevice, s)))) {
         delete G;
         return hip_fail(e, "grid upload");
+    }
+    // derived tables, chunk by chunk through the staging area (stream order
+    // keeps each chunk's positions until its kernels have read them)
+    for (int64_t c0 = 0; c0 < n && !e; c0 += lay.stage_cells) {
+        const int64_t m = std::min(lay.stage_cells, n - c0);
+        const int64_t r0 = std::max(c0, nc);      // first refined cell of the chunk
+        (void)((e = hipMemcpyAsync(stage, cellpos.data() + c0, (size_t)m * 16, hipMemcpyHostToDevice, s)) ||
+               (e = launch_build_dual(gd, stage, c0, m, G->dual, s)) ||
+               (r0 < c0 + m && (e = launch_build_leafinfo(gd, stage + (r0 - c0), r0, c0 + m - r0, G->leafinfo, s))) ||
+               (aux && (e = launch_build_dual_ids(gd, stage, c0, m, G->dual_ids, s))) ||
+               (time_dep && (e = launch_build_tdual(gd, stage, c0, m, G->tpay, G->tdual, s))));
+    }
+    if (e || (e = hipStreamSynchronize(s))) {
+        delete G;
+        return hip_fail(e, "grid build");
     }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -433,6 +589,12 @@ int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* d
         G->num_cus = 0;
     *out = G;
     return MPATH_OK;
+}
+
+int mpath_grid_build(const mpath_grid_desc* d, const mpath_cosmo* cosmo, void* dev_ws, size_t ws_bytes,
+                     void* stream, mpath_grid** out)
+{
+    return mpath_grid_build_with_aux(d, cosmo, dev_ws, ws_bytes, nullptr, 0, stream, out);
 }
 
 int mpath_double_layer(int64_t n, const double* phi1, const double* phi2, const double* a1, const double* a2,
@@ -492,10 +654,11 @@ int mpath_grid_get_info(const mpath_grid* g, mpath_grid_info* info)
 int mpath_grid_set_values(mpath_grid* g, const float* values, void* stream)
 {
     if (!g || !values) return fail(MPATH_ERR_INVALID_ARG, "NULL argument");
+    if (!g->perm) return fail(MPATH_ERR_UNSUPPORTED, "set_values needs the grid's auxiliary tables (mpath_grid_build_with_aux)");
     g->phi_max = INFINITY;   // the new values stay on the device: no bound
     hipError_t e = launch_permute_values(g->payload, g->perm, (const float4*)values, g->n_cells,
                                          (hipStream_t)stream);
-    if (!e) e = launch_build_dual(make_griddev(g), g->cellpos, g->dual, g->n_cells, (hipStream_t)stream);
+    if (!e) e = launch_rebuild_dual(make_griddev(g), g->dual_ids, g->dual, g->n_cells, (hipStream_t)stream);
     return e ? hip_fail(e, "set_values launch") : MPATH_OK;
 }
 
@@ -966,6 +1129,8 @@ int adjoint_impl(const mpath_grid* g, const mpath_cast_desc* d, const mpath_obse
     if (ws_bytes < al.total) return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "adjoint workspace too small");
     if (ad->dL_dphi_total && !(g->max_level == 0 && g->periodic))
         return fail(MPATH_ERR_UNSUPPORTED, "dL_dphi_total needs a uniform periodic grid");
+    if ((ad->dL_dvalues || ad->dL_dphi_total) && !g->perm)
+        return fail(MPATH_ERR_UNSUPPORTED, "cell cotangents need the grid's auxiliary tables (mpath_grid_build_with_aux)");
     const bool jac = ad->jac || ad->dz_dtheta || ad->ray_status;
     const bool loss = ad->dL_dvalues || ad->dL_dphi_total;
     if (!jac && !loss) return MPATH_OK;
@@ -993,8 +1158,7 @@ int adjoint_impl(const mpath_grid* g, const mpath_cast_desc* d, const mpath_obse
     if (!e && ad->dL_dvalues)
         e = launch_scatter_grad(grad, g->perm, (float4*)ad->dL_dvalues, g->n_cells, s);
     if (!e && ad->dL_dphi_total)
-        e = launch_central_transpose(grad, g->cellpos, g->perm, ad->dL_dphi_total, g->n0,
-                                     g->box / g->n0, g->n_cells, s);
+        e = launch_central_transpose(grad, g->perm, ad->dL_dphi_total, g->n0, g->box / g->n0, g->n_cells, s);
     if (e) return hip_fail(e, "adjoint launch");
     return MPATH_OK;
 }
