@@ -51,12 +51,16 @@ class Grid:
     """An octree of Phi and grad Phi resident on the GPU (mpath_grid_build).
 
     cells: an object with box, n0, max_level, periodic, level[n] (uint8),
-    ijk[n,3] (int32), phi[n], grad[n,3] (float64 or float32 numpy arrays)
-    and optionally dphi_deta[n] (a time-dependent potential, Sect. 2.2).
+    ijk[n,3] (int32), phi[n], grad[n,3] (float64 or float32 numpy arrays;
+    grad None: the library's central differences of phi) and optionally
+    dphi_deta[n] (a time-dependent potential, Sect. 2.2).
     cosmo: (omega_m, omega_l, h); (0, 0, h) is a static background.
+    aux: also build the auxiliary tables (40 B per cell) that set_values and
+    the cell cotangents of the adjoint need; a forward-only grid
+    (aux=False) casts and differentiates per ray all the same.
     """
 
-    def __init__(self, cells, cosmo=(0.3, 0.7, 0.7), device="cuda"):
+    def __init__(self, cells, cosmo=(0.3, 0.7, 0.7), device="cuda", aux=True):
         torch = _torch()
         L = _abi.lib()
         self.device = torch.device(device)
@@ -67,7 +71,7 @@ class Grid:
         f32 = np.asarray(cells.phi).dtype == np.float32
         vt = np.float32 if f32 else np.float64
         phi = np.ascontiguousarray(cells.phi, vt)
-        grad = np.ascontiguousarray(cells.grad, vt)
+        grad = None if cells.grad is None else np.ascontiguousarray(cells.grad, vt)
         td = getattr(cells, "dphi_deta", None)
         td = None if td is None else np.ascontiguousarray(td, vt)
         if td is not None and td.shape != phi.shape:
@@ -84,18 +88,26 @@ class Grid:
         d.level = level.ctypes.data
         d.ijk = ijk.ctypes.data
         d.phi = phi.ctypes.data
-        d.grad = grad.ctypes.data
+        d.grad = None if grad is None else grad.ctypes.data
         d.dphi_deta = None if td is None else td.ctypes.data
         nbytes = C.c_size_t()
         _abi.check(L.mpath_grid_workspace_bytes(C.byref(d), C.byref(nbytes)), "mpath_grid_workspace_bytes")
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.aux = None
+        if aux:
+            abytes = C.c_size_t()
+            _abi.check(L.mpath_grid_aux_bytes(C.byref(d), C.byref(abytes)), "mpath_grid_aux_bytes")
+            self.aux = torch.empty(abytes.value, dtype=torch.uint8, device=self.device)
         cz = _abi.mpath_cosmo(*map(float, cosmo))
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            _abi.check(L.mpath_grid_build(C.byref(d), C.byref(cz), _ptr(self.ws), nbytes.value,
-                                          _stream_ptr(self.device), C.byref(h)), "mpath_grid_build")
+            _abi.check(L.mpath_grid_build_with_aux(C.byref(d), C.byref(cz), _ptr(self.ws), nbytes.value,
+                                                   None if self.aux is None else _ptr(self.aux),
+                                                   0 if self.aux is None else self.aux.numel(),
+                                                   _stream_ptr(self.device), C.byref(h)), "mpath_grid_build_with_aux")
         self._h = h
         self._keep = None
+        self.values_version = 0      # counts set_values calls
         self.cosmo = tuple(map(float, cosmo))
         info = _abi.mpath_grid_info()
         _abi.check(L.mpath_grid_get_info(self._h, C.byref(info)), "mpath_grid_get_info")
@@ -120,6 +132,7 @@ class Grid:
         values = values.contiguous()
         _abi.check(_abi.lib().mpath_grid_set_values(self._h, _ptr(values), _stream_ptr(self.device)),
                    "mpath_grid_set_values")
+        self.values_version += 1
         self._values_ref = values     # keep alive until the stream is done with it
 
     def __del__(self):
@@ -328,7 +341,11 @@ def _autograd_function():
     class CastFunction(torch.autograd.Function):
         """(alpha [n_rays, 2], z5 [n_rays]) as functions of the cell values
         [n_cells, 4] = (phi, gx, gy, gz) in the caller's order; backward runs
-        mpath_adjoint.  The grid keeps these values until the backward."""
+        mpath_adjoint, which replays the forward path on the grid's values:
+        the grid must keep these values until the backward (a set_values or
+        another cast_differentiable on the same Grid in between raises
+        there), and a ray whose replay does not retrace its forward path bit
+        for bit raises too instead of contributing nothing."""
 
         @staticmethod
         def forward(ctx, values, grid, cfg):
@@ -337,11 +354,19 @@ def _autograd_function():
             grid.set_values(values.detach().to(torch.float32))
             out = cast(grid, cfg)
             ctx.grid, ctx.cfg, ctx.out = grid, cfg, out
+            ctx.values_version = grid.values_version
             return out["alpha"].clone(), out["z5"].clone()
 
         @staticmethod
         def backward(ctx, g_alpha, g_z5):
+            if ctx.grid.values_version != ctx.values_version:
+                raise RuntimeError("cast_differentiable: the grid's cell values changed between the forward "
+                                   "and the backward (set_values or another cast_differentiable on this Grid)")
             res = adjoint(ctx.grid, ctx.cfg, ctx.out, dL_dalpha=g_alpha, dL_dz=g_z5, cells=True)
+            bad = int((res["ray_status"] == 2).sum())
+            if bad:
+                raise RuntimeError(f"cast_differentiable: {bad} rays did not retrace their forward path in the "
+                                   "reverse sweep (the cell values differ from the forward's)")
             return res["dL_dvalues"], None, None
 
     return CastFunction

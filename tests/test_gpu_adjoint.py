@@ -102,7 +102,7 @@ def test_jacobian_vs_oracle_complex_step(M, gauss64):
     A, dzo, rec = O.jacobian_cs(lambda d, t: O.cast_cs(field, c, p, d, dtheta=t), dirs)
     same = _np(out["hash"]).view(np.uint32) == rec["hash"]
     _print("rays with the oracle's decisions:", same.sum(), "of", len(same))
-    assert same.mean() > 0.95
+    assert same.all()
     dA = np.abs(jac - A)[same].reshape(-1, 4).max(1)
     lens = np.abs(A - np.eye(2)).reshape(-1, 4).max(1)
     _print("|A - I| median", np.median(lens), "max", lens.max())
@@ -241,6 +241,30 @@ def test_autograd_function(M, gauss64):
     assert np.allclose(g, g_ref, rtol=1e-5, atol=1e-6 * np.abs(g_ref).max())
 
 
+def test_autograd_stale_values_raise(M, gauss64):
+    """The backward replays the forward on the grid's values: changing them
+    between forward and backward (set_values, or a second
+    cast_differentiable on the same grid) raises instead of returning a
+    zero or partial gradient."""
+    import torch
+    grid = M.Grid(gauss64, COSMO)
+    cfg = _cfg(M, 0.2, 2, 32)
+    base = np.concatenate([gauss64.phi[:, None], gauss64.grad], 1)
+    vals = torch.tensor(base, dtype=torch.float32, device="cuda", requires_grad=True)
+    alpha, z5 = M.cast_differentiable(vals, grid, cfg)
+    loss = (alpha.double() ** 2).sum()
+    grid.set_values(torch.tensor(1.5 * base, dtype=torch.float32, device="cuda"))
+    with pytest.raises(RuntimeError, match="changed between the forward"):
+        loss.backward()
+    vals2 = torch.tensor(base, dtype=torch.float32, device="cuda", requires_grad=True)
+    a1, _ = M.cast_differentiable(vals2, grid, cfg)
+    a2, _ = M.cast_differentiable((0.5 * vals2).detach().requires_grad_(), grid, cfg)
+    with pytest.raises(RuntimeError, match="changed between the forward"):
+        (a1.double() ** 2).sum().backward()
+    # the latest one is still differentiable
+    (a2.double() ** 2).sum().backward()
+
+
 def test_amr_jacobian_vs_oracle(M):
     """Adaptive steps on a small random AMR tree (level fallback, landing)."""
     import torch
@@ -260,7 +284,7 @@ def test_amr_jacobian_vs_oracle(M):
     jac = _np(res["jac"]).astype(np.float64)
     dA = np.abs(jac - A)[same].reshape(-1, 4).max(1)
     _print("AMR: same decisions", same.sum(), "of", len(same), "|dA| max", dA.max())
-    assert same.mean() > 0.9
+    assert same.all()
     assert dA.max() < 5e-6 and np.median(dA) < 2e-7
 
 
@@ -343,10 +367,10 @@ def test_amr_deep_jacobian_vs_oracle(M):
     field = O.Field.grid(cells)
     A, dz, out = O.jacobian_cs(lambda d, t: O.cast_cs(field, O.cosmo(*COSMO), p, d, dtheta=t), dirs)
     ok = (st == 0) & (out["status"] == O.REACHED)
-    assert ok.sum() >= 44
+    assert ok.all() and (st == 0).all()
     d = np.abs(jac[ok] - A[ok]).max(axis=(1, 2))
     print("deep adjoint: max |dA|", d.max(), "median", np.median(d), flush=True)
-    assert np.median(d) < 2e-7 and (d > 5e-6).sum() <= 1
+    assert np.median(d) < 2e-7 and d.max() < 5e-6
 
 
 def _gpu_end_dirs(M, grid, z, dirs):
@@ -460,3 +484,65 @@ def test_differentiated_full_size_sampled(M):
            f"max rel dz/dtheta {rz.max():.2e}")
     assert dA.max() < 5e-6 and np.median(dA) < 2e-7
     assert rz.max() < 1e-5
+
+
+def test_differentiated_full_size_cell_gradient(M):
+    """The cell gradient of the differentiated configuration at full size
+    (2^20 rays, every lane scattering through the per-wave tables and their
+    evictions): (a) with dL/dalpha = 2 alpha on 256 seeded rays and 0 on the
+    others, <dL/dvalues, delta> along two random directions against the
+    oracle's complex-step directional derivative on those rays; (b) for
+    L = sum |alpha|^2 over all rays, the one sweep against the sum of 16
+    sweeps of 2^16 rays each: float32 atomic sums of up to 2^20 terms per
+    cell (the observer's stencil takes one from every ray) round at about
+    sqrt(2^20) 2^-24 = 6e-5 of the sum, the bar below."""
+    import torch
+    w = synth.WORKLOADS["differentiated"]
+    cells = synth.make_cells(w.grid)
+    grid = M.Grid(cells, COSMO)
+    kw = dict(steps_per_cell=w.steps_per_cell, adaptive=w.adaptive, checkpoint_every=32)
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, **kw)
+    fwd = _fwd(M, grid, cfg)
+    n = w.n_rays
+    sub = np.sort(np.random.default_rng(2028).choice(n, 256, replace=False))
+    cot = torch.zeros((n, 2), dtype=torch.float32, device="cuda")
+    sub_t = torch.from_numpy(sub).cuda()
+    cot[sub_t] = 2.0 * fwd["alpha"][sub_t]
+    res = M.adjoint(grid, cfg, fwd, dL_dalpha=cot, cells=True)
+    torch.cuda.synchronize()
+    assert (_np(res["ray_status"]) == 0).all()
+    g = _np(res["dL_dvalues"]).astype(np.float64)
+    field = O.Field.grid(cells)
+    p = O.params(w.obs[0], z_src=float(np.atleast_1d(w.z_src)[0]), steps_per_cell=w.steps_per_cell,
+                 adaptive=w.adaptive)
+    dirs = O.pix2vec_nest(w.nside, np.asarray(w.pix_first)[0] + sub)
+    a = _np(fwd["alpha"])[sub].astype(np.float64)
+    rng = np.random.default_rng(12)
+    for trial in range(2):
+        delta = rng.normal(size=(cells.n_cells, 4))
+        delta[:, 0] *= 1e-5
+        delta[:, 1:] *= 1e-5 / 7.8
+        _, tan = O.cast_cs(field, O.cosmo(*COSMO), p, dirs, dphi=delta[:, 0], dgrad=delta[:, 1:])
+        want = np.sum(2.0 * a * tan["alpha"])
+        got = np.sum(g * delta)
+        _print(f"full-size cell gradient, trial {trial}: adjoint {got:.9e} oracle {want:.9e} "
+               f"rel {abs(got - want) / abs(want):.2e}")
+        assert abs(got - want) <= 1e-5 * abs(want)
+    # (b) the whole loss in one sweep and in 16 chunks of 2^16 rays
+    full = M.adjoint(grid, cfg, fwd, dL_dalpha=2.0 * fwd["alpha"], cells=True)
+    torch.cuda.synchronize()
+    g_full = _np(full["dL_dvalues"]).astype(np.float64)
+    m = 1 << 16
+    g_sum = np.zeros_like(g_full)
+    for c in range(n // m):
+        cfg_c = M.CastConfig(w.obs, w.z_src, w.nside, [c * m], [m], **kw)
+        f_c = _fwd(M, grid, cfg_c)
+        r_c = M.adjoint(grid, cfg_c, f_c, dL_dalpha=2.0 * f_c["alpha"], cells=True)
+        torch.cuda.synchronize()
+        assert (_np(r_c["ray_status"]) == 0).all()
+        g_sum += _np(r_c["dL_dvalues"]).astype(np.float64)
+    scale = np.abs(g_full).max(axis=0)
+    err = np.abs(g_full - g_sum).max(axis=0) / scale
+    rel = np.linalg.norm(g_full - g_sum) / np.linalg.norm(g_full)
+    _print(f"one sweep vs 16 chunks: max |diff| / max |g| per component {err}, relative norm {rel:.2e}")
+    assert np.all(err < 1e-4) and rel < 1e-4

@@ -54,7 +54,7 @@ def test_amr_grid(M):
     grid = M.Grid(cells, COSMO)
     g = run_gpu(grid, M.CastConfig(obs, 0.4, 4, steps_per_cell=4, adaptive=True, dphidl="diff"))
     o = _oracle(cells, obs, 0.4, 4, 4, True)
-    _print("step-difference dPhi/dl, AMR:", compare(g, o, max_flip_frac=0.02, flip_tol_arcsec=1.0))
+    _print("step-difference dPhi/dl, AMR:", compare(g, o))
 
 
 def test_light_cone_grid(M):

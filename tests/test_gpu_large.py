@@ -6,9 +6,12 @@ oracle one by one; then the adjoint distortion matrix on a 2^20-ray chunk
 against the oracle's complex-step Jacobian on sampled rays, and of the whole
 sky in 48 such chunks.
 
-Building the tree takes a few minutes of host time and about 60 GB of host
-memory, the oracle's copy about 40 GB more, the device image about 100 GB of
-HBM; the tests run when MPATH_TEST_LARGE=1 is set."""
+Measured on the GPU host: drawing the tree takes 80 s and about 60 GB of
+host memory, the oracle's copy 95 s and about 40 GB more, the device image
+(forward-only, without the auxiliary tables) about 70 GB of HBM; the
+sampled tests take about 4 minutes in all.  They are skipped only on a host
+with less than 120 GiB of available memory.  The full-sky adjoint (48
+chunks, about a minute more) runs when MPATH_TEST_LARGE_FULL_SKY=1 is set."""
 import os
 import time
 
@@ -19,10 +22,25 @@ import oracle as O
 import synth
 from parity import compare
 
+NEED_GIB = 120
+
+
+def _available_gib():
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) / 2 ** 20
+    except OSError:
+        pass
+    return 0.0
+
+
 pytestmark = [
     pytest.mark.gpu,
-    pytest.mark.skipif(os.environ.get("MPATH_TEST_LARGE") != "1",
-                       reason="the 4e8-cell tree needs minutes and ~100 GB of host memory: set MPATH_TEST_LARGE=1"),
+    pytest.mark.skipif(_available_gib() < NEED_GIB,
+                       reason=f"the 4e8-cell tree and the oracle's copy need about {NEED_GIB} GiB of host memory "
+                              f"(measured: 60 + 40 GB); {_available_gib():.0f} GiB available"),
 ]
 
 COSMO = (0.3, 0.7, 0.7)
@@ -55,8 +73,8 @@ def large():
 def grid(M, large):
     _, cells = large
     t = time.time()
-    g = M.Grid(cells, COSMO)
-    _print(f"device grid built in {time.time() - t:.1f} s")
+    g = M.Grid(cells, COSMO, aux=False)
+    _print(f"device grid built in {time.time() - t:.1f} s ({g.ws.numel() / 1e9:.1f} GB)")
     return g
 
 
@@ -108,7 +126,7 @@ def test_large_full_sky_sampled(M, large, grid, field):
     o = _oracle(field, w, idx)
     _print(f"oracle: {len(idx)} rays in {time.time() - t:.0f} s; most steps {g['n_steps'][most].min()}.."
            f"{g['n_steps'][most].max()}")
-    _print(compare(g, o, idx=idx, max_flip_frac=0.02, flip_tol_arcsec=1.0))
+    _print(compare(g, o, idx=idx))
 
 
 def _oracle(field, w, idx, max_steps=1 << 40):
@@ -141,7 +159,7 @@ def test_large_adjoint_jacobian_sampled(M, large, grid, field):
     jac = res["jac"].cpu().numpy().astype(np.float64)
     _print(f"adjoint chunk: {n} rays, {int(nst.astype(np.int64).sum())} ray-steps; checkpointed forward "
            f"{(t1 - t) * 1e3:.0f} ms, reverse sweep {(t2 - t1) * 1e3:.0f} ms; not differentiated {(st != 0).sum()}")
-    assert (st == 0).mean() > 0.999
+    assert (st == 0).all()
     rng = np.random.default_rng(2027)
     idx = np.unique(np.concatenate([np.argsort(nst)[-12:], rng.choice(n, 12, replace=False)]))
     dirs = O.pix2vec_nest(w.nside, idx)
@@ -153,10 +171,12 @@ def test_large_adjoint_jacobian_sampled(M, large, grid, field):
     d = np.abs(jac[idx][ok] - A[ok]).max(axis=(1, 2))
     _print(f"oracle complex-step Jacobian of {len(idx)} rays in {time.time() - t:.0f} s; steps "
            f"{nst[idx].min()}..{nst[idx].max()}; max |dA| {d.max():.3g}, median {np.median(d):.3g}")
-    assert ok.sum() >= len(idx) - 1
-    assert np.median(d) < 1e-6 and (d > 2e-5).sum() <= 1
+    assert ok.all()
+    assert np.median(d) < 1e-6 and d.max() < 5e-6
 
 
+@pytest.mark.skipif(os.environ.get("MPATH_TEST_LARGE_FULL_SKY") != "1",
+                    reason="the full-sky adjoint (48 chunks) runs with MPATH_TEST_LARGE_FULL_SKY=1")
 def test_large_full_sky_adjoint(M, large, grid):
     """The distortion matrix of every ray of the full sky: 48 chunks of 2^20
     NESTED pixels, each a checkpointed cast and a reverse sweep; every ray

@@ -53,7 +53,7 @@ def test_amr_orders_match_oracle(M, order):
     _print("order", order, "amr halo small, nside 8, z = 0.4")
     g = run_gpu(grid, cfg)
     o = run_oracle(O.Field.grid(cells, order=order), O.cosmo(*COSMO), obs, 0.4, 8, [0], [768], 4, True)
-    _print(compare(g, o, max_flip_frac=0.02, flip_tol_arcsec=1.0))
+    _print(compare(g, o))
 
 
 def test_orders_finite_beam_and_unsupported_paths(M):

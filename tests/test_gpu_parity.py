@@ -87,7 +87,7 @@ def test_amr_small_adaptive(M, name, seed):
     cfg = M.CastConfig(obs, 0.3, 8, steps_per_cell=4, adaptive=True)
     g = run_gpu(grid, cfg)
     o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), obs, 0.3, 8, [0], [768], 4, True)
-    s = compare(g, o, max_flip_frac=0.02, flip_tol_arcsec=1.0)
+    s = compare(g, o)
     _print(s)
     assert (o["n_steps"] > 400).all()          # about chi / (h0 / N) steps or more
 
@@ -100,7 +100,7 @@ def test_amr_halo_small(M):
     cfg = M.CastConfig(obs, 0.4, 8, steps_per_cell=4, adaptive=True)
     g = run_gpu(grid, cfg)
     o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), obs, 0.4, 8, [0], [768], 4, True)
-    s = compare(g, o, max_flip_frac=0.02, flip_tol_arcsec=1.0)
+    s = compare(g, o)
     _print(s)
 
 
@@ -122,7 +122,7 @@ def test_non_periodic_leaves_domain(M):
     g = run_gpu(grid, cfg)
     o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), obs, 0.2, 4, [0], [192], 4, True)
     assert np.all(o["status"] == O.LEFT_DOMAIN)
-    s = compare(g, o, max_flip_frac=0.02)
+    s = compare(g, o)
     assert np.array_equal(g["n_steps"], o["n_steps"])
     assert np.all(np.isnan(g["z5"]))
     _print(s)
@@ -136,6 +136,39 @@ def test_max_steps(M, gauss64):
                    max_steps=100)
     assert np.all(g["status"] == M.MPATH_RAY_MAX_STEPS) and np.all(g["n_steps"] == 100)
     compare(g, o)
+
+
+def test_nonfinite_cell(M):
+    """A NaN in one cell's gradient stops the rays whose stencils meet it with
+    status NONFINITE, in the same step as the oracle; a NaN potential in the
+    observer's stencil stops every ray in its first step.  Every other ray
+    agrees with the oracle at the parity bar.  (Every lookup of the cast
+    masks or bounds-checks its cell indices, so the NaN positions inside the
+    failing step read valid cells.)"""
+    import copy
+    cells = synth.make_cells("gauss32")
+    obs = [125.0, 125.0, 125.0]
+    for ijk, field, hit_all in (((18, 16, 16), "grad", False), ((16, 16, 16), "phi", True)):
+        c = copy.deepcopy(cells)
+        i = (ijk[0] * 32 + ijk[1]) * 32 + ijk[2]
+        if field == "phi":
+            c.phi[i] = np.nan
+        else:
+            c.grad[i, 1] = np.nan
+        _print("NaN", field, "at cell", ijk)
+        grid = M.Grid(c, COSMO)
+        cfg = M.CastConfig(obs, 0.2, 4, steps_per_cell=4)
+        g = run_gpu(grid, cfg)
+        o = run_oracle(O.Field.grid(c), O.cosmo(*COSMO), obs, 0.2, 4, [0], [192], 4, False)
+        assert np.array_equal(g["status"], o["status"])
+        assert np.array_equal(g["n_steps"], o["n_steps"])
+        hit = o["status"] == O.NONFINITE
+        if hit_all:
+            assert hit.all() and np.all(g["n_steps"] == 0)
+        else:
+            assert 0 < hit.sum() < len(hit) // 2
+            ok = np.nonzero(~hit)[0]
+            _print(compare(g, o[ok], idx=ok))
 
 
 def test_static_background_chi_stop(M):
@@ -192,7 +225,9 @@ def test_invalid_arguments_raise(M, gauss64):
 def test_amr128_full_size_sampled(M):
     """The benchmark configuration itself: AMR 128^3 + 3 levels (10,035,832
     cells), all 786,432 rays (nside 256) to z = 1 in the launch the benchmark
-    times; 384 seeded random rays recomputed by the oracle one by one."""
+    times; 384 seeded random rays, the 32 rays with the most steps (the
+    deepest and longest paths through refined haloes) and the 32 most
+    deflected, recomputed by the oracle one by one."""
     w = synth.WORKLOADS["amr"]
     cells = synth.make_cells(w.grid)
     _print("amr128 cells", cells.n_cells)
@@ -201,10 +236,14 @@ def test_amr128_full_size_sampled(M):
                        adaptive=w.adaptive)
     g = run_gpu(grid, cfg)
     assert np.all(g["status"] == M.MPATH_RAY_REACHED)
-    idx = np.sort(np.random.default_rng(2024).choice(w.n_rays, 384, replace=False))
+    most = np.argsort(g["n_steps"], kind="stable")[-32:]
+    bent = np.argsort(np.hypot(g["alpha"][:, 0], g["alpha"][:, 1]), kind="stable")[-32:]
+    idx = np.unique(np.concatenate([np.random.default_rng(2024).choice(w.n_rays, 384, replace=False), most, bent]))
+    _print("steps of the most-step rays", g["n_steps"][most].min(), "..", g["n_steps"].max(),
+           "; median", int(np.median(g["n_steps"])))
     o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), w.obs, w.z_src, w.nside, w.pix_first, w.pix_count,
                    w.steps_per_cell, w.adaptive, ray_index=idx)
-    s = compare(g, o, idx=idx, max_flip_frac=0.02, flip_tol_arcsec=1.0)
+    s = compare(g, o, idx=idx)
     _print(s)
 
 
@@ -240,7 +279,7 @@ def test_amr_deep_five_levels(M):
     cfg = M.CastConfig(obs, 0.5, 8, steps_per_cell=4, adaptive=True)
     g = run_gpu(grid, cfg)
     o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), obs, 0.5, 8, [0], [768], 4, True)
-    _print(compare(g, o, max_flip_frac=0.02, flip_tol_arcsec=1.0))
+    _print(compare(g, o))
     coarse_only = 1322.038 / (500.0 / 64) * 4
     assert g["n_steps"].max() > 1.2 * coarse_only        # some rays cross the refined haloes
 
@@ -267,3 +306,99 @@ def test_batched_full_size_sampled(M):
     o = run_oracle(O.Field.grid(cells), O.cosmo(*COSMO), w.obs, w.z_src, w.nside, w.pix_first, w.pix_count,
                    w.steps_per_cell, w.adaptive, ray_index=idx)
     _print(compare(g, o, idx=idx))
+
+
+def _payload(grid):
+    """The packed (phi, gx, gy, gz) float32 of every cell, library order."""
+    import torch
+    torch.cuda.synchronize()
+    return grid.ws[: 16 * grid.n_cells].view(torch.float32).reshape(-1, 4).cpu().numpy()
+
+
+def _tree_central_gradient(cells):
+    """The gradient rule of a grid built with grad = NULL, written out per
+    cell: central differences of phi between the two same-level neighbours
+    (periodic wrap), one-sided where one of them is missing, 0 where both are."""
+    where = {(int(l), int(i), int(j), int(k)): c
+             for c, (l, (i, j, k)) in enumerate(zip(cells.level, cells.ijk))}
+    g = np.zeros((cells.n_cells, 3))
+    for c in range(cells.n_cells):
+        l = int(cells.level[c])
+        m = cells.n0 << l
+        h = cells.box / m
+        for a in range(3):
+            e = np.eye(3, dtype=np.int64)[a]
+
+            def nb(sign):
+                q = cells.ijk[c].astype(np.int64) + sign * e
+                if cells.periodic:
+                    q %= m
+                elif np.any(q < 0) or np.any(q >= m):
+                    return None
+                return where.get((l, *map(int, q)))
+            cp, cm = nb(1), nb(-1)
+            if cp is not None and cm is not None:
+                g[c, a] = (cells.phi[cp] - cells.phi[cm]) / (2.0 * h)
+            elif cp is not None:
+                g[c, a] = (cells.phi[cp] - cells.phi[c]) / h
+            elif cm is not None:
+                g[c, a] = (cells.phi[c] - cells.phi[cm]) / h
+    return g
+
+
+def test_grad_null_uniform(M, gauss64):
+    """grad = NULL on a uniform periodic grid: the library's central
+    differences equal synth.central_gradient bit for bit (the float32
+    payload), and so do the casts."""
+    import copy
+    c1 = copy.deepcopy(gauss64)
+    c1.grad = None
+    g0, g1 = M.Grid(gauss64, COSMO), M.Grid(c1, COSMO)
+    assert np.array_equal(_payload(g0), _payload(g1))
+    cfg = M.CastConfig([250.0, 250.0, 250.0], 0.5, 8, steps_per_cell=10)
+    r0, r1 = run_gpu(g0, cfg), run_gpu(g1, cfg)
+    for k in ("beta", "z5", "alpha", "n_steps", "hash", "status"):
+        assert np.array_equal(r0[k], r1[k]), k
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_grad_null_tree(M, periodic):
+    """grad = NULL on a three-level tree (periodic and not): every cell's
+    gradient follows the stated rule per level, and the casts equal those of
+    a grid given these gradients."""
+    import copy
+    cells = synth.random_amr_cells(16, 125.0, 3, seed=5, periodic=periodic)
+    ref = copy.deepcopy(cells)
+    ref.grad = _tree_central_gradient(cells)
+    c1 = copy.deepcopy(cells)
+    c1.grad = None
+    g0, g1 = M.Grid(ref, COSMO), M.Grid(c1, COSMO)
+    p0, p1 = _payload(g0), _payload(g1)
+    assert np.array_equal(p0, p1)
+    obs = [60.0, 62.0, 58.0]
+    cfg = M.CastConfig(obs, 0.02, 4, steps_per_cell=4, adaptive=True)
+    r0, r1 = run_gpu(g0, cfg), run_gpu(g1, cfg)
+    for k in ("beta", "z5", "n_steps", "hash", "status"):
+        # rays that leave the non-periodic box carry NaN observables
+        assert np.array_equal(r0[k], r1[k], equal_nan=k in ("beta", "z5")), k
+
+
+def test_forward_only_grid(M, gauss64):
+    """A grid without its auxiliary tables (aux=False: 40 B per cell less)
+    casts bit for bit like the full grid and gives the same distortion
+    matrices; the calls that need the tables refuse with UNSUPPORTED."""
+    import torch
+    from paper_2111_08744_amd import _abi
+    g_full, g_fwd = M.Grid(gauss64, COSMO), M.Grid(gauss64, COSMO, aux=False)
+    assert g_fwd.aux is None and g_full.aux is not None
+    cfg = M.CastConfig([250.0, 250.0, 250.0], 0.3, 4, steps_per_cell=10, checkpoint_every=32)
+    o_full, o_fwd = M.cast(g_full, cfg), M.cast(g_fwd, cfg)
+    for k in ("beta", "z5", "n_steps", "hash"):
+        assert torch.equal(o_full[k], o_fwd[k]), k
+    j_full = M.adjoint(g_full, cfg, o_full, jacobian=True)["jac"]
+    j_fwd = M.adjoint(g_fwd, cfg, o_fwd, jacobian=True)["jac"]
+    assert torch.equal(j_full, j_fwd)
+    with pytest.raises(_abi.MpathError, match="auxiliary"):
+        M.adjoint(g_fwd, cfg, o_fwd, dL_dalpha=2.0 * o_fwd["alpha"], cells=True)
+    with pytest.raises(_abi.MpathError, match="auxiliary"):
+        g_fwd.set_values(torch.zeros((g_fwd.n_cells, 4), dtype=torch.float32, device="cuda"))

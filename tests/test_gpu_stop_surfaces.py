@@ -63,7 +63,7 @@ def test_amr_surfaces(M, name):
     grid = M.Grid(cells, COSMO)
     g = run_gpu(grid, M.CastConfig(obs, 0.3, 4, steps_per_cell=4, adaptive=True, stop_surface=name))
     o = _oracle(cells, obs, 0.3, 4, 4, True, SURF[name])
-    _print(f"iso-{name} AMR:", compare(g, o, max_flip_frac=0.02, flip_tol_arcsec=1.0, z0_own=True))
+    _print(f"iso-{name} AMR:", compare(g, o, z0_own=True))
 
 
 def test_finite_beam_on_chi_surface(M):
