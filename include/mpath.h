@@ -342,6 +342,23 @@ int mpath_cast_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* de
 int mpath_cast(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observables* out,
                void* dev_ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * mpath_cast with its workspace taken from a static device buffer of
+ * MPATH_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, which the library holds until
+ * the process ends; the caller still passes the grid, the desc and the
+ * output arrays.  Plain casts only: checkpoint_every must be 0
+ * (MPATH_ERR_UNSUPPORTED otherwise), and the workspace that
+ * mpath_cast_workspace_bytes reports for the desc must fit the buffer (about
+ * 48 B per ray and surface plus 80 B per observer: up to about 1.3 million
+ * rays with one surface), else MPATH_ERR_WORKSPACE_TOO_SMALL before any
+ * device work.  Calls no allocating routine.  Every call on one GPU uses
+ * the same buffer: calls that overlap in time on one GPU (several streams
+ * or host threads) race and must be serialised by the caller; a call's
+ * outputs do not depend on what an earlier call left in the buffer. */
+#define MPATH_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mpath_cast_noalloc(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observables* out, void* stream);
+
 /* ---- reverse mode ----
  * The derivative of the discrete map that mpath_cast computes (RK4 on the
  * geodesic equations of Sect. 2.2 with CIC interpolation and the AMR level

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -1039,12 +1040,62 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
 
 }  // namespace
 
+// Workspace of mpath_cast_noalloc: one static buffer per GPU, which the
+// loader places in each device's memory with the code object.  Host code
+// never uses its name as a device address: the address comes from
+// hipGetSymbolAddress, once per device, at the first call there.
+static __device__ __align__(256) unsigned char scratch[MPATH_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+int scratch_for_current_device(void** ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MPATH_ERR_UNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e || !p) return hip_fail(e ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return MPATH_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mpath_cast(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* dev_ws,
                size_t ws_bytes, void* stream)
 {
     return cast_impl(g, d, out, dev_ws, ws_bytes, stream, false, nullptr);
+}
+
+int mpath_cast_noalloc(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* stream)
+{
+    int64_t n_rays;
+    std::vector<ObsDev> obs;
+    CastLayout lay;
+    int rc = cast_plan(g, d, &n_rays, obs, &lay);
+    if (rc) return rc;
+    if (d->checkpoint_every != 0)
+        return fail(MPATH_ERR_UNSUPPORTED, "mpath_cast_noalloc stores no checkpoints (checkpoint_every 0)");
+    if (lay.total > (size_t)MPATH_NOALLOC_SCRATCH_BYTES)
+        return fail(MPATH_ERR_WORKSPACE_TOO_SMALL,
+                    "the cast needs " + std::to_string(lay.total) + " bytes of workspace, above the " +
+                        std::to_string((size_t)MPATH_NOALLOC_SCRATCH_BYTES) + " of the static buffer");
+    void* ws = nullptr;
+    rc = scratch_for_current_device(&ws);
+    if (rc) return rc;
+    return cast_impl(g, d, out, ws, (size_t)MPATH_NOALLOC_SCRATCH_BYTES, stream, false, nullptr);
 }
 
 int mpath_born_beam(const mpath_grid* g, const mpath_cast_desc* d, float* A, int32_t* status, void* dev_ws,
