@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark: backward null-geodesic ray tracing through an AMR octree on one MI355X.
 
-Default workload (one "step" = one full cast of every ray):
-  AMR grid: 128^3 coarse cells + 3 refinement levels (box 500 Mpc/h, Gaussian
-  potential P(k) ~ k^-3 with rms 1e-5 plus 200 truncated NFW-like haloes,
-  refined where the density exceeds 8x the mean; 10,035,832 cells, float32
-  Phi + grad Phi on the GPU); observer at the box centre; 786,432 rays
-  (HEALPix NESTED nside 256, full sky) to z = 1; 4 RK4 steps per leaf cell.
+Default workload (one "step" = one full cast of every ray): the 512^3 + 5
+level light cone, the largest configuration that one GPU holds: 512^3 coarse
+cells + 5 refinement levels (box 2000 Mpc/h, Gaussian potential
+P(k) ~ k^-3 with rms 1e-5 plus 1,900 truncated NFW-like haloes, 950 of them
+within 400 Mpc/h of the observer; 407,828,120 cells, float32 Phi + grad Phi
+on the GPU); observer at the box centre; the full sky at HEALPix NESTED
+nside 2048 (50,331,648 rays) to z = 2; 4 RK4 steps per leaf cell.
 
 Prints one JSON line: ray-steps/s (value), rays/s, the roofline of the cast
-kernel and the FP64 CPU oracle's rate on a bounded sample of the same rays.
+kernel (random-gather bound: algorithmic stencil bytes per ray-step over the
+kernel time, against HBM and against the measured random-gather ceiling at
+the grid image's footprint), the targets with pass/fail, secondary workloads
+(AMR 128^3 + 3 levels, adjoint, batched launch, lensing products, finder,
+orders, variants) and the FP64 CPU oracle's rate on a bounded sample of the
+same rays.
 
-    python bench.py [--steps K] [--warmup W] [--workload amr|uniform|batched]
+    python bench.py [--steps K] [--warmup W] [--workload large|amr|uniform|batched]
 """
 from __future__ import annotations
 
@@ -32,13 +38,30 @@ sys.path.insert(0, ROOT)
 # right-hand side), counted as floating-point operations with a fused
 # multiply-add = 2: ~560 FP32 + ~20 FP64.
 FLOPS_PER_RAY_STEP = 580.0
-# Peak for this kernel: vector FMA on 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
-# Packed FP32 is disabled, so FP32 and FP64 issue at the same rate.
-PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
-# Unique table bytes one ray-step needs with perfect stencil reuse: a new CIC
-# stencil brings 4 new cells of 16 bytes about (|n_x|+|n_y|+|n_z|)/N times per
-# step (N steps per cell; 1.5 on average over directions).
-ALGO_BYTES_PER_RAY_STEP = {"amr": 64 * 1.5 / 4, "uniform": 64 * 1.5 / 10, "batched": 64 * 1.5 / 10}
+# Published FP32 vector peak of the MI355X (packed FP32: 256 CUs x 128
+# lanes x 2 flops x 2.4 GHz) and the issue rate of unpacked FP32 and FP64
+# vector FMAs, which is what this kernel uses (packed FP32 is disabled).
+PEAK_FP32_TFLOPS = 157.3
+ISSUE_RATE_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Peak HBM bandwidth of the MI355X.
+PEAK_HBM_GBS = 8000.0
+
+
+def algo_bytes_per_ray_step(steps_per_cell):
+    """Unique table bytes one ray-step needs with perfect stencil reuse: a
+    new CIC stencil brings 4 new cells of 16 bytes, at most
+    (|n_x|+|n_y|+|n_z|)/N <= sqrt(3)/N times per step (N steps per cell)."""
+    return 64.0 * 3 ** 0.5 / steps_per_cell
+
+
+WORKLOAD_TEXT = {
+    "large": "512^3 coarse + 5 levels (box 2000 Mpc/h, 407,828,120 cells), full sky nside 2048 "
+             "(50,331,648 rays) to z = 2, 4 steps per leaf cell",
+    "amr": "AMR 128^3 coarse + 3 levels (box 500 Mpc/h, 10,035,832 cells), 786,432 rays (nside 256) to z = 1, "
+           "4 steps per leaf cell",
+    "uniform": "uniform 64^3, 3072 rays (nside 16) to z = 0.5, 10 steps per cell",
+    "batched": "64 cones x 16384 rays on the 64^3 grid, z_src in [0.1, 2]",
+}
 
 
 def log(*a):
@@ -48,8 +71,29 @@ def log(*a):
 def workload(name):
     import synth
     w = synth.WORKLOADS[name]
-    cells = synth.make_cells(w.grid)
+    cells = synth.make_cells(w.grid, log=lambda m: log("[bench] grid:", m))
     return w, cells
+
+
+def host_cores():
+    """(threads the oracle may use, nproc, CPU model): the CPUs this process
+    may run on, capped by OMP_NUM_THREADS as nproc does."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, n, model
 
 
 # Sources the forward integration kernel and its launch are built from (the
@@ -101,10 +145,11 @@ def cpu_baseline(w, cells, sample_stride, threads):
             "rays_per_s": len(pix) / dt}
 
 
-def cpu_table1(w, cells):
+def cpu_table1():
     """The oracle's single-thread time per ray-step for the interpolation
     modes of the paper's timing table (FLRW without lookups, NGP, CIC, TSC on
-    the uniform 64^3 grid; CIC on the AMR grid), on a few rays each."""
+    the uniform 64^3 grid; CIC on the AMR 128^3 + 3 levels grid), on a few
+    rays each."""
     import oracle as O
     import synth
     c = O.cosmo(0.3, 0.7, 0.7)
@@ -123,8 +168,9 @@ def cpu_table1(w, cells):
     for order, name in ((0, "ngp"), (1, "cic"), (2, "tsc")):
         res[f"uniform_{name}"] = per_step(O.Field.grid(g64, order=order),
                                           O.params(obs, z_src=0.5, steps_per_cell=10), dirs)
-    res["amr_cic"] = per_step(O.Field.grid(cells), O.params(w.obs[0], z_src=float(w.z_src[0]), steps_per_cell=4,
-                                                            adaptive=True), dirs[:8])
+    w = synth.WORKLOADS["amr"]
+    res["amr_cic"] = per_step(O.Field.grid(synth.make_cells(w.grid)),
+                              O.params(w.obs[0], z_src=float(w.z_src[0]), steps_per_cell=4, adaptive=True), dirs[:8])
     return {"us_per_ray_step": res, "threads": 1,
             "paper_table1_us_per_step": {"flrw": 0.55, "ngp": 1.10, "cic": 6.0, "tsc": 14.6},
             "paper_hardware": "one core of an Intel Xeon Platinum 8168"}
@@ -381,22 +427,91 @@ def measure_orders(M, torch, dev):
     return res
 
 
+def time_casts(M, torch, grid, cfg, out, steps, warmup, label):
+    """warmup untimed casts, then steps casts each bracketed by HIP events on
+    the stream the library launches on (torch's current stream); returns
+    (wall seconds of the timed region, per-launch event milliseconds)."""
+    dev = grid.device
+    ws = None
+    for _ in range(warmup):
+        ws = M.cast(grid, cfg, out, ws)["_ws"]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        ws = M.cast(grid, cfg, out, ws)["_ws"]
+        evs[i][1].record(stream)
+        if steps > 4 and (i + 1) % 5 == 0:
+            log(f"[bench] {label}: {i + 1} of {steps} timed casts queued")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in evs]
+
+
+def roofline(w, ray_steps, launch_ms, traffic, ceiling_gbs=None):
+    """Random-gather roofline of the cast kernel: algorithmic stencil bytes
+    per launch over the mean launch time, against peak HBM bandwidth and
+    against the measured random-gather ceiling; the ALU view beside it."""
+    kern_s = float(np.mean(launch_ms)) / 1e3
+    algo = algo_bytes_per_ray_step(w.steps_per_cell)
+    achieved = algo * ray_steps / kern_s / 1e9
+    flops = FLOPS_PER_RAY_STEP * ray_steps / kern_s / 1e12
+    r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+         "traffic": traffic, "kernel": "cast_static_kernel", "launch_ms_mean": float(np.mean(launch_ms)),
+         "algorithmic_bytes_per_ray_step": algo, "ray_steps_per_launch": ray_steps,
+         "algorithmic_bytes_per_launch": algo * ray_steps,
+         "alu_view": {"achieved_TFLOP_s": flops, "flops_per_ray_step": FLOPS_PER_RAY_STEP,
+                      "peak_fp32_TFLOP_s": PEAK_FP32_TFLOPS, "frac_of_peak_fp32": flops / PEAK_FP32_TFLOPS,
+                      "unpacked_issue_rate_TFLOP_s": ISSUE_RATE_TFLOPS,
+                      "frac_of_unpacked_issue_rate": flops / ISSUE_RATE_TFLOPS}}
+    if traffic is not None:
+        r["hbm_bytes_per_ray_step"] = traffic / ray_steps
+        r["hbm_GB_per_s"] = traffic / kern_s / 1e9
+    if ceiling_gbs is not None:
+        r["measured_gather_ceiling_GB_per_s"] = ceiling_gbs
+        r["frac_of_measured_gather_ceiling"] = achieved / ceiling_gbs
+    return r
+
+
+def measure_secondary_amr(M, torch, dev, steps):
+    """The AMR 128^3 + 3 levels workload (786,432 rays to z = 1) as a
+    secondary line, with its own gather roofline."""
+    w, cells = workload("amr")
+    grid = M.Grid(cells, (0.3, 0.7, 0.7), device=dev, aux=False)
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, steps_per_cell=w.steps_per_cell,
+                       adaptive=w.adaptive)
+    out = M.alloc_outputs(cfg.n_rays(), dev)
+    wall, ms = time_casts(M, torch, grid, cfg, out, steps, 1, "amr")
+    ray_steps = int(out["n_steps"].to(torch.int64).sum())
+    res = {"workload": WORKLOAD_TEXT["amr"], "cells": int(cells.n_cells), "rays": cfg.n_rays(),
+           "ray_steps_per_cast": ray_steps, "ray_steps_per_s": ray_steps * steps / wall,
+           "rays_per_s": cfg.n_rays() * steps / wall, "ms_per_cast": wall * 1e3 / steps,
+           "roofline": roofline(w, ray_steps, ms, traffic_from_profiles("amr"))}
+    res["ray_order"] = measure_ray_order(M, torch, dev, grid, w)
+    log(f"[bench] amr: {res['ray_steps_per_s'] / 1e9:.2f} G ray-steps/s, {res['ms_per_cast']:.2f} ms per cast")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="amr")
+    ap.add_argument("--workload", default="large")
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the adjoint and batched-launch measurements")
+                    help="skip the secondary workloads (AMR 128^3, adjoint, batched launch, products)")
     ap.add_argument("--no-gather-probe", action="store_true",
                     help="skip the random-gather ceiling measurement")
-    ap.add_argument("--cpu-stride", type=int, default=48)
+    ap.add_argument("--cpu-stride", type=int, default=0,
+                    help="oracle on every n-th NESTED pixel (default: 16,384 rays of the workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the casts, copy MIB mebibytes once with a plain device copy "
                          "(reference for the HBM byte counters)")
@@ -420,33 +535,17 @@ def main():
         f"generated in {t_gen:.1f} s")
     torch.cuda.synchronize()
     t0 = time.time()
-    grid = M.Grid(cells, (0.3, 0.7, 0.7), device=dev)
+    grid = M.Grid(cells, (0.3, 0.7, 0.7), device=dev, aux=False)
     torch.cuda.synchronize()
     t_build = time.time() - t0
-    log(f"[bench] grid build {t_build:.2f} s, cells per level {grid.cells_per_level}")
+    log(f"[bench] grid build {t_build:.2f} s ({grid.ws.numel() / 1e9:.1f} GB), cells per level "
+        f"{grid.cells_per_level}")
     cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, steps_per_cell=w.steps_per_cell,
                        adaptive=w.adaptive, schedule=args.schedule, block_size=args.block,
                        waves_per_cu=args.waves_per_cu, batch=args.batch)
     n_rays = cfg.n_rays()
     out = M.alloc_outputs(n_rays, dev)
-    ws = None
-    for i in range(args.warmup):
-        r = M.cast(grid, cfg, out, ws)
-        ws = r["_ws"]
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream(dev)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        evs[i][0].record(stream)
-        r = M.cast(grid, cfg, out, ws)
-        ws = r["_ws"]
-        evs[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = [a.elapsed_time(b) for a, b in evs]
+    wall, launch_ms = time_casts(M, torch, grid, cfg, out, args.steps, args.warmup, w.name)
     # every cast integrates the same rays: count the work from the last one
     n_steps = out["n_steps"].to(torch.int64)
     ray_steps = int(n_steps.sum().item())
@@ -455,8 +554,6 @@ def main():
         f"min {int(n_steps.min())} mean {ray_steps / n_rays:.1f} max {int(n_steps.max())}")
     ms_per_step = wall * 1e3 / args.steps
     value = ray_steps * args.steps / wall
-    kern_s = float(np.mean(launch_ms)) / 1e3
-    achieved = FLOPS_PER_RAY_STEP * ray_steps / kern_s / 1e12
     log(f"[bench] {args.steps} casts in {wall:.3f} s: {value / 1e9:.2f} G ray-steps/s, "
         f"launch mean {np.mean(launch_ms):.2f} ms (min {np.min(launch_ms):.2f}, max {np.max(launch_ms):.2f})")
 
@@ -468,8 +565,18 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {nbytes} bytes copied")
+        del src, dst
 
-    traffic = traffic_from_profiles(w.name)
+    ceiling = None
+    probe = None
+    if not args.no_gather_probe:
+        probe = measure_gather_ceiling(M, torch, grid.ws, dev)
+        ceiling = max(b["GB_per_s"] for b in probe.values())
+    roof = roofline(w, ray_steps, launch_ms, traffic_from_profiles(w.name), ceiling)
+    if probe is not None:
+        roof["gather_probe"] = {"table_bytes": int(grid.ws.numel()), "best_per_record_bytes":
+                                {str(r): b for r, b in probe.items()},
+                                "kind": "uniform random record gathers over a table the size of the grid image"}
     res = {
         "metric": "ray-steps/sec + rays/sec to z_src at 1 GPU; adjoint/forward cost ratio",
         "value": value,
@@ -484,51 +591,45 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": {"amr": "AMR 128^3 coarse + 3 levels, 786432 rays (nside 256) to z = 1, "
-                                "4 steps per leaf cell",
-                         "uniform": "uniform 64^3, 3072 rays (nside 16) to z = 0.5, 10 steps per cell",
-                         "batched": "64 cones x 16384 rays on the 64^3 grid, z_src in [0.1, 2]"}.get(w.name, w.name),
+            "workload": WORKLOAD_TEXT.get(w.name, w.name),
             "cells": int(cells.n_cells), "rays": n_rays, "ray_steps_per_cast": ray_steps,
             "steps_per_cell": w.steps_per_cell, "adaptive": bool(w.adaptive),
         },
         "rays_per_s": n_rays * args.steps / wall,
         "adjoint_forward_ratio": None,
+        "grid_generate_s": t_gen,
         "grid_build_s": t_build,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "cast_kernel",
-                     "launch_ms_mean": float(np.mean(launch_ms))},
+        "grid_device_bytes": int(grid.ws.numel()),
+        "roofline": roof,
     }
-    if not args.no_gather_probe:
-        best = measure_gather_ceiling(M, torch, grid.ws, dev)
-        peak = best[128]["GB_per_s"]
-        hbm = traffic / (kern_s * 1e9) if traffic is not None else None
-        res["gather_roofline"] = {
-            "kernel": "cast_kernel", "unit": "GB/s",
-            "achieved": hbm, "peak": peak, "frac": hbm / peak if hbm is not None else None,
-            "peak_kind": "measured: uniform random 128-byte record gathers over a table of the grid image's size",
-            "achieved_kind": "HBM bytes per launch from FETCH_SIZE + WRITE_SIZE counters / mean launch time",
-            "table_bytes": int(grid.ws.numel()),
-            "probe_best": {str(r): b for r, b in best.items()},
-            "hbm_bytes_per_ray_step": traffic / ray_steps if traffic is not None else None,
-            "algorithmic_bytes_per_ray_step": ALGO_BYTES_PER_RAY_STEP.get(w.name),
-        }
+    del grid, out
+    torch.cuda.empty_cache()
     if not args.no_secondary:
-        sec = {"ray_order": measure_ray_order(M, torch, dev, grid, w)} if w.name == "amr" else {}
+        sec = {"amr": measure_secondary_amr(M, torch, dev, 5)}
         sec.update({"adjoint": measure_adjoint(M, torch, dev), "batched": measure_batched(M, torch, dev),
-               "lensing": measure_lensing(M, torch, dev), "finder": measure_finder(M, torch, dev),
-               "orders": measure_orders(M, torch, dev), "variants": measure_variants(M, torch, dev)})
+                    "lensing": measure_lensing(M, torch, dev), "finder": measure_finder(M, torch, dev),
+                    "orders": measure_orders(M, torch, dev), "variants": measure_variants(M, torch, dev)})
         res["secondary"] = sec
         res["adjoint_forward_ratio"] = sec["adjoint"]["adjoint_forward_ratio"]
+    targets = {}
+    if ceiling is not None:
+        f = roof["frac_of_measured_gather_ceiling"]
+        targets["forward_ge_0.6_of_measured_gather_ceiling"] = {"value": f, "pass": f >= 0.6}
+    if "secondary" in res:
+        r = res["adjoint_forward_ratio"]
+        targets["adjoint_le_3x_forward"] = {"value": r, "pass": r <= 3.0}
+        b = res["secondary"]["batched"]["speedup_vs_one_cone_per_launch"]
+        targets["batched_ge_2x_one_cone_per_launch"] = {"value": b, "pass": b >= 2.0}
+    res["targets"] = targets
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        env = os.environ.get("OMP_NUM_THREADS")
-        if env and env.isdigit():
-            threads = min(threads, int(env))
-        log(f"[bench] CPU baseline: oracle on every {args.cpu_stride}th ray with {threads} threads")
-        res["cpu_baseline"] = cpu_baseline(w, cells, args.cpu_stride, threads)
-        if w.name == "amr":
-            res["cpu_baseline"]["single_thread"] = cpu_table1(w, cells)
+        threads, nproc, model = host_cores()
+        stride = args.cpu_stride or max(1, n_rays // 16384)
+        log(f"[bench] CPU baseline: oracle on every {stride}th ray with {threads} threads ({model})")
+        res["cpu_baseline"] = cpu_baseline(w, cells, stride, threads)
+        res["cpu_baseline"].update({"nproc": nproc, "cpu_model": model})
+        log(f"[bench] CPU baseline: {res['cpu_baseline']['value'] / 1e6:.2f} M ray-steps/s")
+        if not args.no_secondary:
+            res["cpu_baseline"]["single_thread"] = cpu_table1()
             log(f"[bench] oracle single-thread us/step: {res['cpu_baseline']['single_thread']['us_per_ray_step']}")
     print(json.dumps(res), flush=True)
 

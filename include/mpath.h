@@ -591,11 +591,10 @@ int mpath_born_beam(const mpath_grid* grid, const mpath_cast_desc* desc, float* 
  * Launches n_waves one-wave workgroups; each of the n_waves * 64 lanes reads
  * `iters * in_flight` records of `record_bytes` (16, 64 or 128) bytes at
  * indices drawn uniformly in [0, table_bytes / record_bytes) from its own
- * xorshift32 sequence (seeded by `seed` and the lane number), with
+ * xorshift64 sequence (seeded by `seed` and the lane number), with
  * `in_flight` (1, 2 or 4) independent reads outstanding per lane, and writes
  * the float sum of what it read to out[lane].
- *   table: DEVICE, 16-byte aligned, table_bytes readable bytes (any content;
- *          at most 2^32 - 1 records).
+ *   table: DEVICE, 16-byte aligned, table_bytes readable bytes (any content).
  *   out:   DEVICE float[n_waves * 64], written.
  *   n_waves in [1, 2^24], iters >= 1.
  * Bytes gathered = n_waves * 64 * iters * in_flight * record_bytes.  The call

@@ -1339,8 +1339,6 @@ int mpath_gather_probe(const void* table, size_t table_bytes, int32_t record_byt
     if (record_bytes != 16 && record_bytes != 64 && record_bytes != 128)
         return fail(MPATH_ERR_INVALID_ARG, "record_bytes must be 16, 64 or 128");
     if (table_bytes < (size_t)record_bytes) return fail(MPATH_ERR_INVALID_ARG, "table smaller than one record");
-    if (table_bytes / (size_t)record_bytes > 0xffffffffull)
-        return fail(MPATH_ERR_INVALID_ARG, "at most 2^32 - 1 records");
     if (in_flight != 1 && in_flight != 2 && in_flight != 4)
         return fail(MPATH_ERR_INVALID_ARG, "in_flight must be 1, 2 or 4");
     if (n_waves < 1 || n_waves > (1 << 24)) return fail(MPATH_ERR_INVALID_ARG, "n_waves must be in [1, 2^24]");

@@ -4,7 +4,9 @@
 // links) are measured.  Not a step of the method.
 //
 // Every lane draws record indices uniformly over the table from its own
-// xorshift32 sequence and reads whole records (16, 64 or 128 bytes,
+// xorshift64 sequence (Marsaglia 2003, shifts 13, 7, 17; the index is the high
+// half of the 128-bit product of the draw and the record count) and reads
+// whole records (16, 64 or 128 bytes,
 // 16-byte aligned) with `in_flight` independent gathers outstanding per
 // lane; the loaded words are summed into one float per lane so that no load
 // is dead.  Waves are one-per-workgroup, so the grid size sets the number of
@@ -16,11 +18,11 @@
 namespace mpath {
 namespace {
 
-__device__ __forceinline__ uint32_t xorshift32(uint32_t s)
+__device__ __forceinline__ uint64_t xorshift64(uint64_t s)
 {
     s ^= s << 13;
-    s ^= s >> 17;
-    s ^= s << 5;
+    s ^= s >> 7;
+    s ^= s << 17;
     return s;
 }
 
@@ -30,15 +32,15 @@ __global__ __launch_bounds__(64) void gather_probe_kernel(const float4* __restri
 {
     const uint32_t lane = blockIdx.x * 64u + threadIdx.x;
     // distinct non-zero start per lane (the multiplier is odd, so the map is a bijection)
-    uint32_t s = (lane + 1u) * 0x9E3779B1u ^ seed;
-    if (s == 0u) s = 0x6D2B79F5u;
+    uint64_t s = ((uint64_t)lane + 1u) * 0x9E3779B97F4A7C15ull ^ ((uint64_t)seed << 17);
+    if (s == 0u) s = 0x6D2B79F5ull;
     float acc = 0.f;
     for (int it = 0; it < iters; ++it) {
         float4 v[U][R16];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            s = xorshift32(s);
-            const uint64_t r = ((uint64_t)s * n_records) >> 32;   // uniform in [0, n_records)
+            s = xorshift64(s);
+            const uint64_t r = __umul64hi(s, n_records);          // uniform in [0, n_records)
             const float4* p = table + r * R16;
 #pragma unroll
             for (int j = 0; j < R16; ++j) v[u][j] = p[j];

@@ -11,17 +11,18 @@ def host_probe(table, rec16, in_flight, n_waves, iters, seed):
     n_rec = table.shape[0] // rec16
     out = np.zeros(n_waves * 64, np.float32)
     for lane in range(n_waves * 64):
-        s = (((lane + 1) * 0x9E3779B1) & 0xFFFFFFFF) ^ seed
+        M64 = (1 << 64) - 1
+        s = (((lane + 1) * 0x9E3779B97F4A7C15) & M64) ^ (seed << 17)
         if s == 0:
             s = 0x6D2B79F5
         acc = np.float32(0)
         for _ in range(iters):
             recs = []
             for _u in range(in_flight):
-                s ^= (s << 13) & 0xFFFFFFFF
-                s ^= s >> 17
-                s ^= (s << 5) & 0xFFFFFFFF
-                r = (s * n_rec) >> 32
+                s ^= (s << 13) & M64
+                s ^= s >> 7
+                s ^= (s << 17) & M64
+                r = (s * n_rec) >> 64
                 recs.append(table[r * rec16:(r + 1) * rec16])
             for v in recs:
                 for x, y, z, w in v:
