@@ -512,6 +512,9 @@ def main():
                     help="skip the random-gather ceiling measurement")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle on every n-th NESTED pixel (default: 16,384 rays of the workload)")
+    ap.add_argument("--only", default=None,
+                    choices=("amr", "adjoint", "batched", "lensing", "finder", "orders", "variants"),
+                    help="run one secondary measurement alone (no headline cast; for profiling) and print it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the casts, copy MIB mebibytes once with a plain device copy "
                          "(reference for the HBM byte counters)")
@@ -528,6 +531,13 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     dev = torch.device("cuda:0")
+    if args.only:
+        fn = {"amr": lambda: measure_secondary_amr(M, torch, dev, 5), "adjoint": lambda: measure_adjoint(M, torch, dev),
+              "batched": lambda: measure_batched(M, torch, dev), "lensing": lambda: measure_lensing(M, torch, dev),
+              "finder": lambda: measure_finder(M, torch, dev), "orders": lambda: measure_orders(M, torch, dev),
+              "variants": lambda: measure_variants(M, torch, dev)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
     t0 = time.time()
     w, cells = workload(args.workload)
     t_gen = time.time() - t0

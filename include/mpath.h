@@ -359,6 +359,31 @@ int mpath_cast(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observ
 #define MPATH_NOALLOC_SCRATCH_BYTES (64u << 20)
 int mpath_cast_noalloc(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observables* out, void* stream);
 
+/* ---- forward mode ----
+ * The distortion matrix of the lens equation (Sect. 2.3) and dz5/dtheta by
+ * forward-mode differentiation of the same discrete map that mpath_cast
+ * computes (RK4 on the geodesic equations of Sect. 2.2 with CIC
+ * interpolation and the AMR level fallback, step length h_leaf / N through
+ * |k0|, landing on the iso-eta surface): one pass carries, with every ray,
+ * the tangents of its state for the two directions e1 = e_phi, e2 =
+ * -e_theta in which the initial direction theta can move; the discrete
+ * decisions (leaf levels, stencils) carry no derivative.  No checkpoints and
+ * no reverse sweep: the cost is one cast with about twice the arithmetic.
+ * Outputs as mpath_cast (bit for bit the same) plus, DEVICE, length n_rays:
+ *   jac[2][2]     A_ab = d beta_a / d theta_b, beta_a on the screen basis
+ *                 e~1 = e_phi, e~2 = -e_theta at the end direction, theta_b
+ *                 on the basis at the initial direction (row-major: a, then
+ *                 b); NaN for rays that did not reach the source
+ *   dz_dtheta[2]  d z5 / d theta_b (NaN likewise)
+ * either may be NULL.  CIC casts (order 1) to an iso-eta surface with the
+ * chain-rule dPhi/dlambda, n_surfaces 0 and a static potential
+ * (MPATH_ERR_UNSUPPORTED otherwise), checkpoint_every 0 (INVALID_ARG);
+ * static schedule (the launch-shape fields are ignored).  Workspace:
+ * mpath_cast_jacobian_workspace_bytes (the cast's plus 80 B per ray). */
+int mpath_cast_jacobian_workspace_bytes(const mpath_grid* grid, const mpath_cast_desc* desc, size_t* bytes);
+int mpath_cast_jacobian(const mpath_grid* grid, const mpath_cast_desc* desc, mpath_observables* out, float* jac,
+                        float* dz_dtheta, void* dev_ws, size_t ws_bytes, void* stream);
+
 /* ---- reverse mode ----
  * The derivative of the discrete map that mpath_cast computes (RK4 on the
  * geodesic equations of Sect. 2.2 with CIC interpolation and the AMR level

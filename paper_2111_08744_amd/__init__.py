@@ -24,7 +24,7 @@ from ._abi import (MPATH_RAY_LEFT_DOMAIN, MPATH_RAY_MAX_STEPS, MPATH_RAY_NONFINI
                    MPATH_RAY_REACHED, MPATH_SCHED_AUTO, MPATH_SCHED_PERSISTENT,
                    MPATH_SCHED_STATIC, MPATH_STOP_CHI, MPATH_STOP_REDSHIFT, MpathError)
 
-__all__ = ["Grid", "cast", "CastConfig", "adjoint", "autotune", "cast_differentiable", "library_path",
+__all__ = ["Grid", "cast", "CastConfig", "jacobian", "adjoint", "autotune", "cast_differentiable", "library_path",
            "lensing_maps", "finite_beam", "infinitesimal_beam", "born_beam", "find_geodesics",
            "MpathError"]
 
@@ -269,6 +269,36 @@ def cast(grid: Grid, cfg: CastConfig, out=None, ws=None):
     with torch.cuda.device(grid.device):
         _abi.check(L.mpath_cast(grid.handle, C.byref(d), C.byref(obs), _ptr(ws), ws.numel(),
                                 _stream_ptr(grid.device)), "mpath_cast")
+    out["_ws"] = ws
+    return out
+
+
+def jacobian(grid: Grid, cfg: CastConfig, out=None, ws=None):
+    """mpath_cast_jacobian: the cast of every ray of cfg (the outputs of
+    ``cast``, bit for bit) with the distortion matrix ``jac`` [n_rays, 2, 2]
+    (A_ab = d beta_a / d theta_b) and ``dz_dtheta`` [n_rays, 2] by
+    forward-mode differentiation in the same pass."""
+    torch = _torch()
+    L = _abi.lib()
+    d = cfg.desc()
+    n = cfg.n_rays()
+    if cfg.dirs is not None and cfg.dirs.shape[0] != n:
+        raise ValueError(f"dirs has {cfg.dirs.shape[0]} rows for {n} rays")
+    if out is None:
+        out = alloc_outputs(n, grid.device)
+    for k in ("jac", "dz_dtheta"):
+        if k not in out:
+            out[k] = torch.empty((n, 2, 2) if k == "jac" else (n, 2), dtype=torch.float32, device=grid.device)
+    nbytes = C.c_size_t()
+    _abi.check(L.mpath_cast_jacobian_workspace_bytes(grid.handle, C.byref(d), C.byref(nbytes)),
+               "mpath_cast_jacobian_workspace_bytes")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=grid.device)
+    obs = observables_struct(out)
+    with torch.cuda.device(grid.device):
+        _abi.check(L.mpath_cast_jacobian(grid.handle, C.byref(d), C.byref(obs), _ptr(out["jac"]),
+                                         _ptr(out["dz_dtheta"]), _ptr(ws), ws.numel(), _stream_ptr(grid.device)),
+                   "mpath_cast_jacobian")
     out["_ws"] = ws
     return out
 

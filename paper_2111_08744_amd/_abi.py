@@ -111,6 +111,8 @@ def lib():
         L.mpath_cast.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp, sz, vp]
         L.mpath_cast_count_rays.argtypes = [P(mpath_cast_desc), P(C.c_int64)]
         L.mpath_cast_noalloc.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp]
+        L.mpath_cast_jacobian_workspace_bytes.argtypes = [vp, P(mpath_cast_desc), P(sz)]
+        L.mpath_cast_jacobian.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp, vp, vp, sz, vp]
         L.mpath_adjoint_workspace_bytes.argtypes = [vp, P(mpath_cast_desc), P(sz)]
         L.mpath_adjoint.argtypes = [vp, P(mpath_cast_desc), P(mpath_observables), vp, sz,
                                     P(mpath_adjoint_desc), vp, sz, vp]
@@ -135,6 +137,7 @@ def lib():
                      "mpath_grid_aux_bytes", "mpath_grid_build_with_aux",
                      "mpath_grid_get_info", "mpath_grid_set_values", "mpath_cast_workspace_bytes",
                      "mpath_cast", "mpath_cast_count_rays", "mpath_cast_noalloc", "mpath_adjoint_workspace_bytes",
+                     "mpath_cast_jacobian_workspace_bytes", "mpath_cast_jacobian",
                      "mpath_adjoint", "mpath_autotune_workspace_bytes", "mpath_autotune", "mpath_gather_probe",
                      "mpath_lensing_maps", "mpath_finite_beam_workspace_bytes", "mpath_finite_beam",
                      "mpath_infinitesimal_beam", "mpath_find_geodesics_workspace_bytes", "mpath_find_geodesics",

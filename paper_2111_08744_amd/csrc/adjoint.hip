@@ -108,7 +108,8 @@ struct StageRecord {
     }
 
     template <class FC>
-    __device__ __forceinline__ void stage(int i, const GeoState& yi, const FC& F, const float* G)
+    __device__ __forceinline__ void stage(int i, const GeoState&, const GeoState& yi, const FC& F, const float* G,
+                                          const HubbleCubic&, const CosmoDev&)
     {
         float* q = p + i * kWords * kBlock;
         put64(q, 0, yi.eta);

@@ -287,6 +287,59 @@ struct RayRun {
     }
 
     // Outputs at the end of advance_stop: the end point's own scale factor.
+    // advance() for a plain cast (iso-eta stop, chain rule, static
+    // potential) with a stage recorder T that also sees every step's start
+    // and end: T.begin_step(y, dl, regular) before the RK4 pass it records
+    // (every regular step; of the landing only the final pass) and
+    // T.end_step(y, yn) after it.  The steps, their decisions and the
+    // primal arithmetic are those of advance(), bit for bit.
+    template <class Tan>
+    __device__ __forceinline__ void advance_recorded(const CastArgs& a, Tan& T)
+    {
+        if (status >= 0) return;
+        const GridDev& g = a.grid;
+        ChainRule cr;
+        for (;;) {
+            if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return; }
+            double v[3];
+            grid_coords(g, geo, y.eta, y.dx, v);
+            int I[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
+            const int L = F.leaf(g, I);
+            if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return; }
+            hash = fnv(hash, (uint32_t)L);
+            const double dl = a.ds_level[L] / y.K;
+            if (fma(-y.K, dl, y.eta) < eta_s) break;
+            GeoState yn;
+            T.begin_step(y, dl, true);
+            if (rk4_core<FC, Tan, ChainRule>(g, a.cosmo, F, geo, y, dl, yn, hash, T, true, cr)) {
+                status = MPATH_RAY_LEFT_DOMAIN;
+                return;
+            }
+            if (!finite_state(yn)) { status = MPATH_RAY_NONFINITE; return; }
+            T.end_step(y, yn);
+            y = yn;
+            ++n_steps;
+        }
+        // landing on the iso-eta surface (as advance())
+        double dlx = (y.eta - eta_s) / y.K;
+        GeoState yn;
+        for (int k = 0; k < 3; ++k) {
+            if (k == 2) T.begin_step(y, dlx, false);
+            if (rk4_core<FC, Tan, ChainRule>(g, a.cosmo, F, geo, y, dlx, yn, hash, T, k == 2, cr)) {
+                status = MPATH_RAY_LEFT_DOMAIN;
+                return;
+            }
+            if (k < 2) dlx = dlx + (yn.eta - eta_s) / yn.K;
+        }
+        const bool fin = finite_state(yn);
+        T.end_step(y, yn);
+        y = yn;
+        ++n_steps;
+        status = fin ? MPATH_RAY_REACHED : MPATH_RAY_NONFINITE;
+    }
+
     __device__ __forceinline__ void finish_stop(const CastArgs& a)
     {
         int j = a.n_obs - 1;
@@ -754,6 +807,336 @@ __global__ void permute_values_kernel(float4* payload, const int64_t* perm, cons
     if (i < n) payload[i] = values[perm[i]];
 }
 
+// ---------------------------------------------------------------------------
+// Forward-mode derivative of the cast with respect to the initial direction
+// theta: two tangents, b = 1, 2, moving the initial unit vector n along
+// e1 = e_phi, e2 = -e_theta (the screen basis at theta).  Written in the
+// physical variables (eta, x, k0 = -K, k) of the geodesic equations
+// (Sect. 2.2), whose RK4 map equals the split one of the kernels; the
+// tangent of a state is kept as
+//   (deta, dK, dX = dx - s e_b, dQ = dk - K e_b),   s = eta_0 - eta,
+// so that the parts of order one (the unlensed change s e_b of the position
+// and K e_b of the wave vector, carried exactly by the primal s and K) never
+// enter float32 arithmetic, and only lensing-sized quantities do.  With
+// F = dy/dl, psi = G.k and G, JG the interpolated gradient and its spatial
+// derivative (the trilinear interpolant of the stencil),
+//   deta' = -dK
+//   dK'   = 2 H' K^2 deta + (4 H K - 2 psi) dK - 2 K dpsi
+//   dX'   = dQ
+//   dQ'   = 2 H' deta K k + 2 H dK k + (2 H K + 2 psi) dQ + 2 dpsi k
+//           - 2 dG K^2 - 4 G K dK + 4 psi K e_b,
+//   dG = JG (s e_b + dX),  dpsi = dG.k + K G.e_b + G.dQ,
+// and RK4 is differentiated stage by stage, including the step length
+// dl = ds / K (d(dl) = -dl dK / K: the term rho (Y_i - y), rho = -dK/K,
+// with Y_i - y = c_i dl F_{i-1}).  The landing step's length is set by the
+// source surface; its pass is differentiated at fixed length and the end
+// tangent projected along the flow afterwards (tangent_observables_kernel).
+// ---------------------------------------------------------------------------
+struct TangentPair {
+    float n[3];                                   // initial direction
+    float e[2][3];                                // e_b
+    float dEta[2], dK[2], dX[2][3], dQ[2][3];     // tangents at the step start
+    float fEta[2], fK[2], fX[2][3], fQ[2][3];     // their derivative at the previous stage
+    float aEta[2], aK[2], aX[2][3], aQ[2][3];     // sum of w_i times it over the stages
+    float rho[2];                                  // d(dl)/dl of the recorded pass
+    float dlf;                                     // its affine length
+    double eta0;
+    float inv_h0;
+
+    __device__ __forceinline__ void init(const CastArgs& a, const RayGeom& geo, float phi_o)
+    {
+        eta0 = a.cosmo_eta0;
+        inv_h0 = (float)a.grid.inv_h0;
+        const double* v = geo.n;
+        const double rh = hypot(v[0], v[1]);
+        const double cp = rh > 0.0 ? v[0] / rh : 1.0, sp = rh > 0.0 ? v[1] / rh : 0.0;
+        const double ct = v[2], st = rh;
+        const double eb[2][3] = {{-sp, cp, 0.0}, {-cp * ct, -sp * ct, st}};
+        // k = kmag n at the observer, so dk = kmag e_b there and dQ = (kmag - 1) e_b
+        const double po = (double)phi_o;
+        const float km1 = (float)(sqrt((1.0 + 2.0 * po) / (1.0 - 2.0 * po)) - 1.0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) n[i] = (float)v[i];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            dEta[b] = 0.0f;
+            dK[b] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                e[b][i] = (float)eb[b][i];
+                dX[b][i] = 0.0f;
+                dQ[b][i] = km1 * e[b][i];
+            }
+        }
+    }
+
+    __device__ __forceinline__ void begin_step(const GeoState& y, double dl, bool regular)
+    {
+        dlf = (float)dl;
+        const float invK = 1.0f / (float)y.K;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            rho[b] = regular ? -dK[b] * invK : 0.0f;
+            aEta[b] = 0.0f;
+            aK[b] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { aX[b][i] = 0.0f; aQ[b][i] = 0.0f; }
+        }
+    }
+
+    // Y - y in the physical variables: (eta, K, x, k) differences
+    __device__ __forceinline__ void diff(const GeoState& y, const GeoState& Y, float& De, float& DK, float Dx[3],
+                                         float Dk[3]) const
+    {
+        De = (float)(Y.eta - y.eta);
+        DK = (float)(Y.K - y.K);
+        const float KY = (float)Y.K, Ky = (float)y.K;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            Dx[i] = fmaf(-De, n[i], Y.dx[i] - y.dx[i]);
+            Dk[i] = fmaf(DK, n[i], fmaf(KY, Y.d[i], -Ky * y.d[i]));
+        }
+    }
+
+    template <class FC>
+    __device__ __forceinline__ void stage(int st, const GeoState& y, const GeoState& yi, const FC& F,
+                                          const float* G, const HubbleCubic& Hc, const CosmoDev& cz)
+    {
+        const float c = st == 0 ? 0.0f : (st == 3 ? 1.0f : 0.5f);
+        const float cdl = c * dlf;
+        const float w = (st == 0 || st == 3) ? 1.0f : 2.0f;
+        const float Kf = (float)yi.K;
+        float k[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) k[i] = Kf * (n[i] + yi.d[i]);
+        const float s = (float)(eta0 - yi.eta);
+        const float H = (float)Hc(cz, yi.eta), dH = (float)Hc.deriv(cz, yi.eta);
+        const float psi = G[0] * k[0] + G[1] * k[1] + G[2] * k[2];
+        float De, DK, Dx[3], Dk[3];
+        diff(y, yi, De, DK, Dx, Dk);
+        // spatial derivative of the interpolated gradient: the t-derivatives
+        // of the stencil's trilinear interpolant times 2^lvl / h0
+        const float tx = F.t[0], ty = F.t[1], tz = F.t[2];
+        const float sc = ldexpf(inv_h0, F.lvl);
+        float JG[3][3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float* q = F.c + 8 * (j + 1) * FC::cstride;
+            const float c1 = q[FC::cstride], c2 = q[2 * FC::cstride], c3 = q[3 * FC::cstride];
+            const float c4 = q[4 * FC::cstride], c5 = q[5 * FC::cstride], c6 = q[6 * FC::cstride];
+            const float c7 = q[7 * FC::cstride];
+            JG[j][0] = (c1 + ty * c4 + tz * c5 + ty * tz * c7) * sc;
+            JG[j][1] = (c2 + tx * c4 + tz * c6 + tx * tz * c7) * sc;
+            JG[j][2] = (c3 + tx * c5 + ty * c6 + tx * ty * c7) * sc;
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            float te = dEta[b], tK = dK[b], tX[3], tQ[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { tX[i] = dX[b][i]; tQ[i] = dQ[b][i]; }
+            if (st > 0) {
+                te += cdl * fEta[b] + rho[b] * De;
+                tK += cdl * fK[b] + rho[b] * DK;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    tX[i] += cdl * fX[b][i] + rho[b] * Dx[i];
+                    tQ[i] += cdl * fQ[b][i] + rho[b] * Dk[i];
+                }
+            }
+            float dxf[3], dG[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dxf[i] = s * e[b][i] + tX[i];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dG[j] = JG[j][0] * dxf[0] + JG[j][1] * dxf[1] + JG[j][2] * dxf[2];
+            const float dpsi = (dG[0] * k[0] + dG[1] * k[1] + dG[2] * k[2]) +
+                               Kf * (G[0] * e[b][0] + G[1] * e[b][1] + G[2] * e[b][2]) +
+                               (G[0] * tQ[0] + G[1] * tQ[1] + G[2] * tQ[2]);
+            fEta[b] = -tK;
+            fK[b] = 2.0f * dH * Kf * Kf * te + (4.0f * H * Kf - 2.0f * psi) * tK - 2.0f * Kf * dpsi;
+            const float ck = 2.0f * dH * te * Kf + 2.0f * H * tK + 2.0f * dpsi;
+            const float cq = 2.0f * H * Kf + 2.0f * psi;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                fX[b][i] = tQ[i];
+                fQ[b][i] = ck * k[i] + cq * tQ[i] - 2.0f * Kf * Kf * dG[i] - 4.0f * Kf * tK * G[i] +
+                           4.0f * psi * Kf * e[b][i];
+            }
+            aEta[b] += w * fEta[b];
+            aK[b] += w * fK[b];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                aX[b][i] += w * fX[b][i];
+                aQ[b][i] += w * fQ[b][i];
+            }
+        }
+    }
+
+    __device__ __forceinline__ void end_step(const GeoState& y, const GeoState& yn)
+    {
+        float De, DK, Dx[3], Dk[3];
+        diff(y, yn, De, DK, Dx, Dk);
+        const float h6 = dlf * (1.0f / 6.0f);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            dEta[b] += h6 * aEta[b] + rho[b] * De;
+            dK[b] += h6 * aK[b] + rho[b] * DK;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                dX[b][i] += h6 * aX[b][i] + rho[b] * Dx[i];
+                dQ[b][i] += h6 * aQ[b][i] + rho[b] * Dk[i];
+            }
+        }
+    }
+};
+
+// The cast with the two tangents: the primal outputs of the plain cast (bit
+// for bit) and the tangent end states for tangent_observables_kernel.
+// The tangents take registers the plain cast has not: two waves per SIMD.
+template <bool AMR>
+__global__ __launch_bounds__(kBlock, 2) void cast_tangent_kernel(CastArgs a, TanEnd* te)
+{
+    extern __shared__ float coef_lds[];
+    const int64_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (r >= a.n_rays) return;
+    RayRun<AMR> R;
+    R.F.bind(coef_lds + threadIdx.x);
+    R.start(a, r);
+    TangentPair T;
+    T.init(a, R.geo, R.phi_o);
+    R.advance_recorded(a, T);
+    R.finish(a);           // leaves the end point's stencil in R.F
+    TanEnd e;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        e.deta[b] = T.dEta[b];
+        e.dK[b] = T.dK[b];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) e.dX[b][i] = T.dX[b][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) e.d[i] = R.y.d[i];
+    e.phi_o = R.phi_o;
+    e.K = R.y.K;
+    e.base = R.F.base;
+    e.lvl = R.F.lvl;
+    e.status = R.status;
+    e.pad = 0;
+    te[r] = e;
+}
+
+// Distortion matrix and dz5/dtheta from the tangent end states (double
+// precision).  The landing step ends on eta = eta_s whatever theta is, so
+// the end tangent is projected along the flow F(y_f) until deta = 0:
+// dy_f += F(y_f) deta / K_f.  Then, with r = x_f - x_obs,
+//   A_ab = e~_a(beta) . (s_f e_b + dX_b) / |r|     (Sect. 2.3, rows on the
+//          screen basis at the end direction, columns on the one at theta)
+//   dz5_b = a_s / (1 + Phi_o) [dK_b (1 + Phi_s) + K_f dPhi_s_b],
+// dPhi_s_b the derivative of the interpolated Phi along the end tangent
+// (Sect. 2.5, z5 with v = 0).
+__global__ __launch_bounds__(256) void tangent_observables_kernel(CastArgs a, const TanEnd* te, float* jac,
+                                                                  float* dz)
+{
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ray >= a.n_rays) return;
+    const float q = __builtin_nanf("");
+    const TanEnd T = te[ray];
+    if (T.status != MPATH_RAY_REACHED) {
+        if (jac) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) jac[4 * ray + i] = q;
+        }
+        if (dz) { dz[2 * ray] = q; dz[2 * ray + 1] = q; }
+        return;
+    }
+    const GridDev& g = a.grid;
+    const RayEnd e = a.ends[ray];
+    const ObsDev& ob = a.obs[e.obs];
+    const double n[3] = {a.dirs[3 * ray], a.dirs[3 * ray + 1], a.dirs[3 * ray + 2]};
+    const double s = a.cosmo_eta0 - e.eta;
+    double r[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r[i] = s * n[i] + (double)e.dx[i];
+    const double chi = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    // bases: e_b at theta, e~_a at the end direction
+    auto basis = [](const double v[3], double e1[3], double e2[3]) {
+        const double rh = hypot(v[0], v[1]), rr = sqrt(rh * rh + v[2] * v[2]);
+        const double cp = rh > 0.0 ? v[0] / rh : 1.0, sp = rh > 0.0 ? v[1] / rh : 0.0;
+        const double ct = v[2] / rr, st = rh / rr;
+        e1[0] = -sp; e1[1] = cp; e1[2] = 0.0;
+        e2[0] = -cp * ct; e2[1] = -sp * ct; e2[2] = st;
+    };
+    double eb[2][3], ea[2][3];
+    basis(n, eb[0], eb[1]);
+    basis(r, ea[0], ea[1]);
+    // the interpolant at the end point: Phi, its gradient and grad Phi
+    double v[3];
+    {
+        RayGeom geo;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            geo.vo[i] = ldexp(ob.x[i] / g.h0, g.max_level + 1);
+            geo.n[i] = n[i];
+        }
+        grid_coords(g, geo, e.eta, e.dx, v);
+    }
+    const double sl = ldexp(1.0, T.lvl - g.max_level - 1);
+    double t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double u = v[d] * sl - 0.5;
+        t[d] = u - floor(u);
+    }
+    const float4* rec = g.dual + 8 * (int64_t)T.base;
+    double cf[4][8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const float4 c4 = rec[o];
+        cf[0][o] = c4.x; cf[1][o] = c4.y; cf[2][o] = c4.z; cf[3][o] = c4.w;
+    }
+    auto tri = [&](const double* c, double& f, double& fx, double& fy, double& fz) {
+        const double tx = t[0], ty = t[1], tz = t[2];
+        f = c[0] + tx * (c[1] + ty * (c[4] + tz * c[7]) + tz * c[5]) + ty * (c[2] + tz * c[6]) + tz * c[3];
+        fx = c[1] + ty * c[4] + tz * c[5] + ty * tz * c[7];
+        fy = c[2] + tx * c[4] + tz * c[6] + tx * tz * c[7];
+        fz = c[3] + tx * c[5] + ty * c[6] + tx * ty * c[7];
+    };
+    const double scale = ldexp(g.inv_h0, T.lvl);
+    double phis, gp[3], G[3], dum[3];
+    tri(cf[0], phis, gp[0], gp[1], gp[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gp[i] *= scale;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tri(cf[j + 1], G[j], dum[0], dum[1], dum[2]);
+    HubbleCubic Hc;
+    Hc.init(a.cosmo, e.eta);
+    const double H = Hc(a.cosmo, e.eta);
+    const double K = T.K;
+    double k[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k[i] = K * (n[i] + (double)T.d[i]);
+    const double psi = G[0] * k[0] + G[1] * k[1] + G[2] * k[2];
+    const double FK = 2.0 * H * K * K - 2.0 * psi * K;
+    const double a_s = a.ray_stop ? a.ray_stop[ray].y : ob.a_s;
+    const double pref = a_s / (1.0 + (double)T.phi_o);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const double tau = (double)T.deta[b] / K;
+        double dr[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dr[i] = s * eb[b][i] + ((double)T.dX[b][i] + tau * k[i]);
+        const double dKb = (double)T.dK[b] + tau * FK;
+        if (jac) {
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa)
+                jac[4 * ray + 2 * aa + b] = (float)((ea[aa][0] * dr[0] + ea[aa][1] * dr[1] + ea[aa][2] * dr[2]) / chi);
+        }
+        if (dz) {
+            const double dphi = gp[0] * dr[0] + gp[1] * dr[1] + gp[2] * dr[2];
+            dz[2 * ray + b] = (float)(pref * (dKb * (1.0 + phis) + K * dphi));
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_cast_static(const CastArgs& a, int block, hipStream_t s)
@@ -795,6 +1178,27 @@ hipError_t launch_cast_infbeam(const CastArgs& a, float* A, hipStream_t s)
         hipLaunchKernelGGL(cast_infbeam_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, A);
     else
         hipLaunchKernelGGL(cast_infbeam_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_tangent(const CastArgs& a, TanEnd* te, hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
+    const size_t lds = (size_t)32 * kBlock * sizeof(float);
+    if (a.grid.max_level > 0)
+        hipLaunchKernelGGL(cast_tangent_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, te);
+    else
+        hipLaunchKernelGGL(cast_tangent_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a, te);
+    return hipGetLastError();
+}
+
+hipError_t launch_tangent_observables(const CastArgs& a, const TanEnd* te, float* jac, float* dz_dtheta,
+                                      hipStream_t s)
+{
+    if (a.n_rays == 0) return hipSuccess;
+    hipLaunchKernelGGL(tangent_observables_kernel, dim3((unsigned)((a.n_rays + 255) / 256)), dim3(256), 0, s, a, te,
+                       jac, dz_dtheta);
     return hipGetLastError();
 }
 

@@ -652,10 +652,16 @@ struct StepDifference {
     float D;            // its dPhi/dl
 };
 
-// No-op stage recorder of the forward kernels.
+// No-op stage recorder of the forward kernels.  A recorder's stage hook
+// sees the stage index, the step-start state y, the stage state yi, the
+// field evaluator (its stencil and offsets at the stage), the interpolated
+// gradient and the background cubic of the step.
 struct NoRecord {
     template <class FC>
-    __device__ __forceinline__ void stage(int, const GeoState&, const FC&, const float*) {}
+    __device__ __forceinline__ void stage(int, const GeoState&, const GeoState&, const FC&, const float*,
+                                          const HubbleCubic&, const CosmoDev&)
+    {
+    }
 };
 
 // One RK4 step of affine length dl from y into out (F: the lane's field
@@ -713,7 +719,7 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
         int leafl, l = 0;
         const bool bad = F.eval(g, u, phi, G, leafl, l) != 0;
         h = fnv(h, (uint32_t)l);
-        if (record) rec.stage(st, yi, F, G);
+        if (record) rec.stage(st, y, yi, F, G, Hc, cz);
         const double H = Hc(cz, yi.eta);
         const float m[3] = {nf[0] + yi.d[0], nf[1] + yi.d[1], nf[2] + yi.d[2]};
         const float mG = fmaf(m[2], G[2], fmaf(m[1], G[1], m[0] * G[0]));

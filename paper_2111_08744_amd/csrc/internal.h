@@ -83,6 +83,22 @@ struct RayEnd {
     int32_t obs;
 };
 
+// End state of the two forward-mode tangents of a ray (mpath_cast_jacobian):
+// per tangent b the tangents of eta and K = |k0| and dX = dx - s e_b
+// (x = x_obs + s n, s the path length, e_b the direction the initial n moves
+// along) at the end point before the landing step's length is
+// differentiated; the end state's d and K, Phi at the observer, and the
+// stencil (lowest corner, level) of the end point.
+struct TanEnd {
+    float deta[2], dK[2], dX[2][3];
+    float d[3];
+    float phi_o;
+    double K;
+    int32_t base, lvl;
+    int32_t status;
+    int32_t pad;
+};
+
 struct OutDev {
     double* beta;
     float* alpha;
@@ -149,6 +165,9 @@ hipError_t launch_cast_persistent(const CastArgs& a, int block, int blocks, hipS
 hipError_t launch_observables(const CastArgs& a, hipStream_t s);
 hipError_t launch_ray_dirs(const CastArgs& a, hipStream_t s);
 hipError_t launch_cast_infbeam(const CastArgs& a, float* A, hipStream_t s);
+hipError_t launch_cast_tangent(const CastArgs& a, TanEnd* te, hipStream_t s);
+hipError_t launch_tangent_observables(const CastArgs& a, const TanEnd* te, float* jac, float* dz_dtheta,
+                                      hipStream_t s);
 hipError_t launch_cast_order(const CastArgs& a, int order, hipStream_t s);
 hipError_t launch_born_beam(const CastArgs& a, float* A, int32_t* status, hipStream_t s);
 hipError_t launch_cast_surfaces(const CastArgs& a, const double2* surf, int n_extra, hipStream_t s);

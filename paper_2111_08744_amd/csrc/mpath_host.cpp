@@ -936,10 +936,19 @@ int mpath_cast_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, si
 
 namespace {
 
+// Outputs of the forward-mode derivative (mpath_cast_jacobian).
+struct TangentOut {
+    TanEnd* ends;
+    float* jac;
+    float* dz_dtheta;
+};
+
 // mpath_cast, or with inf set the cast that also integrates the
-// infinitesimal-beam distortion matrix into inf_A (static schedule).
+// infinitesimal-beam distortion matrix into inf_A (static schedule), or with
+// tg set the cast that carries the two tangents (static schedule).
 int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, void* dev_ws,
-              size_t ws_bytes, void* stream, bool inf, float* inf_A, const double2* ray_stop = nullptr)
+              size_t ws_bytes, void* stream, bool inf, float* inf_A, const double2* ray_stop = nullptr,
+              const TangentOut* tg = nullptr)
 {
     int64_t n_rays;
     std::vector<ObsDev> obs;
@@ -1006,6 +1015,12 @@ int cast_impl(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* 
         }
         if (e) return hip_fail(e, "cast launch");
         return MPATH_OK;
+    }
+    if (tg) {
+        e = launch_cast_tangent(a, tg->ends, s);
+        if (!e) e = launch_observables(a, s);
+        if (!e) e = launch_tangent_observables(a, tg->ends, tg->jac, tg->dz_dtheta, s);
+        return e ? hip_fail(e, "tangent cast launch") : MPATH_OK;
     }
     if (inf) {
         e = launch_cast_infbeam(a, inf_A, s);
@@ -1127,6 +1142,42 @@ int mpath_born_beam(const mpath_grid* g, const mpath_cast_desc* d, float* A, int
         e = launch_ray_dirs(a, s);
     if (!e) e = launch_born_beam(a, A, status, s);
     return e ? hip_fail(e, "Born beam launch") : MPATH_OK;
+}
+
+int mpath_cast_jacobian_workspace_bytes(const mpath_grid* g, const mpath_cast_desc* d, size_t* bytes)
+{
+    if (!bytes) return fail(MPATH_ERR_INVALID_ARG, "bytes is NULL");
+    int64_t n_rays;
+    std::vector<ObsDev> obs;
+    CastLayout lay;
+    const int rc = cast_plan(g, d, &n_rays, obs, &lay);
+    if (rc) return rc;
+    *bytes = align_up(lay.total, 256) + (size_t)n_rays * sizeof(TanEnd);
+    return MPATH_OK;
+}
+
+int mpath_cast_jacobian(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, float* jac,
+                        float* dz_dtheta, void* dev_ws, size_t ws_bytes, void* stream)
+{
+    int64_t n_rays;
+    std::vector<ObsDev> obs;
+    CastLayout lay;
+    int rc = cast_plan(g, d, &n_rays, obs, &lay);
+    if (rc) return rc;
+    if (d->order != 1 || d->stop_surface != MPATH_SURFACE_ETA || d->dphidl != MPATH_DPHIDL_CHAIN ||
+        d->n_surfaces != 0 || g->tdual)
+        return fail(MPATH_ERR_UNSUPPORTED, "the forward-mode Jacobian takes CIC casts to an iso-eta surface with the "
+                                           "chain-rule dPhi/dlambda, one stop surface and a static potential");
+    if (d->checkpoint_every != 0) return fail(MPATH_ERR_INVALID_ARG, "the forward-mode Jacobian stores no checkpoints");
+    if (!dev_ws) return fail(MPATH_ERR_INVALID_ARG, "dev_ws is NULL");
+    const size_t off = align_up(lay.total, 256);
+    if (ws_bytes < off + (size_t)n_rays * sizeof(TanEnd))
+        return fail(MPATH_ERR_WORKSPACE_TOO_SMALL, "jacobian workspace too small");
+    TangentOut tg;
+    tg.ends = (TanEnd*)((char*)dev_ws + off);
+    tg.jac = jac;
+    tg.dz_dtheta = dz_dtheta;
+    return cast_impl(g, d, out, dev_ws, ws_bytes, stream, false, nullptr, nullptr, &tg);
 }
 
 int mpath_infinitesimal_beam(const mpath_grid* g, const mpath_cast_desc* d, mpath_observables* out, float* A,

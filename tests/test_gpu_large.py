@@ -175,6 +175,36 @@ def test_large_adjoint_jacobian_sampled(M, large, grid, field):
     assert np.median(d) < 1e-6 and d.max() < 5e-6
 
 
+def test_large_full_sky_tangent_jacobian(M, large, grid, field):
+    """The distortion matrix of every ray of the full sky in one pass by
+    forward-mode tangents (no checkpoints); 24 rays (the 12 with the most
+    steps and 12 at random) against the oracle's complex-step Jacobian."""
+    import torch
+    w, cells = large
+    cfg = M.CastConfig(w.obs, w.z_src, w.nside, w.pix_first, w.pix_count, steps_per_cell=w.steps_per_cell,
+                       adaptive=w.adaptive)
+    torch.cuda.synchronize()
+    t = time.time()
+    out = M.jacobian(grid, cfg)
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    st = out["status"].cpu().numpy()
+    nst = out["n_steps"].cpu().numpy()
+    jac = out["jac"].cpu().numpy().astype(np.float64)
+    _print(f"full-sky tangent Jacobian: {w.n_rays} rays, {int(nst.astype(np.int64).sum())} ray-steps in "
+           f"{dt * 1e3:.0f} ms; finite {np.isfinite(jac).all()}")
+    assert (st == M.MPATH_RAY_REACHED).all() and np.isfinite(jac).all()
+    rng = np.random.default_rng(2029)
+    idx = np.unique(np.concatenate([np.argsort(nst)[-12:], rng.choice(w.n_rays, 12, replace=False)]))
+    dirs = O.pix2vec_nest(w.nside, idx)
+    p = O.params(w.obs[0], z_src=float(w.z_src[0]), steps_per_cell=w.steps_per_cell, adaptive=w.adaptive)
+    A, dz, o = O.jacobian_cs(lambda d, th: O.cast_cs(field, O.cosmo(*COSMO), p, d, dtheta=th), dirs)
+    assert (o["status"] == O.REACHED).all()
+    d = np.abs(jac[idx] - A).max(axis=(1, 2))
+    _print(f"tangent vs oracle on {len(idx)} rays: max |dA| {d.max():.3g}, median {np.median(d):.3g}")
+    assert np.median(d) < 1e-6 and d.max() < 5e-6
+
+
 @pytest.mark.skipif(os.environ.get("MPATH_TEST_LARGE_FULL_SKY") != "1",
                     reason="the full-sky adjoint (48 chunks) runs with MPATH_TEST_LARGE_FULL_SKY=1")
 def test_large_full_sky_adjoint(M, large, grid):
