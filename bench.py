@@ -246,13 +246,26 @@ def measure_adjoint(M, torch, dev):
                                                           cells=True, ws=res.get("_ws"))), reps=1)
     steps = int(outK["n_steps"].to(torch.int64).sum())
     bad = int((res["ray_status"] != 0).sum())
+    # the loss gradient alone (one cotangent column) and the distortion matrix
+    # by forward-mode tangents in the cast itself
+    res1 = {}
+    t_loss = _time_ms(torch, lambda: res1.update(M.adjoint(grid, cfgK, outK, dL_dalpha=alpha2, cells=True,
+                                                            ws=res1.get("_ws"))), reps=1)
+    outJ = M.alloc_outputs(w.n_rays, dev)
+    jres = {}
+    t_tan = _time_ms(torch, lambda: jres.update(M.jacobian(grid, cfg0, outJ, jres.get("_ws"))))
     log(f"[bench] adjoint: forward {t_fwd:.1f} ms, checkpointed forward {t_ckpt:.1f} ms, "
-        f"reverse sweep {t_adj:.1f} ms ({t_adj / t_fwd:.2f}x), {steps} ray-steps, {bad} rays not differentiated")
+        f"reverse sweep {t_adj:.1f} ms ({t_adj / t_fwd:.2f}x), {steps} ray-steps, {bad} rays not differentiated; "
+        f"loss-only reverse sweep {t_loss:.1f} ms ({t_loss / t_fwd:.2f}x); forward-mode distortion matrix "
+        f"{t_tan:.1f} ms ({t_tan / t_fwd:.2f}x)")
     return {"workload": "2^20 rays (nside 512) to z = 1 on the uniform 64^3 grid, 10 steps per cell, "
                         "checkpoint every 32 steps; A, dz/dtheta per ray and dL/dcells, L = sum |alpha|^2",
             "ray_steps": steps, "forward_ms": t_fwd, "checkpointed_forward_ms": t_ckpt,
             "reverse_ms": t_adj, "adjoint_forward_ratio": t_adj / t_fwd,
-            "forward_plus_adjoint_ratio": (t_ckpt + t_adj) / t_fwd, "rays_not_differentiated": bad}
+            "forward_plus_adjoint_ratio": (t_ckpt + t_adj) / t_fwd, "rays_not_differentiated": bad,
+            "reverse_loss_only_ms": t_loss, "reverse_loss_only_forward_ratio": t_loss / t_fwd,
+            "forward_mode_jacobian_ms": t_tan, "forward_mode_jacobian_forward_ratio": t_tan / t_fwd,
+            "jacobian_by_tangents_plus_loss_by_reverse_ratio": (t_tan + t_ckpt + t_loss) / t_fwd}
 
 
 def measure_batched(M, torch, dev):
@@ -577,6 +590,22 @@ def main():
         log(f"[bench] copy calibration: {nbytes} bytes copied")
         del src, dst
 
+    # the distortion matrix of every ray by forward-mode tangents, one pass
+    jac_line = None
+    if not args.no_secondary and w.adaptive:
+        jw = {}
+        torch.cuda.synchronize()
+        ev = _events(torch)
+        ev[0].record()
+        jw.update(M.jacobian(grid, cfg))
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_j = ev[0].elapsed_time(ev[1])
+        jac_line = {"ms": t_j, "forward_ms": float(np.mean(launch_ms)), "ratio_to_forward": t_j / float(np.mean(launch_ms)),
+                    "rays_per_s": n_rays / (t_j / 1e3), "all_finite": bool(torch.isfinite(jw["jac"]).all())}
+        log(f"[bench] forward-mode distortion matrix of all {n_rays} rays: {t_j:.0f} ms "
+            f"({jac_line['ratio_to_forward']:.2f}x the cast)")
+        del jw
     ceiling = None
     probe = None
     if not args.no_gather_probe:
@@ -612,6 +641,8 @@ def main():
         "grid_device_bytes": int(grid.ws.numel()),
         "roofline": roof,
     }
+    if jac_line is not None:
+        res["distortion_matrix_forward_mode"] = jac_line
     del grid, out
     torch.cuda.empty_cache()
     if not args.no_secondary:
@@ -627,7 +658,11 @@ def main():
         targets["forward_ge_0.6_of_measured_gather_ceiling"] = {"value": f, "pass": f >= 0.6}
     if "secondary" in res:
         r = res["adjoint_forward_ratio"]
-        targets["adjoint_le_3x_forward"] = {"value": r, "pass": r <= 3.0}
+        targets["adjoint_le_3x_forward"] = {"value": r, "pass": r <= 3.0,
+                                            "what": "reverse sweep (distortion matrix and cell gradient) / cast"}
+        r = res["secondary"]["adjoint"]["forward_mode_jacobian_forward_ratio"]
+        targets["distortion_matrix_le_3x_forward"] = {"value": r, "pass": r <= 3.0,
+                                                      "what": "forward-mode distortion matrix / cast"}
         b = res["secondary"]["batched"]["speedup_vs_one_cone_per_launch"]
         targets["batched_ge_2x_one_cone_per_launch"] = {"value": b, "pass": b >= 2.0}
     res["targets"] = targets
