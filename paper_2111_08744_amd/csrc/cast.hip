@@ -1206,7 +1206,7 @@ hipError_t launch_cast_order(const CastArgs& a, int order, hipStream_t s)
 {
     if (a.n_rays == 0) return hipSuccess;
     const int64_t blocks = (a.n_rays + kBlock - 1) / kBlock;
-    const size_t lds = order == 2 ? (size_t)27 * kBlock * sizeof(int) : 0;
+    const size_t lds = 0;
     const dim3 grid((unsigned)blocks), block(kBlock);
     const bool amr = a.grid.max_level > 0;
     if (order == 0) {

@@ -496,9 +496,10 @@ struct NgpCache {
 // the cell containing the point at the leaf level, falling back one level at
 // a time while any of them is missing.  The stencil depends only on the leaf
 // cell (the cell containing the point at every coarser level is its
-// ancestor), so the lane keeps the 27 ids of its leaf's stencil in LDS and
-// resolves them again only when the leaf changes.  Per axis, with f the
-// position in the centre cell (in [0, 1)), the weights of the cells at
+// ancestor), so the lane resolves it (27 octree lookups) only when the leaf
+// changes and keeps the 27 payloads in registers: a stage then costs its
+// weights and 108 multiply-adds, with no memory access.  Per axis, with f
+// the position in the centre cell (in [0, 1)), the weights of the cells at
 // -1, 0, +1 are (1 - f)^2 / 2, 3/4 - (f - 1/2)^2 and f^2 / 2.
 template <bool AMR>
 struct TscCache {
@@ -508,9 +509,9 @@ struct TscCache {
     int key[3];         // its unwrapped coordinates at that level
     int lvl;            // level of the stencil (-1: not resolved for this leaf)
     int c[3];           // centre cell of the stencil, unwrapped, at level lvl
-    int* ids;           // LDS: id of stencil cell q at ids[q * kBlock]
+    float4 p[27];       // payloads of stencil cell q = (x + 1) + 3 (y + 1) + 9 (z + 1)
 
-    __device__ __forceinline__ void bind(float* lds) { ids = reinterpret_cast<int*>(lds); }
+    __device__ __forceinline__ void bind(float*) {}
     __device__ __forceinline__ void reset()
     {
         keyL = 0;
@@ -539,11 +540,14 @@ struct TscCache {
         for (int l = L; l >= 0; --l) {
             const int s = Lm + 1 - l;
             const int c0 = I[0] >> s, c1 = I[1] >> s, c2 = I[2] >> s;
+            // each payload is loaded as soon as its cell is found (cell 0
+            // stands in for a missing one: its level is refused below)
             bool all = true;
-            for (int q = 0; q < 27 && all; ++q) {
+#pragma unroll
+            for (int q = 0; q < 27; ++q) {
                 const int id = lookup_cell(g, l, c0 + q % 3 - 1, c1 + (q / 3) % 3 - 1, c2 + q / 9 - 1);
-                ids[q * kBlock] = id;
-                all = id >= 0;
+                all = all && id >= 0;
+                p[q] = g.payload[id >= 0 ? id : 0];
             }
             if (all) {
                 lvl = l;
@@ -586,11 +590,11 @@ struct TscCache {
 #pragma unroll
                 for (int x = 0; x < 3; ++x) {
                     const float wq = w[0][x] * wyz;
-                    const float4 p = g.payload[ids[(x + 3 * y + 9 * z) * kBlock]];
-                    acc[0] = fmaf(wq, p.x, acc[0]);
-                    acc[1] = fmaf(wq, p.y, acc[1]);
-                    acc[2] = fmaf(wq, p.z, acc[2]);
-                    acc[3] = fmaf(wq, p.w, acc[3]);
+                    const float4 q = p[x + 3 * y + 9 * z];
+                    acc[0] = fmaf(wq, q.x, acc[0]);
+                    acc[1] = fmaf(wq, q.y, acc[1]);
+                    acc[2] = fmaf(wq, q.z, acc[2]);
+                    acc[3] = fmaf(wq, q.w, acc[3]);
                 }
             }
         phi = acc[0];
