@@ -152,7 +152,7 @@ __device__ inline double scale_factor(const CosmoDev& c, double eta)
 
 // Id of cell (l, J) or -1 if it does not exist: coarse ancestor by Morton
 // index, then one child link per level.
-__device__ __forceinline__ int lookup_cell(const GridDev& g, int l, int J0, int J1, int J2)
+__host__ __device__ __forceinline__ int lookup_cell(const GridDev& g, int l, int J0, int J1, int J2)
 {
     const int M = g.n0 << l;
     if (g.periodic) {
@@ -496,8 +496,8 @@ struct NgpCache {
 // the cell containing the point at the leaf level, falling back one level at
 // a time while any of them is missing.  The stencil depends only on the leaf
 // cell (the cell containing the point at every coarser level is its
-// ancestor), so the lane resolves it (27 octree lookups) only when the leaf
-// changes and keeps the 27 payloads in registers: a stage then costs its
+// ancestor), so the lane resolves it only when the leaf changes and keeps
+// the 27 payloads in registers: a stage then costs its
 // weights and 108 multiply-adds, with no memory access.  Per axis, with f
 // the position in the centre cell (in [0, 1)), the weights of the cells at
 // -1, 0, +1 are (1 - f)^2 / 2, 3/4 - (f - 1/2)^2 and f^2 / 2.
@@ -534,27 +534,97 @@ struct TscCache {
         return L;
     }
 
+    // Load the payloads of the 27 cells cc + {-1, 0, 1}^3 at level l when
+    // all of them exist; false otherwise (nothing is loaded).  Level 0: the
+    // Morton id is the OR of one bit spread per axis, so 9 spreads give the
+    // 27 ids.  Refined level: the 27 cells have 2 x 2 x 2 parents (two per
+    // axis, the parents of cc - 1 and cc + 1); each cell is its parent's
+    // first child plus its octant, so 8 walks to level l - 1 replace 27
+    // walks to level l.
+    __host__ __device__ __forceinline__ bool gather(const GridDev& g, int l, const int cc[3])
+    {
+        if (!AMR || l == 0) {
+            const int M = g.n0;
+            uint32_t sp[3][3];
+            bool all = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int J = cc[d] + a - 1;
+                    all &= g.periodic || (unsigned)J < (unsigned)M;
+                    sp[d][a] = part1by2((uint32_t)(J & (M - 1))) << d;
+                }
+            if (!all) return false;
+#pragma unroll
+            for (int q = 0; q < 27; ++q) p[q] = g.payload[sp[0][q % 3] | sp[1][(q / 3) % 3] | sp[2][q / 9]];
+            return true;
+        }
+        // per axis: the two parents, which of them holds the middle cell, and
+        // the octant bit of the outer cells (cc -+ 1) and of the middle one
+        int P[3][2], mid[3], bo[3], bm[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            P[d][0] = (cc[d] - 1) >> 1;
+            P[d][1] = (cc[d] + 1) >> 1;
+            mid[d] = (cc[d] >> 1) - P[d][0];
+            bo[d] = (cc[d] + 1) & 1;
+            bm[d] = cc[d] & 1;
+        }
+        int ch[8];
+        bool all = true;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int par = lookup_cell(g, l - 1, P[0][s & 1], P[1][(s >> 1) & 1], P[2][s >> 2]);
+            const int k = g.child[par >= 0 ? par : 0];
+            ch[s] = par >= 0 ? k : -1;
+            all &= ch[s] >= 0;
+        }
+        if (!all) return false;
+        // first child of the parent of every cell, selected along z, y, x
+        int t[2][2][3], u[2][3][3];
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx)
+#pragma unroll
+            for (int sy = 0; sy < 2; ++sy) {
+                t[sx][sy][0] = ch[sx + 2 * sy];
+                t[sx][sy][2] = ch[sx + 2 * sy + 4];
+                t[sx][sy][1] = mid[2] ? t[sx][sy][2] : t[sx][sy][0];
+            }
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx)
+#pragma unroll
+            for (int z = 0; z < 3; ++z) {
+                u[sx][0][z] = t[sx][0][z];
+                u[sx][2][z] = t[sx][1][z];
+                u[sx][1][z] = mid[1] ? u[sx][2][z] : u[sx][0][z];
+            }
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            const int x = q % 3, y = (q / 3) % 3, z = q / 9;
+            const int first = x == 0 ? u[0][y][z] : x == 2 ? u[1][y][z] : (mid[0] ? u[1][y][z] : u[0][y][z]);
+            const int oct = (x == 1 ? bm[0] : bo[0]) | ((y == 1 ? bm[1] : bo[1]) << 1) | ((z == 1 ? bm[2] : bo[2]) << 2);
+            p[q] = g.payload[first + oct];
+        }
+        return true;
+    }
+
     __device__ __forceinline__ bool resolve(const GridDev& g, int L, const int I[3])
     {
         const int Lm = AMR ? g.max_level : 0;
         for (int l = L; l >= 0; --l) {
             const int s = Lm + 1 - l;
-            const int c0 = I[0] >> s, c1 = I[1] >> s, c2 = I[2] >> s;
-            // each payload is loaded as soon as its cell is found (cell 0
-            // stands in for a missing one: its level is refused below)
-            bool all = true;
-#pragma unroll
-            for (int q = 0; q < 27; ++q) {
-                const int id = lookup_cell(g, l, c0 + q % 3 - 1, c1 + (q / 3) % 3 - 1, c2 + q / 9 - 1);
-                all = all && id >= 0;
-                p[q] = g.payload[id >= 0 ? id : 0];
-            }
-            if (all) {
+            const int cc[3] = {I[0] >> s, I[1] >> s, I[2] >> s};
+            if (gather(g, l, cc)) {
                 lvl = l;
-                c[0] = c0; c[1] = c1; c[2] = c2;
+                c[0] = cc[0]; c[1] = cc[1]; c[2] = cc[2];
                 return true;
             }
         }
+        // no stencil (the ray stops): the payloads are cleared so that every
+        // path writes them, and the old ones need no registers during the search
+#pragma unroll
+        for (int q = 0; q < 27; ++q) p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         return false;
     }
 
