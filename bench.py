@@ -665,6 +665,10 @@ def main():
                                                       "what": "forward-mode distortion matrix / cast"}
         b = res["secondary"]["batched"]["speedup_vs_one_cone_per_launch"]
         targets["batched_ge_2x_one_cone_per_launch"] = {"value": b, "pass": b >= 2.0}
+        o = res["secondary"]["orders"]
+        for grid in ("uniform", "amr"):
+            r = o[grid]["tsc"]["ms"] / o[grid]["cic"]["ms"]
+            targets[f"tsc_le_3x_cic_{grid}"] = {"value": r, "pass": r <= 3.0, "what": "TSC cast time / CIC cast time"}
     res["targets"] = targets
     if not args.no_cpu_baseline:
         threads, nproc, model = host_cores()

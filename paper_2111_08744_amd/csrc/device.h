@@ -835,7 +835,7 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
 #pragma unroll 1
     for (int st = 0; st < 4; ++st) failed |= stage(st);
     if (failed) return 1;
-    const double h6 = dl / 6.0;
+    const double h6 = dl * (1.0 / 6.0);
     out.eta = fma(h6, acc_eta, y.eta);
     out.K = fma(h6, acc_K, y.K);
     const float h6f = (float)h6;

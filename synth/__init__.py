@@ -2,9 +2,11 @@
 
 This module only *draws* inputs: cell lists of an octree carrying a potential
 and its gradient, observer positions, source redshifts and sky-pixel ranges.
-It contains none of the ray-tracing arithmetic (no geodesics, interpolation,
-cosmology or HEALPix geometry); both implementations of the method receive
-what is built here as plain arrays.
+It contains none of the ray-tracing arithmetic (no geodesics, field
+evaluation along rays, cosmology or HEALPix geometry); both implementations
+of the method receive what is built here as plain arrays.  The one
+interpolation it does, a periodic trilinear sampling of the coarse
+potential, only sets the values of refined cells when a tree is drawn.
 
 Every generator takes an explicit seed and uses numpy's PCG64 stream, so the
 same call gives bit-identical arrays on every machine with this image.
