@@ -272,9 +272,12 @@ struct FieldCache {
             return 0;
         }
         const int Lm = g.max_level;
-        if (keyL >= 0) {
+        {
+            // the cached leaf (comparisons combined without branches; with
+            // nothing cached, keyL = -1 and the shift stays below 32)
             const int sh = Lm + 1 - keyL;
-            if ((I[0] >> sh) == (key[0] >> 1) && (I[1] >> sh) == (key[1] >> 1) && (I[2] >> sh) == (key[2] >> 1))
+            if ((keyL >= 0) & ((I[0] >> sh) == (key[0] >> 1)) & ((I[1] >> sh) == (key[1] >> 1)) &
+                ((I[2] >> sh) == (key[2] >> 1)))
                 return keyL;
         }
         int J0 = I[0] >> 1, J1 = I[1] >> 1, J2 = I[2] >> 1;   // level max_level
@@ -304,7 +307,7 @@ struct FieldCache {
         const int Lm = AMR ? g.max_level : 0;
         const int sh = Lm - L;                   // I is at level Lm + 1
         const int k0 = I[0] >> sh, k1 = I[1] >> sh, k2 = I[2] >> sh;
-        if (keyL == L && k0 == key[0] && k1 == key[1] && k2 == key[2]) return true;
+        if ((keyL == L) & (k0 == key[0]) & (k1 == key[1]) & (k2 == key[2])) return true;
         int base, l;
         // a point in a leaf of level 0 takes the level-0 stencil (or none at
         // the edge of a non-periodic box), whose base follows from the Morton
@@ -361,8 +364,8 @@ struct FieldCache {
         for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
         int L;
         bool bad = false;
-        if (AMR && keyL >= 0 && (I[0] >> (Lm - keyL)) == key[0] && (I[1] >> (Lm - keyL)) == key[1] &&
-            (I[2] >> (Lm - keyL)) == key[2]) {
+        const int shk = Lm - keyL;   // keyL = -1 (nothing cached): Lm + 1, below 32
+        if (AMR && ((keyL >= 0) & ((I[0] >> shk) == key[0]) & ((I[1] >> shk) == key[1]) & ((I[2] >> shk) == key[2]))) {
             // same half-cell of the same leaf as the cached stencil
             L = keyL;
         } else if constexpr (!ONE_EXIT) {
