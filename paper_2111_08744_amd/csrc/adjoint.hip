@@ -544,7 +544,7 @@ __device__ __forceinline__ bool plan_step(const CastArgs& a, FieldCache<AMR>& F,
     for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
     const int L = F.leaf(g, I);
     if (L < 0) return false;
-    ds = a.ds_level[L];
+    ds = step_length(a, L);
     dl = ds / y.K;
     landing = fma(-y.K, dl, y.eta) < eta_s;
     return true;

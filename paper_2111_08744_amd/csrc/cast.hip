@@ -122,7 +122,7 @@ struct RayRun {
                 if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
                 hash = fnv(hash, (uint32_t)L);
                 smp.at_step(a, geo, y, L);
-                const double dl = a.ds_level[L] / y.K;
+                const double dl = step_length(a, L) / y.K;
                 if (fma(-y.K, dl, y.eta) < eta_s) break;
                 GeoState yn;
                 if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dl, yn, hash, dp)) {
@@ -224,7 +224,7 @@ struct RayRun {
             const int L = F.leaf(g, I);
             if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return; }
             hash = fnv(hash, (uint32_t)L);
-            const double dl = a.ds_level[L] / y.K;
+            const double dl = step_length(a, L) / y.K;
             GeoState yn;
             if constexpr (SURF == MPATH_SURFACE_LAMBDA) {
                 if (lam + dl >= p_s) {
@@ -309,7 +309,7 @@ struct RayRun {
             const int L = F.leaf(g, I);
             if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return; }
             hash = fnv(hash, (uint32_t)L);
-            const double dl = a.ds_level[L] / y.K;
+            const double dl = step_length(a, L) / y.K;
             if (fma(-y.K, dl, y.eta) < eta_s) break;
             GeoState yn;
             T.begin_step(y, dl, true);
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(kBlock, 2) void born_beam_kernel(CastArgs a, float*
         B.at_step(a, geo, y, L);
         if (chi >= chis) { status = MPATH_RAY_REACHED; break; }
         if (steps >= a.max_steps) break;
-        const double ds = a.ds_level[L];
+        const double ds = step_length(a, L);
         chi = chi + ds < chis ? chi + ds : chis;
     }
     B.write(A + 4 * r, status == MPATH_RAY_REACHED);

@@ -695,6 +695,15 @@ struct RayGeom {
     double n[3];        // initial direction (unit)
 };
 
+// Comoving step length in a leaf of level L: h_L / N = ds_level[L], which
+// equals ds_level[0] 2^-L exactly (h0 / 2^L / N rounds like h0 / N, and the
+// power of two scales exactly); computed so, since indexing the argument
+// array by a per-lane level would be a memory load at every step.
+__device__ __forceinline__ double step_length(const CastArgs& a, int L)
+{
+    return a.adaptive ? ldexp(a.ds_level[0], -L) : a.ds_level[0];
+}
+
 // Fine-grid coordinates v = x / h_f, h_f = h0 / 2^(max_level + 1), of
 // x = x_obs + s n + dx, s = eta0 - eta.  The observer term is the exact
 // quotient; the displacement is scaled by 1/h_f (at the observer both agree

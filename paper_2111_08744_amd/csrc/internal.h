@@ -123,7 +123,8 @@ struct CastArgs {
     int32_t nside;
     int32_t steps_per_cell;
     int32_t adaptive;
-    double ds_level[kMaxLevels + 1];  // comoving step length h_l / N (h_0 / N on every level if not adaptive)
+    double ds_level[kMaxLevels + 1];  // comoving step length h_l / N (h_0 / N on every level if not adaptive);
+                                      // kernels read it through step_length()
     int64_t max_steps;
     int64_t n_rays;
     OutDev out;
