@@ -326,7 +326,25 @@ struct FieldCache {
                        (unsigned)b2 >= (unsigned)(M - 1)) {
                 return false;                     // b + 1 must exist too
             }
-            base = (int)morton3((uint32_t)b0, (uint32_t)b1, (uint32_t)b2);
+            if constexpr (AMR) {
+                // the leaf is the coarse cell J = k >> 1, whose id leafId is
+                // its Morton index, and b = J - 1 + (k & 1): the base id is
+                // leafId with the dilated coordinate of every axis of even k
+                // decremented, masked to the grid's bits (which wraps a
+                // periodic grid like b & (M - 1))
+                const uint32_t bits = (1u << (3 * __builtin_ctz((unsigned)M))) - 1u;
+                const int kk[3] = {k0, k1, k2};
+                uint32_t m = (uint32_t)leafId;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const uint32_t md = (0x49249249u << d) & bits;
+                    const uint32_t dec = (m & ~md) | (((m & md) - (1u << d)) & md);
+                    m = (kk[d] & 1) ? m : dec;
+                }
+                base = (int)m;
+            } else {
+                base = (int)morton3((uint32_t)b0, (uint32_t)b1, (uint32_t)b2);
+            }
         }
         this->base = base;
         const float4* rec = g.dual + 8 * (int64_t)base;
