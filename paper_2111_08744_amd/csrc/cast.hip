@@ -106,26 +106,31 @@ struct RayRun {
         const GridDev& g = a.grid;
         int it = 0;
         for (;;) {
+            // the field at the step start (stage 0 of the step, and of every
+            // landing pass, which all start there)
+            Stage0 s0;
             // regular steps up to the one that would cross the stop surface
             for (;; ++it) {
                 if (it >= max_iter) return false;
                 if (n_steps >= a.max_steps) { status = MPATH_RAY_MAX_STEPS; return true; }
                 if (CKPT && n_steps % a.ckpt_every == 0)
                     a.ckpt[(n_steps / a.ckpt_every) * a.n_rays + ray] = y;
-                // leaf level at the step start sets the step length (N steps per cell)
+                // leaf level at the step start sets the step length (N steps
+                // per cell); the same evaluation gives stage 0's field
                 double v[3];
                 grid_coords(g, geo, y.eta, y.dx, v);
-                int I[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
-                const int L = F.leaf(g, I);
+                int L;
+                s0.phi = s0.G[0] = s0.G[1] = s0.G[2] = 0.0f;
+                s0.l = 0;
+                s0.bad = F.eval(g, v, s0.phi, s0.G, L, s0.l);
+                if constexpr (FC::kTime) s0.tv = F.tv;
                 if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
                 hash = fnv(hash, (uint32_t)L);
                 smp.at_step(a, geo, y, L);
                 const double dl = step_length(a, L) / y.K;
                 if (fma(-y.K, dl, y.eta) < eta_s) break;
                 GeoState yn;
-                if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dl, yn, hash, dp)) {
+                if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dl, yn, hash, dp, &s0)) {
                     status = MPATH_RAY_LEFT_DOMAIN;
                     return true;
                 }
@@ -144,7 +149,7 @@ struct RayRun {
             double dlx = (y.eta - eta_s) / y.K;
             GeoState yn;
             for (int k = 0; k < 3; ++k) {
-                if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dlx, yn, hash, dp)) {
+                if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dlx, yn, hash, dp, &s0)) {
                     status = MPATH_RAY_LEFT_DOMAIN;
                     return true;
                 }

@@ -768,6 +768,15 @@ struct NoRecord {
     }
 };
 
+// The field at a step's start point, evaluated by the caller (which needs
+// the leaf level there for the step length): stage 0 of the step then
+// takes it instead of evaluating the same point again.
+struct Stage0 {
+    float phi, G[3], tv;   // tv: dPhi/deta (time-dependent potential)
+    int l;                 // stencil level
+    int bad;               // no complete stencil
+};
+
 // One RK4 step of affine length dl from y into out (F: the lane's field
 // evaluator, any interpolation order).  With a time-dependent potential
 // (FC::kTime) the spatial equation takes dPhi/dl = grad Phi . k + T k0 with
@@ -780,7 +789,8 @@ struct NoRecord {
 template <class FC, class Rec, class DP>
 __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
-                                        uint32_t& hash, Rec& rec, bool record, DP& dp)
+                                        uint32_t& hash, Rec& rec, bool record, DP& dp,
+                                        const Stage0* s0 = nullptr)
 {
     #pragma clang fp contract(off)
     const float nf[3] = {(float)r.n[0], (float)r.n[1], (float)r.n[2]};
@@ -796,7 +806,7 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
     // remaining stages then run on meaningless values, every lookup staying
     // in bounds, and the step is rejected after the loop, so that the loop
     // has a single exit)
-    auto stage = [&](const int st) -> bool {
+    auto stage = [&](const int st, const Stage0* z) -> bool {
         #pragma clang fp contract(off)
         GeoState yi;
         if (st == 0) {
@@ -817,11 +827,22 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
                 yi.d[i] = fmaf(cK, f_P[i], fmaf(rm1, y.d[i], y.d[i]));
             }
         }
-        double u[3];
-        grid_coords(g, r, yi.eta, yi.dx, u);
         float phi = 0.0f, G[3] = {0.0f, 0.0f, 0.0f};
-        int leafl, l = 0;
-        const bool bad = F.eval(g, u, phi, G, leafl, l) != 0;
+        int l = 0;
+        bool bad;
+        if (z) {
+            // stage 0 at the step start, evaluated by the caller
+            phi = z->phi;
+            G[0] = z->G[0]; G[1] = z->G[1]; G[2] = z->G[2];
+            l = z->l;
+            bad = z->bad != 0;
+            if constexpr (FC::kTime) F.tv = z->tv;
+        } else {
+            double u[3];
+            grid_coords(g, r, yi.eta, yi.dx, u);
+            int leafl;
+            bad = F.eval(g, u, phi, G, leafl, l) != 0;
+        }
         h = fnv(h, (uint32_t)l);
         if (record) rec.stage(st, y, yi, F, G, Hc, cz);
         const double H = Hc(cz, yi.eta);
@@ -861,9 +882,9 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
         }
         return bad;
     };
-    bool failed = false;
+    bool failed = stage(0, s0);
 #pragma unroll 1
-    for (int st = 0; st < 4; ++st) failed |= stage(st);
+    for (int st = 1; st < 4; ++st) failed |= stage(st, nullptr);
     if (failed) return 1;
     const double h6 = dl * (1.0 / 6.0);
     out.eta = fma(h6, acc_eta, y.eta);
@@ -904,10 +925,10 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC
 template <class FC, class DP>
 __device__ __forceinline__ int rk4_step_dp(const GridDev& g, const CosmoDev& cz, FC& F,
                                            const RayGeom& r, const GeoState& y, double dl, GeoState& out,
-                                           uint32_t& hash, DP& dp)
+                                           uint32_t& hash, DP& dp, const Stage0* s0 = nullptr)
 {
     NoRecord none;
-    return rk4_core<FC, NoRecord, DP>(g, cz, F, r, y, dl, out, hash, none, false, dp);
+    return rk4_core<FC, NoRecord, DP>(g, cz, F, r, y, dl, out, hash, none, false, dp, s0);
 }
 
 // NaN or infinity anywhere in the state (a sum of the small FP32 parts is
