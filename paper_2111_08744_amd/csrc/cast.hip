@@ -104,6 +104,9 @@ struct RayRun {
     {
         if (status >= 0) return true;
         const GridDev& g = a.grid;
+        // plain casts peel stage 0 (the step start's field evaluation serves
+        // it); the sampling casts keep the shorter code of the plain loop
+        constexpr bool kPeel = std::is_same<Smp, NoSample>::value;
         int it = 0;
         for (;;) {
             // the field at the step start (stage 0 of the step, and of every
@@ -120,17 +123,24 @@ struct RayRun {
                 double v[3];
                 grid_coords(g, geo, y.eta, y.dx, v);
                 int L;
-                s0.phi = s0.G[0] = s0.G[1] = s0.G[2] = 0.0f;
-                s0.l = 0;
-                s0.bad = F.eval(g, v, s0.phi, s0.G, L, s0.l);
-                if constexpr (FC::kTime) s0.tv = F.tv;
+                if constexpr (kPeel) {
+                    s0.phi = s0.G[0] = s0.G[1] = s0.G[2] = 0.0f;
+                    s0.l = 0;
+                    s0.bad = F.eval(g, v, s0.phi, s0.G, L, s0.l);
+                    if constexpr (FC::kTime) s0.tv = F.tv;
+                } else {
+                    int I[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
+                    L = F.leaf(g, I);
+                }
                 if (L < 0) { status = MPATH_RAY_LEFT_DOMAIN; return true; }
                 hash = fnv(hash, (uint32_t)L);
                 smp.at_step(a, geo, y, L);
                 const double dl = step_length(a, L) / y.K;
                 if (fma(-y.K, dl, y.eta) < eta_s) break;
                 GeoState yn;
-                if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dl, yn, hash, dp, &s0)) {
+                if (rk4_step_dp<FC, DP, kPeel>(g, a.cosmo, F, geo, y, dl, yn, hash, dp, &s0)) {
                     status = MPATH_RAY_LEFT_DOMAIN;
                     return true;
                 }
@@ -149,7 +159,7 @@ struct RayRun {
             double dlx = (y.eta - eta_s) / y.K;
             GeoState yn;
             for (int k = 0; k < 3; ++k) {
-                if (rk4_step_dp<FC, DP>(g, a.cosmo, F, geo, y, dlx, yn, hash, dp, &s0)) {
+                if (rk4_step_dp<FC, DP, kPeel>(g, a.cosmo, F, geo, y, dlx, yn, hash, dp, &s0)) {
                     status = MPATH_RAY_LEFT_DOMAIN;
                     return true;
                 }

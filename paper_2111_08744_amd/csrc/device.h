@@ -769,8 +769,10 @@ struct NoRecord {
 };
 
 // The field at a step's start point, evaluated by the caller (which needs
-// the leaf level there for the step length): stage 0 of the step then
-// takes it instead of evaluating the same point again.
+// the leaf level there for the step length): with PEEL, stage 0 of the step
+// runs before the stage loop and takes it instead of evaluating the same
+// point again.  (Peeling lengthens the code; kernels whose registers are
+// tight keep the plain loop.)
 struct Stage0 {
     float phi, G[3], tv;   // tv: dPhi/deta (time-dependent potential)
     int l;                 // stencil level
@@ -786,7 +788,7 @@ struct Stage0 {
 // are appended to hash only when all four stages succeed (return 0).  When
 // record is set, the recorder receives every stage's state and stencil (base
 // id, level); the reverse sweep uses it to replay the forward stages exactly.
-template <class FC, class Rec, class DP>
+template <class FC, class Rec, class DP, bool PEEL = false>
 __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
                                         uint32_t& hash, Rec& rec, bool record, DP& dp,
@@ -882,9 +884,15 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
         }
         return bad;
     };
-    bool failed = stage(0, s0);
+    bool failed = false;
+    if constexpr (PEEL) {
+        failed = stage(0, s0);
 #pragma unroll 1
-    for (int st = 1; st < 4; ++st) failed |= stage(st, nullptr);
+        for (int st = 1; st < 4; ++st) failed |= stage(st, nullptr);
+    } else {
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) failed |= stage(st, nullptr);
+    }
     if (failed) return 1;
     const double h6 = dl * (1.0 / 6.0);
     out.eta = fma(h6, acc_eta, y.eta);
@@ -922,13 +930,13 @@ __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC
 }
 
 // The forward step with a choice of dPhi/dl (ChainRule or StepDifference).
-template <class FC, class DP>
+template <class FC, class DP, bool PEEL = false>
 __device__ __forceinline__ int rk4_step_dp(const GridDev& g, const CosmoDev& cz, FC& F,
                                            const RayGeom& r, const GeoState& y, double dl, GeoState& out,
                                            uint32_t& hash, DP& dp, const Stage0* s0 = nullptr)
 {
     NoRecord none;
-    return rk4_core<FC, NoRecord, DP>(g, cz, F, r, y, dl, out, hash, none, false, dp, s0);
+    return rk4_core<FC, NoRecord, DP, PEEL>(g, cz, F, r, y, dl, out, hash, none, false, dp, s0);
 }
 
 // NaN or infinity anywhere in the state (a sum of the small FP32 parts is
