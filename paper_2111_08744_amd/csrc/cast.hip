@@ -328,7 +328,7 @@ struct RayRun {
             if (fma(-y.K, dl, y.eta) < eta_s) break;
             GeoState yn;
             T.begin_step(y, dl, true);
-            if (rk4_core<FC, Tan, ChainRule>(g, a.cosmo, F, geo, y, dl, yn, hash, T, true, cr)) {
+            if (rk4_core<FC, Tan, ChainRule, true>(g, a.cosmo, F, geo, y, dl, yn, hash, T, true, cr)) {
                 status = MPATH_RAY_LEFT_DOMAIN;
                 return;
             }
@@ -342,7 +342,7 @@ struct RayRun {
         GeoState yn;
         for (int k = 0; k < 3; ++k) {
             if (k == 2) T.begin_step(y, dlx, false);
-            if (rk4_core<FC, Tan, ChainRule>(g, a.cosmo, F, geo, y, dlx, yn, hash, T, k == 2, cr)) {
+            if (rk4_core<FC, Tan, ChainRule, true>(g, a.cosmo, F, geo, y, dlx, yn, hash, T, k == 2, cr)) {
                 status = MPATH_RAY_LEFT_DOMAIN;
                 return;
             }
