@@ -177,7 +177,7 @@ struct RayCtx {
 template <bool AMR>
 __device__ __forceinline__ void stencil_coefs(const GridDev& g, const FieldCache<AMR>& F, int base, float c[32])
 {
-    if (F.keyL >= 0 && F.base == base) {
+    if ((F.keyL >= 0) & (F.base == base)) {
 #pragma unroll
         for (int i = 0; i < 32; ++i) c[i] = F.c[i * FieldCache<AMR>::cstride];
     } else {
@@ -531,18 +531,19 @@ __device__ __forceinline__ void scatter_phi(const AdjointArgs& A, int base, cons
 }
 
 // Step length and landing decision at the start of a step, exactly as the
-// forward kernels take them.
+// forward kernels take them; the field there (stage 0 of the step) into s0.
 template <bool AMR>
 __device__ __forceinline__ bool plan_step(const CastArgs& a, FieldCache<AMR>& F, const RayGeom& geo,
-                                          const GeoState& y, double eta_s, double& ds, double& dl, bool& landing)
+                                          const GeoState& y, double eta_s, double& ds, double& dl, bool& landing,
+                                          Stage0& s0)
 {
     const GridDev& g = a.grid;
     double v[3];
     grid_coords(g, geo, y.eta, y.dx, v);
-    int I[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) I[d] = (int)floor(v[d]);
-    const int L = F.leaf(g, I);
+    int L;
+    s0.phi = s0.G[0] = s0.G[1] = s0.G[2] = s0.tv = 0.0f;
+    s0.l = 0;
+    s0.bad = F.eval(g, v, s0.phi, s0.G, L, s0.l);
     if (L < 0) return false;
     ds = step_length(a, L);
     dl = ds / y.K;
@@ -559,18 +560,25 @@ __device__ __forceinline__ bool forward_step(const CastArgs& a, FieldCache<AMR>&
                                              double& dl_taken, double& ds_out, bool& landing)
 {
     double ds, dl;
-    if (!plan_step<AMR>(a, F, geo, y, eta_s, ds, dl, landing)) return false;
+    Stage0 s0;
+    if (!plan_step<AMR>(a, F, geo, y, eta_s, ds, dl, landing, s0)) return false;
     uint32_t h = 0;
     ds_out = ds;
     if (__builtin_expect(!landing, 1)) {
-        if (rk4_step<FieldCache<AMR>, Rec>(a.grid, a.cosmo, F, geo, y, dl, yn, h, rec, record)) return false;
+        // the recorder of stage 0 sees the lane's cache as plan_step left it
+        if (rk4_step<FieldCache<AMR>, Rec, true>(a.grid, a.cosmo, F, geo, y, dl, yn, h, rec, record, &s0))
+            return false;
         dl_taken = dl;
         return true;
     }
-    // landing: two Newton passes for the step length, then the step
+    // landing: two Newton passes for the step length, then the step (a
+    // recorded pass evaluates its stage 0 again, since the passes before it
+    // moved the lane's cache)
     double dlx = (y.eta - eta_s) / y.K;
     for (int k = 0; k < 3; ++k) {
-        if (rk4_step<FieldCache<AMR>, Rec>(a.grid, a.cosmo, F, geo, y, dlx, yn, h, rec, record && k == 2))
+        const bool rec_pass = record && k == 2;
+        if (rk4_step<FieldCache<AMR>, Rec, true>(a.grid, a.cosmo, F, geo, y, dlx, yn, h, rec, rec_pass,
+                                                 rec_pass ? nullptr : &s0))
             return false;
         if (k < 2) dlx = dlx + (yn.eta - eta_s) / yn.K;
     }

@@ -911,13 +911,13 @@ __device__ __forceinline__ int rk4_core(const GridDev& g, const CosmoDev& cz, FC
     return 0;
 }
 
-template <class FC, class Rec>
+template <class FC, class Rec, bool PEEL = false>
 __device__ __forceinline__ int rk4_step(const GridDev& g, const CosmoDev& cz, FC& F,
                                         const RayGeom& r, const GeoState& y, double dl, GeoState& out,
-                                        uint32_t& hash, Rec& rec, bool record)
+                                        uint32_t& hash, Rec& rec, bool record, const Stage0* s0 = nullptr)
 {
     ChainRule cr;
-    return rk4_core<FC, Rec, ChainRule>(g, cz, F, r, y, dl, out, hash, rec, record, cr);
+    return rk4_core<FC, Rec, ChainRule, PEEL>(g, cz, F, r, y, dl, out, hash, rec, record, cr, s0);
 }
 
 template <class FC>
