@@ -172,21 +172,18 @@ struct RayCtx {
     double xobs[3];
 };
 
-// Trilinear coefficients (component-major: c[8 q + k]) of a stencil: from the
-// lane's LDS cache when it holds that stencil, else from the dual table.
-template <bool AMR>
-__device__ __forceinline__ void stencil_coefs(const GridDev& g, const FieldCache<AMR>& F, int base, float c[32])
+// Trilinear coefficients (component-major: c[8 q + k]) of a stencil, read
+// from the dual table.  (The lane's LDS copy holds only the stencil of the
+// replay's last stage; choosing between the two per lane made a wave wait
+// for the table whenever any of its lanes missed, and the records of a
+// step's stencils are in the caches after its replay.)
+__device__ __forceinline__ void stencil_coefs(const GridDev& g, int base, float c[32])
 {
-    if ((F.keyL >= 0) & (F.base == base)) {
+    const float4* rec = g.dual + 8 * (int64_t)base;
 #pragma unroll
-        for (int i = 0; i < 32; ++i) c[i] = F.c[i * FieldCache<AMR>::cstride];
-    } else {
-        const float4* rec = g.dual + 8 * (int64_t)base;
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const float4 q = rec[o];
-            c[o] = q.x; c[8 + o] = q.y; c[16 + o] = q.z; c[24 + o] = q.w;
-        }
+    for (int o = 0; o < 8; ++o) {
+        const float4 q = rec[o];
+        c[o] = q.x; c[8 + o] = q.y; c[16 + o] = q.z; c[24 + o] = q.w;
     }
 }
 
@@ -245,12 +242,10 @@ __device__ __forceinline__ void jet_from_stage(const AdjointArgs& A, const RayCt
 
 // Spatial derivatives of the interpolated gradient at the stage: the
 // t-derivatives of the trilinear interpolant (Eq. W_CIC) times 2^lvl / h0.
-template <bool AMR>
-__device__ __forceinline__ void jet_gradient(const GridDev& g, const FieldCache<AMR>& F, const StageData& d,
-                                             Jet32& J)
+__device__ __forceinline__ void jet_gradient(const GridDev& g, const StageData& d, Jet32& J)
 {
     float c[32];
-    stencil_coefs<AMR>(g, F, d.base, c);
+    stencil_coefs(g, d.base, c);
     const float tx = d.t[0], ty = d.t[1], tz = d.t[2];
     const float scale = (float)((double)(1 << d.lvl) * g.inv_h0);
 #pragma unroll
@@ -596,8 +591,8 @@ __device__ __forceinline__ bool forward_step(const CastArgs& a, FieldCache<AMR>&
 // Stage I (0-based) is handled with J holding its jet; the recursion moves
 // to stage I - 1.
 template <int I, bool AMR, int W, bool SCATTER>
-__device__ __forceinline__ void reverse_stage(const AdjointArgs& A, const RayCtx& R, const FieldCache<AMR>& F,
-                                              const StageRecord& rec, const HubbleCubic& Hc, float dlf, Jet32& J,
+__device__ __forceinline__ void reverse_stage(const AdjointArgs& A, const RayCtx& R, const StageRecord& rec,
+                                              const HubbleCubic& Hc, float dlf, Jet32& J,
                                               const Phys32 (&v)[W], Phys32 (&Fb)[W], float (&dlbar)[W],
                                               Phys32 (&dy)[W], const float (&lc)[W], Scatter<AMR>& S, WaveTable& T)
 {
@@ -630,8 +625,8 @@ __device__ __forceinline__ void reverse_stage(const AdjointArgs& A, const RayCtx
     if (SCATTER) rec.template put_gbar<I>(gL);
     if constexpr (I > 0) {
         J = P;
-        jet_gradient<AMR>(A.c.grid, F, rec.template get<I - 1>(), J);
-        reverse_stage<I - 1, AMR, W, SCATTER>(A, R, F, rec, Hc, dlf, J, v, Fb, dlbar, dy, lc, S, T);
+        jet_gradient(A.c.grid, rec.template get<I - 1>(), J);
+        reverse_stage<I - 1, AMR, W, SCATTER>(A, R, rec, Hc, dlf, J, v, Fb, dlbar, dy, lc, S, T);
     }
 }
 
@@ -641,8 +636,8 @@ __device__ __forceinline__ void reverse_stage(const AdjointArgs& A, const RayCtx
 // not propagated separately: its gradient cotangents are that combination of
 // the columns' ones.  Alone (W = 1) it is the only column, with lc_0 = 1.
 template <bool AMR, int W, bool SCATTER>
-__device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx& R, const FieldCache<AMR>& F,
-                                             const StageRecord& rec, const HubbleCubic& Hc, double dl,
+__device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx& R, const StageRecord& rec,
+                                             const HubbleCubic& Hc, double dl,
                                              double ds_reg, double k0_step, Phys (&yb)[W], const float (&lc)[W],
                                              Scatter<AMR>& S, WaveTable& T)
 {
@@ -652,7 +647,7 @@ __device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx&
     Jet32 J;
     const StageData d3 = rec.template get<3>();
     jet_from_stage(A, R, d3, Hc, J);
-    jet_gradient<AMR>(A.c.grid, F, d3, J);
+    jet_gradient(A.c.grid, d3, J);
     {
         const Phys32 F4 = rhs32(J);
 #pragma unroll
@@ -664,7 +659,7 @@ __device__ __forceinline__ void reverse_step(const AdjointArgs& A, const RayCtx&
             phys_zero(dy[c]);
         }
     }
-    reverse_stage<3, AMR, W, SCATTER>(A, R, F, rec, Hc, dlf, J, v, Fb, dlbar, dy, lc, S, T);
+    reverse_stage<3, AMR, W, SCATTER>(A, R, rec, Hc, dlf, J, v, Fb, dlbar, dy, lc, S, T);
     if (SCATTER) {
         // the stages' gradient cotangents to the cells, last stage first (one
         // copy of the accumulate-and-flush code)
@@ -978,7 +973,7 @@ __global__ __launch_bounds__(kBlock, 1) void adjoint_kernel(AdjointArgs A)
                 HubbleCubic Hc;
                 Hc.init(a.cosmo, ys.eta);
                 const double ds_reg = landing ? 0.0 : ds;
-                reverse_step<AMR, W, SCATTER>(A, R, F, rec, Hc, dl, ds_reg, -ys.K, yb, lc, S, T);
+                reverse_step<AMR, W, SCATTER>(A, R, rec, Hc, dl, ds_reg, -ys.K, yb, lc, S, T);
             }
         }
     }
