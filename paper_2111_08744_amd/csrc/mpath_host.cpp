@@ -32,6 +32,15 @@ int hip_fail(hipError_t e, const char* what)
     return fail(MPATH_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// A failed enqueue after others on the stream: wait for what was queued
+// before it (which may still read host buffers released on return), then
+// report the failure.
+int hip_fail_drain(hipError_t e, hipStream_t s, const char* what)
+{
+    (void)hipStreamSynchronize(s);
+    return hip_fail(e, what);
+}
+
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr double kH0 = 1.0 / 2997.92458;   // h/Mpc with c = 1
@@ -567,7 +576,7 @@ int mpath_grid_build_with_aux(const mpath_grid_desc* d, const mpath_cosmo* cosmo
         (e = hipMemcpyAsync(G->atable, atable.data(), (size_t)kTableN * 16, hipMemcpyHostToDevice, s)) ||
         (time_dep && (e = hipMemcpyAsync(G->tpay, tpay.data(), (size_t)n * 4, hipMemcpyHostToDevice, s)))) {
         delete G;
-        return hip_fail(e, "grid upload");
+        return hip_fail_drain(e, s, "grid upload");
     }
     // derived tables, chunk by chunk through the staging area (stream order
     // keeps each chunk's positions until its kernels have read them)
@@ -582,7 +591,7 @@ int mpath_grid_build_with_aux(const mpath_grid_desc* d, const mpath_cosmo* cosmo
     }
     if (e || (e = hipStreamSynchronize(s))) {
         delete G;
-        return hip_fail(e, "grid build");
+        return hip_fail_drain(e, s, "grid build");
     }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1340,8 +1349,11 @@ int mpath_autotune(const mpath_grid* g, const mpath_cast_desc* d, int32_t sample
     for (int w : {occ, std::max(1, occ / 2), 2 * occ})
         for (int b : {8, 16, 32, 64, 128}) cands.push_back({MPATH_SCHED_PERSISTENT, w, b});
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess) return fail(MPATH_ERR_DEVICE, "autotune: event creation failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return fail(MPATH_ERR_DEVICE, "autotune: event creation failed");
+    }
     mpath_observables none;
     std::memset(&none, 0, sizeof none);
     float best = 1e30f;
@@ -1664,7 +1676,7 @@ int mpath_find_geodesics(const mpath_grid* g, const mpath_finder_desc* f, mpath_
     if (!e) e = hipMemcpyAsync(theta, ws + P.off_target, n * 24, hipMemcpyDeviceToDevice, s);   // theta_0 = beta
     if (!e) e = hipStreamSynchronize(s);   // host tables are released on return
     if (!e) e = launch_fill_i32(n_iter, P.n, -1, s);
-    if (e) return hip_fail(e, "finder set-up");
+    if (e) return hip_fail_drain(e, s, "finder set-up");
     P.cd.dirs = theta;
     const RayEnd* ends = reinterpret_cast<const RayEnd*>(cws + P.lay.off_ends);
     const int K = f->checkpoint_every;
