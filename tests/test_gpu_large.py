@@ -12,6 +12,7 @@ host memory, the oracle's copy 95 s and about 40 GB more, the device image
 sampled tests take about 4 minutes in all.  They are skipped only on a host
 with less than 120 GiB of available memory.  The full-sky adjoint (48
 chunks, about a minute more) runs when MPATH_TEST_LARGE_FULL_SKY=1 is set."""
+import contextlib
 import os
 import time
 
@@ -45,10 +46,33 @@ pytestmark = [
 
 COSMO = (0.3, 0.7, 0.7)
 T0 = time.time()
+_CAPMAN = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _live_progress(request):
+    """The steps of this module take minutes without a test ending (the
+    tree, the oracle's copy of it): their progress lines go to the terminal
+    as they come instead of being held by pytest's capture until the test
+    ends, so that a run watching its output sees it alive."""
+    global _CAPMAN
+    _CAPMAN = request.config.pluginmanager.getplugin("capturemanager")
+    yield
+    _CAPMAN = None
+
+
+@contextlib.contextmanager
+def _live():
+    if _CAPMAN is None:
+        yield
+    else:
+        with _CAPMAN.global_and_fixture_disabled():
+            yield
 
 
 def _print(*a):
-    print(f"[{time.time() - T0:6.0f}s]", *a, flush=True)
+    with _live():
+        print(f"[{time.time() - T0:6.0f}s]", *a, flush=True)
 
 
 @pytest.fixture(scope="module")
@@ -82,7 +106,8 @@ def grid(M, large):
 def field(large):
     _, cells = large
     t = time.time()
-    f = O.Field.grid(cells)
+    with _live():                          # the oracle prints its own progress
+        f = O.Field.grid(cells)
     _print(f"oracle grid built in {time.time() - t:.1f} s")
     return f
 
