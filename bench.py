@@ -508,12 +508,27 @@ def measure_secondary_amr(M, torch, dev, steps):
     return res
 
 
+LARGE_NEED_GIB = 120
+
+
+def host_available_gib():
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) / 2 ** 20
+    except OSError:
+        pass
+    return float("inf")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large")
+    ap.add_argument("--workload", default=None,
+                    help="large (default: the 512^3 + 5 level light cone) or amr")
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
@@ -551,6 +566,17 @@ def main():
               "variants": lambda: measure_variants(M, torch, dev)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
+    fallback = None
+    if args.workload is None:
+        # the light cone's tree takes about 60 GB of host memory and the
+        # oracle's copy of it (CPU baseline) about 40 GB more
+        avail = host_available_gib()
+        args.workload = "large"
+        if avail < LARGE_NEED_GIB:
+            args.workload = "amr"
+            fallback = (f"{avail:.0f} GiB of host memory available, below the {LARGE_NEED_GIB} GiB the 512^3 + 5 "
+                        f"level light cone needs: the AMR 128^3 workload instead")
+            log(f"[bench] {fallback}")
     t0 = time.time()
     w, cells = workload(args.workload)
     t_gen = time.time() - t0
@@ -633,6 +659,7 @@ def main():
             "workload": WORKLOAD_TEXT.get(w.name, w.name),
             "cells": int(cells.n_cells), "rays": n_rays, "ray_steps_per_cast": ray_steps,
             "steps_per_cell": w.steps_per_cell, "adaptive": bool(w.adaptive),
+            **({"fallback": fallback} if fallback else {}),
         },
         "rays_per_s": n_rays * args.steps / wall,
         "adjoint_forward_ratio": None,
