@@ -133,8 +133,8 @@ int mpath_grid_aux_bytes(const mpath_grid_desc* desc, size_t* bytes);
  * refined cell has 1-7 children, a coarse cell is missing or a cell repeats),
  * order it (coarse cells in Morton order, then blocks of 8 siblings level by
  * level), pack (phi, grad) to float32 and upload into dev_ws on the stream.
- * Synchronises the stream before returning; the host arrays may be freed
- * afterwards.  *out receives a handle that refers to dev_ws: dev_ws must
+ * Synchronises the stream before returning, also when the upload or the
+ * build fails part way; the host arrays may be freed afterwards.  *out receives a handle that refers to dev_ws: dev_ws must
  * outlive the handle. */
 int mpath_grid_build(const mpath_grid_desc* desc, const mpath_cosmo* cosmo, void* dev_ws,
                      size_t ws_bytes, void* stream, mpath_grid** out);
